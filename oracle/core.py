@@ -1,0 +1,236 @@
+"""ctypes front end of the C oracle (``hbmc_oracle.c``).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the library imports this module; only
+the tests, the smoke check and the benchmark's CPU-baseline leg do.  It
+shares no code with the HIP path: the two meet only at the seeded inputs.
+
+Every function is a thin call into the C file, whose header states which
+passage of the paper each step follows and the readings taken where the paper
+is silent.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "hbmc_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+OK, EINVAL, ENOTSYM, EDIAG, EBREAKDOWN, ENOMEM, ENOCONV = 0, -1, -2, -3, -4, -6, 1
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc, one thread of plain C, no FMA contraction."""
+    if force or not os.path.exists(LIB):
+        tmp = LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared",
+                               "-o", tmp, SRC, "-lm"])
+        os.replace(tmp, LIB)
+    return LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build(force=True)
+        L = C.CDLL(LIB)
+        i32, i64, f64 = C.c_int32, C.c_int64, C.c_double
+        P = C.c_void_p
+        L.orc_check.argtypes = [i32, P, P, P]
+        L.orc_blocking.argtypes = [i32, P, P, i32, P, P]
+        L.orc_coloring.argtypes = [i32, P, P, i32, P, i32, P, P, P]
+        L.orc_hbmc_perm.argtypes = [i32, i32, i32, P, i32, P, i32, P, P, P]
+        L.orc_permute.argtypes = [i32, P, P, P, P, i64, P, P, P]
+        L.orc_ic0.argtypes = [i64, P, P, P, f64, P, P]
+        L.orc_apply.argtypes = [i64, P, P, P, P, P, P, P]
+        L.orc_apply.restype = None
+        L.orc_apply_f32.argtypes = [i64, P, P, P, P, P, P, P]
+        L.orc_apply_f32.restype = None
+        L.orc_spmv.argtypes = [i64, P, P, P, P, P]
+        L.orc_spmv.restype = None
+        L.orc_pcg.argtypes = [i64, P, P, P, P, P, i32, P, P, f64, i32, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _csr(A):
+    return (np.ascontiguousarray(A.rowptr, np.int64), np.ascontiguousarray(A.col, np.int32),
+            np.ascontiguousarray(A.val, np.float64))
+
+
+class OracleError(RuntimeError):
+    def __init__(self, what, status):
+        super().__init__(f"{what}: status {status}")
+        self.status = status
+
+
+def check(A) -> int:
+    rp, ci, v = _csr(A)
+    return lib().orc_check(A.n, _p(rp), _p(ci), _p(v))
+
+
+@dataclass
+class Ordering:
+    n: int
+    bs: int
+    w: int
+    members: np.ndarray      # [n] unknowns block by block, insertion order
+    nblocks: int
+    block_of: np.ndarray     # [n]
+    color: np.ndarray        # [nblocks]
+    ncolors: int
+    perm: np.ndarray         # [n] original -> HBMC index
+    color_start: np.ndarray  # [ncolors+1] in unknowns
+    n_pad: int
+
+
+def order(A, bs: int, w: int) -> Ordering:
+    """Blocking, greedy block coloring, padding and HBMC secondary reordering."""
+    L = lib()
+    rp, ci, _ = _csr(A)
+    n = A.n
+    members = np.empty(n, np.int32)
+    nb = C.c_int32(0)
+    st = L.orc_blocking(n, _p(rp), _p(ci), bs, _p(members), C.byref(nb))
+    if st:
+        raise OracleError("orc_blocking", st)
+    nblocks = nb.value
+    block_of = np.empty(n, np.int32)
+    color = np.empty(nblocks, np.int32)
+    nc = C.c_int32(0)
+    st = L.orc_coloring(n, _p(rp), _p(ci), bs, _p(members), nblocks, _p(block_of),
+                        _p(color), C.byref(nc))
+    if st:
+        raise OracleError("orc_coloring", st)
+    perm = np.empty(n, np.int32)
+    cstart = np.empty(nc.value + 1, np.int64)
+    npad = C.c_int64(0)
+    st = L.orc_hbmc_perm(n, bs, w, _p(members), nblocks, _p(color), nc.value, _p(perm),
+                         _p(cstart), C.byref(npad))
+    if st:
+        raise OracleError("orc_hbmc_perm", st)
+    return Ordering(n, bs, w, members, nblocks, block_of, color, nc.value, perm, cstart,
+                    int(npad.value))
+
+
+@dataclass
+class Permuted:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+
+def permute(A, perm: np.ndarray, n_pad: int) -> Permuted:
+    """Abar = P A P^T with identity rows for the dummy unknowns."""
+    rp, ci, v = _csr(A)
+    nnz2 = int(rp[-1]) + (n_pad - A.n)
+    rp2 = np.empty(n_pad + 1, np.int64)
+    ci2 = np.empty(nnz2, np.int32)
+    v2 = np.empty(nnz2, np.float64)
+    st = lib().orc_permute(A.n, _p(rp), _p(ci), _p(v), _p(np.ascontiguousarray(perm, np.int32)),
+                           n_pad, _p(rp2), _p(ci2), _p(v2))
+    if st:
+        raise OracleError("orc_permute", st)
+    return Permuted(n_pad, rp2, ci2, v2)
+
+
+def ic0(Ab, shift: float = 0.0):
+    """Returns (d, fac): the pivots and the factored copy of Ab's values."""
+    rp, ci, v = _csr(Ab)
+    d = np.empty(Ab.n, np.float64)
+    fac = np.empty_like(v)
+    st = lib().orc_ic0(Ab.n, _p(rp), _p(ci), _p(v), float(shift), _p(d), _p(fac))
+    if st:
+        raise OracleError("orc_ic0", st)
+    return d, fac
+
+
+def apply(Ab, d, fac, r, precision: str = "f64") -> np.ndarray:
+    """z = M^-1 r in the reordered numbering."""
+    rp, ci, _ = _csr(Ab)
+    r = np.ascontiguousarray(r, np.float64)
+    z = np.empty(Ab.n, np.float64)
+    if precision == "f64":
+        y = np.empty(Ab.n, np.float64)
+        lib().orc_apply(Ab.n, _p(rp), _p(ci), _p(fac), _p(d), _p(r), _p(y), _p(z))
+    else:
+        y = np.empty(Ab.n, np.float32)
+        lib().orc_apply_f32(Ab.n, _p(rp), _p(ci), _p(fac), _p(d), _p(r), _p(y), _p(z))
+    return z
+
+
+def spmv(Ab, x) -> np.ndarray:
+    rp, ci, v = _csr(Ab)
+    x = np.ascontiguousarray(x, np.float64)
+    y = np.empty(Ab.n, np.float64)
+    lib().orc_spmv(Ab.n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
+    return y
+
+
+@dataclass
+class PCGResult:
+    x: np.ndarray
+    iters: int
+    status: int
+    hist: np.ndarray
+
+
+def pcg(Ab, d, fac, b, x0=None, tol: float = 1e-7, maxit: int = 10000,
+        precision: str = "f64") -> PCGResult:
+    rp, ci, v = _csr(Ab)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.zeros(Ab.n) if x0 is None else np.array(x0, np.float64, copy=True)
+    hist = np.full(maxit + 1, np.nan)
+    it = C.c_int32(0)
+    st = lib().orc_pcg(Ab.n, _p(rp), _p(ci), _p(v), _p(fac), _p(d),
+                       1 if precision == "f32" else 0, _p(b), _p(x), float(tol), int(maxit),
+                       C.byref(it), _p(hist))
+    return PCGResult(x, it.value, st, hist[: it.value + 1])
+
+
+@dataclass
+class System:
+    """A problem carried through the oracle: ordering, reordered matrix,
+    factor.  ``solve`` maps b and x between the original and HBMC numbering."""
+    A: object
+    ordr: Ordering
+    Ab: Permuted
+    d: np.ndarray
+    fac: np.ndarray
+
+    def to_hbmc(self, v):
+        out = np.zeros(self.ordr.n_pad)
+        out[self.ordr.perm] = v
+        return out
+
+    def from_hbmc(self, vb):
+        return np.asarray(vb)[self.ordr.perm]
+
+    def solve(self, b, x0=None, tol=1e-7, maxit=10000, precision="f64") -> PCGResult:
+        xb0 = None if x0 is None else self.to_hbmc(x0)
+        res = pcg(self.Ab, self.d, self.fac, self.to_hbmc(b), xb0, tol, maxit, precision)
+        return PCGResult(self.from_hbmc(res.x), res.iters, res.status, res.hist)
+
+
+def system(A, bs: int, w: int, shift: float = 0.0) -> System:
+    st = check(A)
+    if st:
+        raise OracleError("orc_check", st)
+    o = order(A, bs, w)
+    Ab = permute(A, o.perm, o.n_pad)
+    d, fac = ic0(Ab, shift)
+    return System(A, o, Ab, d, fac)
