@@ -1,0 +1,179 @@
+#!/usr/bin/env python3
+"""Benchmark of the HBMC-ordered IC(0)-CG hot path on one MI355X.
+
+Workload: 3D 7-point cell-centred diffusion on 128^3 (n = 2,097,152) with
+lognormal (sigma = 1) face coefficients from seed 2, b ~ U[-1, 1] from seed
+3, HBMC with bs = 8, w = 64, FP64 throughout, x0 = 0, tol 1e-7.
+
+A step is one ICCG solve to ||r||/||b|| < 1e-7 (SpMV, dots, vector updates
+and one ic0_apply per iteration, plus the permutations in and out).  The
+headline value is the ic0_apply rate in algorithmic GB/s: bytes the
+substitutions must move (factor values and indices read once, diaginv, r
+in, z out, y out and back) divided by the apply's measured time, with the
+256 MB last-level cache flushed before each timed apply.
+
+Prints one JSON line on stdout; everything else goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "ic0_apply GB/s (% HBM peak); ICCG time-to-1e-7 residual vs plain FP64"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def apply_bytes(n: int, nnz_lower: int, s_v: int = 8, s_d: int = 8, s_y: int = 8) -> int:
+    """Algorithmic bytes of one ic0_apply: L and U values + int32 indices read
+    once, diaginv for the forward and backward sweeps, r read, z written, and
+    the intermediate y written and read back."""
+    return 2 * nnz_lower * (s_v + 4) + 2 * n * s_d + n * 8 + n * 8 + 2 * n * s_y
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--N", type=int, default=128)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: the hot path has no multi-GPU form in this "
+              "library (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import numpy as np
+    import torch
+
+    from paper_1908_00741_amd import hbmc, inputs
+
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    N, bs, w = args.N, 8, 64
+    log(f"[bench] building 128^3 workload N={N}")
+    A = inputs.diffusion3d(N, 1.0, 2)
+    b_np = inputs.uniform_rhs(A.n, 3)
+    t0 = time.perf_counter()
+    solver = hbmc.Solver.setup(A, bs, w, device=dev)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    f = solver.factor
+    nnz_lower = (A.nnz - A.n) // 2
+    B = apply_bytes(f.n_pad, nnz_lower)
+    log(f"[bench] setup {setup_s:.2f} s, n_pad {f.n_pad}, colors {f.n_colors}, "
+        f"apply bytes {B / 1e6:.1f} MB")
+
+    # ---- ic0_apply timing ------------------------------------------------
+    stream = torch.cuda.current_stream()
+    perm, _ = solver.order.perm()
+    r_np = np.zeros(f.n_pad)
+    r_np[perm] = np.random.default_rng(17).uniform(-1, 1, A.n)
+    r = torch.from_numpy(r_np).to(dev)
+    z = torch.empty_like(r)
+    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    for _ in range(5):
+        hbmc.ic0_apply(f, r, z)
+    torch.cuda.synchronize()
+
+    def timed(reps, cold):
+        ts = []
+        for i in range(reps):
+            if cold:
+                flush.fill_(i & 255)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            hbmc.ic0_apply(f, r, z)
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return np.array(ts)
+
+    t_cold = timed(args.apply_reps, True)
+    t_warm = timed(args.apply_reps, False)
+    log(f"[bench] apply cold: median {np.median(t_cold) * 1e3:.1f} us, "
+        f"warm: median {np.median(t_warm) * 1e3:.1f} us")
+    gbs_cold = B / (np.median(t_cold) * 1e-3) / 1e9
+    gbs_warm = B / (np.median(t_warm) * 1e-3) / 1e9
+
+    # ---- ICCG steps --------------------------------------------------------
+    b = torch.from_numpy(b_np).to(dev)
+    x = torch.zeros_like(b)
+    work = hbmc.workspace(f, 1, dev)
+    st = None
+    for _ in range(args.warmup):
+        x, st = solver.solve(b, x, tol=1e-7, x0_zero=True, work=work)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        x, st = solver.solve(b, x, tol=1e-7, x0_zero=True, work=work)
+        log(f"[bench] step {k}: {st.iters} iterations, true residual {st.true_rel_res:.2e}")
+    torch.cuda.synchronize()
+    ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
+    log(f"[bench] ICCG {ms_per_step:.2f} ms per solve, {st.iters} iterations")
+
+    # ---- oracle on the host ------------------------------------------------
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("[bench] timing the oracle on the host")
+        ref = oracle.system(A, bs, w)
+        reps, tcpu = 0, 0.0
+        while tcpu < args.cpu_seconds or reps < 3:
+            t1 = time.perf_counter()
+            oracle.apply(ref.Ab, ref.d, ref.fac, r_np)
+            tcpu += time.perf_counter() - t1
+            reps += 1
+        bb = np.zeros(f.n_pad)
+        bb[perm] = b_np
+        t1 = time.perf_counter()
+        kit = 10
+        oracle.pcg(ref.Ab, ref.d, ref.fac, bb, tol=0.0, maxit=kit)
+        ms_it = (time.perf_counter() - t1) * 1e3 / kit
+        cpu = {"value": round(B * reps / tcpu / 1e9, 4), "unit": "GB/s", "cores": 1,
+               "kind": "oracle",
+               "sample": f"{reps} sequential FP64 ic0_apply calls on the same 128^3 workload "
+                         f"({tcpu:.1f} s); oracle PCG {ms_it:.0f} ms/iteration over {kit} iterations",
+               "host_cpu_count": os.cpu_count()}
+
+    out = {
+        "metric": METRIC, "value": round(gbs_cold, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"diffusion3d {N}^3 lognormal sigma=1 seed 2, b~U[-1,1] seed 3, "
+                               f"HBMC bs={bs} w={w}, FP64, x0=0, tol 1e-7",
+                   "n": A.n, "n_pad": f.n_pad, "nnz": A.nnz, "nnz_lower": nnz_lower,
+                   "n_colors": f.n_colors, "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": round(gbs_cold, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(gbs_cold / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "ic0_apply (2*n_colors-1 phase launches)",
+                     "bytes_per_launch": B},
+        "apply": {"median_us_cold": round(float(np.median(t_cold)) * 1e3, 2),
+                  "median_us_warm": round(float(np.median(t_warm)) * 1e3, 2),
+                  "gbs_warm": round(gbs_warm, 2), "reps": args.apply_reps},
+        "iccg": {"ms_to_1e-7": round(ms_per_step, 3), "iterations": st.iters,
+                 "true_rel_res": st.true_rel_res, "ms_per_iteration": round(ms_per_step / max(st.iters, 1), 4),
+                 "setup_s": round(setup_s, 2)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,211 @@
+/*
+ * hbmc.h -- C ABI of the HBMC-ordered IC(0)-CG library for MI355X (gfx950).
+ *
+ * Method: Iwashita, Li, Fukaya, "Hierarchical block multi-color ordering: a
+ * new parallel ordering method for vectorization and parallelization of the
+ * sparse triangular solver in the ICCG method" (arXiv 1908.00741).
+ *
+ * Conventions for every entry point
+ *  - Status: each call returns an int status (HBMC_OK = 0; negative = error,
+ *    positive = a warning whose outputs are still valid).  The message of the
+ *    last error on the calling thread is returned by hbmc_last_error().
+ *    No C++ exception crosses this interface.
+ *  - Matrices: square CSR, 0-based; rowptr is int64[n+1], col is int32[nnz]
+ *    sorted strictly ascending inside each row; both triangles are stored and
+ *    the pattern must be symmetric (values too, for ic0_factor and
+ *    hbmc_matrix_create); every diagonal entry must be present and > 0.
+ *  - Host pointers are read during the call only; the caller keeps ownership.
+ *  - Device pointers: device memory on the current HIP device.  The library
+ *    never allocates device memory: objects that live on the device report the
+ *    bytes they need (..._device_bytes), the caller allocates them and hands
+ *    them over with ..._upload, and keeps them alive (and unmodified) for the
+ *    lifetime of the object.
+ *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *    stream).  Calls that take a stream only enqueue work on it, except
+ *    iccg_solve, which synchronizes the stream to read residuals.
+ *  - Vector orders: ic0_apply and hbmc_spmv work on vectors in HBMC order
+ *    (length n_pad, dummies included); iccg_solve takes b and x in the
+ *    caller's original numbering (length n).
+ *  - Multiple right-hand sides are stored row-major [length][nrhs]: the
+ *    nrhs values of one unknown are adjacent.
+ *  - Objects are not internally locked: use one object per thread, or
+ *    serialize calls that use the same object.
+ */
+#ifndef HBMC_H
+#define HBMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------- */
+#define HBMC_OK 0
+#define HBMC_EINVAL (-1)      /* bad argument, malformed CSR, unsupported size */
+#define HBMC_ENOTSYM (-2)     /* pattern or values not exactly symmetric       */
+#define HBMC_EDIAG (-3)       /* a diagonal entry is missing or not > 0        */
+#define HBMC_EBREAKDOWN (-4)  /* IC(0) pivot <= 0, or CG (p, Ap) <= 0 / NaN    */
+#define HBMC_EHIP (-5)        /* a HIP runtime call failed                     */
+#define HBMC_ENOMEM (-6)      /* host allocation failed                        */
+#define HBMC_ENOTREADY (-7)   /* device data not uploaded yet                  */
+#define HBMC_ENOCONV 1        /* maxit reached; outputs hold the last iterate  */
+
+/* precision of the stored factor and of the substitutions */
+#define HBMC_F64 0
+#define HBMC_F32 1
+
+typedef struct hbmc_order_s hbmc_order_t;
+typedef struct hbmc_factor_s hbmc_factor_t;
+typedef struct hbmc_matrix_s hbmc_matrix_t;
+
+/* Message of the last error raised on the calling thread ("" if none). */
+const char *hbmc_last_error(void);
+
+/* ---- ordering ------------------------------------------------------------
+ * hbmc_order: block multi-color ordering followed by the HBMC secondary
+ * reordering (Sections 4.1-4.3; blocking and coloring heuristics of
+ * Section 5.1).
+ *  - Blocking (BMC, Section 4.1): blocks of bs unknowns.  A block starts at
+ *    the smallest unassigned unknown and grows by the smallest unassigned
+ *    unknown adjacent to one of its members, else by the smallest unassigned
+ *    unknown overall; members keep their insertion order.
+ *  - Coloring: greedy, blocks in id order, smallest color unused by the
+ *    already-colored adjacent blocks; colors 0..n_colors-1.
+ *  - Padding (Section 4.3): each color is completed with dummy unknowns to a
+ *    multiple of bs*w unknowns; dummy rows are identity rows.
+ *  - Secondary reordering (Section 4.2, eq. "simd-block"): a level-1 block is
+ *    w consecutive BMC blocks of one color; inside it the j-th unknowns of
+ *    the w blocks are numbered together, j = 0..bs-1.
+ * Arguments: n >= 1 unknowns; CSR pattern (values not needed); 1 <= bs <= 32;
+ * w a divisor of 64.  Errors: HBMC_EINVAL, HBMC_ENOTSYM (pattern), HBMC_EDIAG
+ * (missing diagonal), HBMC_ENOMEM.  *out receives a new handle owned by the
+ * caller (free with hbmc_order_destroy).  Deterministic.
+ */
+int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
+               int32_t w, hbmc_order_t **out);
+
+typedef struct {
+    int64_t n;          /* unknowns of the original system                */
+    int64_t n_pad;      /* unknowns after padding (HBMC vector length)     */
+    int64_t n_blocks;   /* BMC blocks, dummy blocks excluded              */
+    int32_t n_colors;
+    int32_t bs;
+    int32_t w;
+    int32_t reserved;
+} hbmc_order_info_t;
+
+int hbmc_order_info(const hbmc_order_t *h, hbmc_order_info_t *info);
+
+/* perm[n]: original index -> HBMC index (Section 3, the reordering pi);
+ * color_start[n_colors+1]: first HBMC index of each color, last = n_pad.
+ * Either pointer may be NULL. */
+int hbmc_order_perm(const hbmc_order_t *h, int32_t *perm, int64_t *color_start);
+
+void hbmc_order_destroy(hbmc_order_t *h);
+
+/* ---- IC(0) factor -----------------------------------------------------------
+ * ic0_factor: incomplete Cholesky factorization with zero fill (Section 2,
+ * eq. "ILU"; Appendix A) of Abar = P A P^T in HBMC order, with identity rows
+ * for the dummy unknowns: M = (D + L) D^-1 (D + L^T), where L has the pattern
+ * of the strictly lower part of Abar and d the diagonal.  The forward
+ * substitution uses L with diaginv = 1/d (Fig. 6); the backward substitution
+ * uses the unit upper factor U = I + D^-1 L^T.  shift (>= 0) multiplies the
+ * diagonal by (1 + shift) first (shifted IC, Section 5.1).
+ * precision: HBMC_F64, or HBMC_F32 (the factor is computed in FP64 and
+ * rounded to FP32; the substitutions then run in FP32).
+ * Errors: HBMC_EINVAL, HBMC_ENOTSYM, HBMC_EDIAG, HBMC_EBREAKDOWN (pivot not
+ * > 0), HBMC_ENOMEM.  The order handle must outlive nothing: the factor
+ * copies what it needs.
+ */
+int ic0_factor(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
+               const double *val, int32_t precision, double shift, hbmc_factor_t **out);
+
+/* Host copy of the factor, for checking: d[n_pad] and the strictly lower
+ * part of L in CSR over HBMC indices (lower_rowptr[n_pad+1], lower_col and
+ * lower_val sized by *lower_nnz).  Call with lower_col == NULL to get
+ * *lower_nnz only.  Values are FP64 (the FP64 factor before any rounding). */
+int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lower_rowptr,
+                       int32_t *lower_col, double *lower_val, int64_t *lower_nnz);
+
+int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes);
+
+/* Copies the factor's device image into dev[0, bytes) on stream (async).
+ * dev must be 256-byte aligned and at least hbmc_factor_device_bytes long. */
+int hbmc_factor_upload(hbmc_factor_t *f, void *dev, size_t bytes, void *stream);
+
+void hbmc_factor_destroy(hbmc_factor_t *f);
+
+/* ---- preconditioning step --------------------------------------------------
+ * ic0_apply: z = M^-1 r, i.e. the forward substitution y = L^-1 r and the
+ * backward substitution z = U^-1 y (Section 2, eqs. "for" and "back"), run
+ * color by color (Section 4.2.2, eqs. "for2", "for3", "BAMC3"): within a
+ * color the level-1 blocks are independent, and inside a level-1 block the
+ * bs steps of eqs. "y2-2", "y2-3" each solve w independent rows.  The
+ * backward substitution runs the colors in reverse.
+ * r, z: device FP64, HBMC order, [n_pad][nrhs]; z must not alias r.  nrhs
+ * >= 1 right-hand sides share one read of the factor.  Dummy entries of r
+ * must be 0 (then those of z are 0).  Asynchronous on stream.
+ * Errors: HBMC_EINVAL, HBMC_ENOTREADY (factor not uploaded), HBMC_EHIP.
+ */
+int ic0_apply(const hbmc_factor_t *f, const double *r, double *z, int32_t nrhs,
+              void *stream);
+
+/* ---- coefficient matrix ----------------------------------------------------
+ * The reordered matrix Abar = P A P^T (Section 3, eq. "AB") in a sliced ELL
+ * layout (Section 4.4.2) for the SpMV of CG. */
+int hbmc_matrix_create(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
+                       const double *val, hbmc_matrix_t **out);
+int hbmc_matrix_device_bytes(const hbmc_matrix_t *m, size_t *bytes);
+int hbmc_matrix_upload(hbmc_matrix_t *m, void *dev, size_t bytes, void *stream);
+void hbmc_matrix_destroy(hbmc_matrix_t *m);
+
+/* y = Abar x, device FP64 vectors in HBMC order [n_pad][nrhs]; y must not
+ * alias x.  Asynchronous on stream. */
+int hbmc_spmv(const hbmc_matrix_t *m, const double *x, double *y, int32_t nrhs, void *stream);
+
+/* Between numberings, device FP64 [length][nrhs]: v_hbmc[perm[i]] = v[i] and
+ * dummies = 0 (gather), or v[i] = v_hbmc[perm[i]] (scatter). */
+int hbmc_to_hbmc(const hbmc_factor_t *f, const double *v, double *v_hbmc, int32_t nrhs,
+                 void *stream);
+int hbmc_from_hbmc(const hbmc_factor_t *f, const double *v_hbmc, double *v, int32_t nrhs,
+                   void *stream);
+
+/* ---- solver ------------------------------------------------------------------
+ * iccg_solve: IC(0)-preconditioned CG (Section 2) on Abar xbar = bbar in HBMC
+ * order, stopping when ||r||_2 / ||b||_2 < tol for the recurrence residual
+ * (Section 5.1), checked after each update of r; at most maxit products
+ * A p.  b (input) and x (input x0 unless opts->x0_zero, output solution) are
+ * device FP64 in the caller's numbering, [n][nrhs].  work: device scratch of
+ * iccg_workspace_bytes(f, nrhs).  Synchronous: returns when x is written.
+ * b = 0 gives x = 0 after 0 iterations.
+ * Returns HBMC_OK, HBMC_ENOCONV (maxit reached for some right-hand side),
+ * HBMC_EBREAKDOWN, or an error; per-RHS details go to stats[nrhs] if not
+ * NULL.
+ */
+typedef struct {
+    int32_t x0_zero;       /* 1: ignore x on input, start from 0              */
+    int32_t check_every;   /* iterations between residual readbacks (>= 1)    */
+    int32_t use_graph;     /* 1: replay the iterations as a captured hipGraph */
+    int32_t record_history;/* 1: keep ||r||/||b|| per iteration (device)      */
+} hbmc_solve_opts_t;
+
+typedef struct {
+    int32_t iters;          /* products A p made before stopping              */
+    int32_t status;         /* HBMC_OK, HBMC_ENOCONV or HBMC_EBREAKDOWN       */
+    double rel_res;         /* recurrence ||r|| / ||b|| at stop               */
+    double true_rel_res;    /* ||b - A x|| / ||b|| at stop                    */
+} hbmc_solve_stats_t;
+
+int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);
+
+int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
+               int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
+               hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HBMC_H */

@@ -1,0 +1,243 @@
+// Host side of the ordering: block multi-color ordering (BMC) and the HBMC
+// secondary reordering (Sections 4.1-4.3; blocking and coloring heuristics
+// of Section 5.1).
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "hbmc_internal.h"
+
+namespace hbmc {
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+size_t ImageBuilder::add(const void *src, size_t n) {
+    size_t at = (bytes.size() + 255) & ~size_t(255);
+    bytes.resize(at + n);
+    if (n) std::memcpy(bytes.data() + at, src, n);
+    return at;
+}
+
+int check_csr(int32_t n, const int64_t *rp, const int32_t *ci, const double *v) {
+    if (n < 1) return fail(HBMC_EINVAL, "n must be >= 1 (got %d)", n);
+    if (!rp || !ci) return fail(HBMC_EINVAL, "null CSR pointer");
+    if (rp[0] != 0) return fail(HBMC_EINVAL, "rowptr[0] must be 0");
+    for (int32_t i = 0; i < n; ++i) {
+        if (rp[i + 1] < rp[i]) return fail(HBMC_EINVAL, "rowptr decreases at row %d", i);
+        bool diag = false;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            if (ci[p] < 0 || ci[p] >= n) return fail(HBMC_EINVAL, "column out of range in row %d", i);
+            if (p > rp[i] && ci[p] <= ci[p - 1])
+                return fail(HBMC_EINVAL, "columns of row %d not strictly ascending", i);
+            if (ci[p] == i) {
+                diag = true;
+                if (v && !(v[p] > 0.0)) return fail(HBMC_EDIAG, "diagonal of row %d is not > 0", i);
+            }
+        }
+        if (!diag) return fail(HBMC_EDIAG, "row %d has no diagonal entry", i);
+    }
+    // symmetry: walk each row's upper part against the matching column of
+    // the lower parts, using a per-row cursor (rows are sorted)
+    std::vector<int64_t> cursor(rp, rp + n);
+    for (int32_t i = 0; i < n; ++i) {
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+            int32_t j = ci[p];
+            if (j <= i) continue;
+            // entry (j, i) must be the next unvisited lower entry of row j
+            int64_t &c = cursor[j];
+            while (c < rp[j + 1] && ci[c] < i) {
+                // a lower entry (j, ci[c]) with ci[c] < i whose mirror (ci[c], j)
+                // would have been met in row ci[c] < i: missing mirror
+                return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", j, ci[c]);
+            }
+            if (c >= rp[j + 1] || ci[c] != i)
+                return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", i, j);
+            if (v && v[c] != v[p])
+                return fail(HBMC_ENOTSYM, "values not symmetric at (%d,%d)", i, j);
+            ++c;
+        }
+    }
+    // every lower entry must have been matched by an upper one
+    for (int32_t j = 0; j < n; ++j) {
+        int64_t c = cursor[j];
+        if (c < rp[j + 1] && ci[c] < j)
+            return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", j, ci[c]);
+    }
+    return HBMC_OK;
+}
+
+}  // namespace hbmc
+
+using namespace hbmc;
+
+namespace {
+
+// Blocking: blocks of bs unknowns grown from the minimal-numbered
+// unassigned unknown through its smallest unassigned neighbours.  The
+// frontier is kept as an unsorted candidate list; each pick scans it for the
+// smallest unassigned entry and drops entries that became assigned.
+void build_blocks(int32_t n, const int64_t *rp, const int32_t *ci, int32_t bs,
+                  std::vector<int32_t> &members) {
+    members.clear();
+    members.reserve(n);
+    std::vector<uint8_t> taken(n, 0);
+    std::vector<int32_t> cand;
+    int32_t scan = 0;   // every unknown below scan is assigned
+    while (true) {
+        while (scan < n && taken[scan]) ++scan;
+        if (scan >= n) break;
+        cand.clear();
+        int32_t u = scan;
+        for (int32_t size = 1;; ++size) {
+            taken[u] = 1;
+            members.push_back(u);
+            if (size == bs) break;
+            for (int64_t p = rp[u]; p < rp[u + 1]; ++p)
+                if (!taken[ci[p]]) cand.push_back(ci[p]);
+            int32_t best = -1;
+            size_t keep = 0;
+            for (size_t t = 0; t < cand.size(); ++t) {
+                int32_t v = cand[t];
+                if (taken[v]) continue;
+                cand[keep++] = v;
+                if (best < 0 || v < best) best = v;
+            }
+            cand.resize(keep);
+            if (best < 0) {
+                while (scan < n && taken[scan]) ++scan;
+                if (scan >= n) break;
+                best = scan;
+            }
+            u = best;
+        }
+    }
+}
+
+// Greedy coloring of the block graph: blocks in id order, smallest color
+// not present among already-colored adjacent blocks.  The colors of the
+// neighbours are collected in a bitmap that grows with the color count.
+int32_t color_blocks(int32_t n, const int64_t *rp, const int32_t *ci, int32_t bs,
+                     const std::vector<int32_t> &members, std::vector<int32_t> &color) {
+    const int64_t nb = (int64_t(n) + bs - 1) / bs;
+    std::vector<int32_t> block(n);
+    for (int64_t t = 0; t < n; ++t) block[members[t]] = int32_t(t / bs);
+    color.assign(nb, -1);
+    std::vector<uint64_t> used;
+    int32_t ncolors = 0;
+    for (int64_t b = 0; b < nb; ++b) {
+        std::fill(used.begin(), used.end(), 0);
+        const int64_t t1 = std::min<int64_t>((b + 1) * bs, n);
+        for (int64_t t = b * bs; t < t1; ++t) {
+            const int32_t u = members[t];
+            for (int64_t p = rp[u]; p < rp[u + 1]; ++p) {
+                const int32_t c = color[block[ci[p]]];
+                if (c < 0) continue;   // not colored yet (or this block)
+                if (size_t(c / 64) >= used.size()) used.resize(c / 64 + 1, 0);
+                used[c / 64] |= uint64_t(1) << (c % 64);
+            }
+        }
+        int32_t c = 0;
+        for (size_t wd = 0;; ++wd) {
+            const uint64_t bits = wd < used.size() ? used[wd] : 0;
+            if (bits != ~uint64_t(0)) {
+                c = int32_t(wd * 64) + __builtin_ctzll(~bits);
+                break;
+            }
+        }
+        color[b] = c;
+        ncolors = std::max(ncolors, c + 1);
+    }
+    return ncolors;
+}
+
+}  // namespace
+
+extern "C" int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
+                          int32_t w, hbmc_order_t **out) {
+    clear_error();
+    if (!out) return fail(HBMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (bs < 1 || bs > 32) return fail(HBMC_EINVAL, "bs must be in [1, 32] (got %d)", bs);
+    if (w < 1 || w > kTileLanes || kTileLanes % w != 0)
+        return fail(HBMC_EINVAL, "w must divide %d (got %d)", kTileLanes, w);
+    int st = check_csr(n, rowptr, col, nullptr);
+    if (st) return st;
+    try {
+        auto *h = new hbmc_order_s;
+        h->n = n; h->bs = bs; h->w = w;
+        std::vector<int32_t> members, color;
+        build_blocks(n, rowptr, col, bs, members);
+        h->nc = color_blocks(n, rowptr, col, bs, members, color);
+        h->nblocks = int64_t(color.size());
+        // blocks of each color in ascending id
+        std::vector<std::vector<int32_t>> of_color(h->nc);
+        for (int64_t b = 0; b < h->nblocks; ++b) of_color[color[b]].push_back(int32_t(b));
+        // padding: every color to a multiple of w blocks, i.e. of bs*w unknowns
+        h->color_start.assign(h->nc + 1, 0);
+        for (int32_t c = 0; c < h->nc; ++c) {
+            const int64_t padded = (int64_t(of_color[c].size()) + w - 1) / w * w;
+            h->color_start[c + 1] = h->color_start[c] + padded * bs;
+        }
+        h->n_pad = h->color_start[h->nc];
+        if (h->n_pad > INT32_MAX) { delete h; return fail(HBMC_EINVAL, "n_pad exceeds int32"); }
+        h->perm.assign(n, -1);
+        h->iperm.assign(h->n_pad, -1);
+        // the q-th block of color c is BMC block m = q mod w of level-1 block
+        // k' = q / w; its j-th member goes to S_c + k' bs w + j w + m
+        for (int32_t c = 0; c < h->nc; ++c) {
+            const auto &list = of_color[c];
+            for (size_t q = 0; q < list.size(); ++q) {
+                const int64_t kp = int64_t(q) / w, m = int64_t(q) % w;
+                const int64_t first = int64_t(list[q]) * bs;
+                for (int32_t j = 0; j < bs && first + j < n; ++j) {
+                    const int64_t dst = h->color_start[c] + kp * bs * w + int64_t(j) * w + m;
+                    const int32_t u = members[first + j];
+                    h->perm[u] = int32_t(dst);
+                    h->iperm[dst] = u;
+                }
+            }
+        }
+        *out = h;
+        return HBMC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HBMC_ENOMEM, "out of host memory in hbmc_order");
+    }
+}
+
+extern "C" int hbmc_order_info(const hbmc_order_t *h, hbmc_order_info_t *info) {
+    if (!h || !info) return fail(HBMC_EINVAL, "null argument");
+    info->n = h->n;
+    info->n_pad = h->n_pad;
+    info->n_blocks = h->nblocks;
+    info->n_colors = h->nc;
+    info->bs = h->bs;
+    info->w = h->w;
+    info->reserved = 0;
+    return HBMC_OK;
+}
+
+extern "C" int hbmc_order_perm(const hbmc_order_t *h, int32_t *perm, int64_t *color_start) {
+    if (!h) return fail(HBMC_EINVAL, "null handle");
+    if (perm) std::memcpy(perm, h->perm.data(), h->perm.size() * sizeof(int32_t));
+    if (color_start)
+        std::memcpy(color_start, h->color_start.data(), h->color_start.size() * sizeof(int64_t));
+    return HBMC_OK;
+}
+
+extern "C" void hbmc_order_destroy(hbmc_order_t *h) { delete h; }
+
+extern "C" const char *hbmc_last_error(void) { return hbmc::g_last_error.c_str(); }

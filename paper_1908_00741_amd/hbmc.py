@@ -1,0 +1,343 @@
+"""Python binding of ``libhbmc.so`` (the C ABI declared in include/hbmc.h).
+
+Argument marshalling only: every step of the method runs in the library.
+PyTorch provides device memory (tensors whose pointers are handed to the
+library) and the current HIP stream.  The binding fails loudly when the
+library is missing; there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libhbmc.so")
+
+HBMC_OK, HBMC_EINVAL, HBMC_ENOTSYM, HBMC_EDIAG, HBMC_EBREAKDOWN = 0, -1, -2, -3, -4
+HBMC_EHIP, HBMC_ENOMEM, HBMC_ENOTREADY, HBMC_ENOCONV = -5, -6, -7, 1
+HBMC_F64, HBMC_F32 = 0, 1
+
+# every symbol include/hbmc.h declares
+SYMBOLS = (
+    "hbmc_last_error", "hbmc_order", "hbmc_order_info", "hbmc_order_perm",
+    "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
+    "hbmc_factor_upload", "hbmc_factor_destroy", "ic0_apply", "hbmc_matrix_create",
+    "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
+    "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve",
+)
+
+
+class HbmcError(RuntimeError):
+    def __init__(self, call: str, code: int, msg: str):
+        super().__init__(f"{call} -> {code}: {msg}")
+        self.code = code
+
+
+class OrderInfo(C.Structure):
+    _fields_ = [("n", C.c_int64), ("n_pad", C.c_int64), ("n_blocks", C.c_int64),
+                ("n_colors", C.c_int32), ("bs", C.c_int32), ("w", C.c_int32),
+                ("reserved", C.c_int32)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("x0_zero", C.c_int32), ("check_every", C.c_int32),
+                ("use_graph", C.c_int32), ("record_history", C.c_int32)]
+
+
+class SolveStats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
+                ("true_rel_res", C.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libhbmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1908_00741_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        P, i32, i64, f64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
+        L.hbmc_last_error.restype = C.c_char_p
+        L.hbmc_order.argtypes = [i32, P, P, i32, i32, P]
+        L.hbmc_order_info.argtypes = [P, P]
+        L.hbmc_order_perm.argtypes = [P, P, P]
+        L.hbmc_order_destroy.argtypes = [P]
+        L.hbmc_order_destroy.restype = None
+        L.ic0_factor.argtypes = [P, P, P, P, i32, f64, P]
+        L.hbmc_factor_export.argtypes = [P, P, P, P, P, P]
+        L.hbmc_factor_device_bytes.argtypes = [P, P]
+        L.hbmc_factor_upload.argtypes = [P, P, sz, P]
+        L.hbmc_factor_destroy.argtypes = [P]
+        L.hbmc_factor_destroy.restype = None
+        L.ic0_apply.argtypes = [P, P, P, i32, P]
+        L.hbmc_matrix_create.argtypes = [P, P, P, P, P]
+        L.hbmc_matrix_device_bytes.argtypes = [P, P]
+        L.hbmc_matrix_upload.argtypes = [P, P, sz, P]
+        L.hbmc_matrix_destroy.argtypes = [P]
+        L.hbmc_matrix_destroy.restype = None
+        L.hbmc_spmv.argtypes = [P, P, P, i32, P]
+        L.hbmc_to_hbmc.argtypes = [P, P, P, i32, P]
+        L.hbmc_from_hbmc.argtypes = [P, P, P, i32, P]
+        L.iccg_workspace_bytes.argtypes = [P, i32, P]
+        L.iccg_solve.argtypes = [P, P, P, P, i32, f64, i32, P, P, P, sz, P]
+        _lib = L
+    return _lib
+
+
+def _check(call: str, code: int, ok=(HBMC_OK,)):
+    if code not in ok:
+        raise HbmcError(call, code, lib().hbmc_last_error().decode())
+    return code
+
+
+def _ptr(a: np.ndarray):
+    assert a.flags.c_contiguous
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def _csr_arrays(A):
+    return (np.ascontiguousarray(A.rowptr, np.int64), np.ascontiguousarray(A.col, np.int32),
+            np.ascontiguousarray(A.val, np.float64))
+
+
+def _stream(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Order:
+    """Handle of hbmc_order: BMC blocking + coloring + HBMC reordering."""
+
+    def __init__(self, handle, A):
+        self._h = handle
+        info = OrderInfo()
+        _check("hbmc_order_info", lib().hbmc_order_info(self._h, C.byref(info)))
+        self.n, self.n_pad, self.n_blocks = info.n, info.n_pad, info.n_blocks
+        self.n_colors, self.bs, self.w = info.n_colors, info.bs, info.w
+
+    @property
+    def handle(self):
+        return self._h
+
+    def perm(self):
+        perm = np.empty(self.n, np.int32)
+        cs = np.empty(self.n_colors + 1, np.int64)
+        _check("hbmc_order_perm", lib().hbmc_order_perm(self._h, _ptr(perm), _ptr(cs)))
+        return perm, cs
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbmc_order_destroy(self._h)
+            self._h = None
+
+
+def hbmc_order(A, bs: int, w: int) -> Order:
+    rp, ci, _ = _csr_arrays(A)
+    h = C.c_void_p()
+    _check("hbmc_order", lib().hbmc_order(A.n, _ptr(rp), _ptr(ci), bs, w, C.byref(h)))
+    return Order(h, A)
+
+
+class Factor:
+    """Handle of ic0_factor; ``upload()`` places it in device memory."""
+
+    def __init__(self, handle, order: Order, precision: int):
+        self._h = handle
+        self.n, self.n_pad, self.bs, self.w = order.n, order.n_pad, order.bs, order.w
+        self.n_colors = order.n_colors
+        self.precision = precision
+        self.dev = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def export(self):
+        """(d, lower_rowptr, lower_col, lower_val) of the FP64 factor."""
+        nnz = C.c_int64(0)
+        _check("hbmc_factor_export", lib().hbmc_factor_export(self._h, None, None, None, None,
+                                                              C.byref(nnz)))
+        d = np.empty(self.n_pad)
+        rp = np.empty(self.n_pad + 1, np.int64)
+        ci = np.empty(nnz.value, np.int32)
+        v = np.empty(nnz.value)
+        _check("hbmc_factor_export", lib().hbmc_factor_export(self._h, _ptr(d), _ptr(rp), _ptr(ci),
+                                                              _ptr(v), C.byref(nnz)))
+        return d, rp, ci, v
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t(0)
+        _check("hbmc_factor_device_bytes", lib().hbmc_factor_device_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        nbytes = self.device_bytes()
+        self.dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _check("hbmc_factor_upload", lib().hbmc_factor_upload(self._h, _dptr(self.dev), nbytes,
+                                                              _stream(stream)))
+        return self
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbmc_factor_destroy(self._h)
+            self._h = None
+
+
+def ic0_factor(order: Order, A, precision: int = HBMC_F64, shift: float = 0.0) -> Factor:
+    rp, ci, v = _csr_arrays(A)
+    h = C.c_void_p()
+    _check("ic0_factor", lib().ic0_factor(order.handle, _ptr(rp), _ptr(ci), _ptr(v), precision,
+                                          float(shift), C.byref(h)))
+    return Factor(h, order, precision)
+
+
+class Matrix:
+    """Handle of hbmc_matrix_create: Abar in sliced ELL."""
+
+    def __init__(self, handle, order: Order):
+        self._h = handle
+        self.n, self.n_pad = order.n, order.n_pad
+        self.dev = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def device_bytes(self) -> int:
+        b = C.c_size_t(0)
+        _check("hbmc_matrix_device_bytes", lib().hbmc_matrix_device_bytes(self._h, C.byref(b)))
+        return b.value
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        nbytes = self.device_bytes()
+        self.dev = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _check("hbmc_matrix_upload", lib().hbmc_matrix_upload(self._h, _dptr(self.dev), nbytes,
+                                                              _stream(stream)))
+        return self
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbmc_matrix_destroy(self._h)
+            self._h = None
+
+
+def hbmc_matrix_create(order: Order, A) -> Matrix:
+    rp, ci, v = _csr_arrays(A)
+    h = C.c_void_p()
+    _check("hbmc_matrix_create", lib().hbmc_matrix_create(order.handle, _ptr(rp), _ptr(ci), _ptr(v),
+                                                          C.byref(h)))
+    return Matrix(h, order)
+
+
+def _vec_check(t, n, nrhs, name):
+    import torch
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous float64 device tensor")
+    if t.numel() != n * nrhs:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {n * nrhs}")
+
+
+def ic0_apply(f: Factor, r, z=None, nrhs: int = 1, stream=None):
+    """z = M^-1 r on device vectors in HBMC order ([n_pad][nrhs])."""
+    import torch
+    _vec_check(r, f.n_pad, nrhs, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _vec_check(z, f.n_pad, nrhs, "z")
+    _check("ic0_apply", lib().ic0_apply(f.handle, _dptr(r), _dptr(z), nrhs, _stream(stream)))
+    return z
+
+
+def hbmc_spmv(m: Matrix, x, y=None, nrhs: int = 1, stream=None):
+    import torch
+    _vec_check(x, m.n_pad, nrhs, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    _check("hbmc_spmv", lib().hbmc_spmv(m.handle, _dptr(x), _dptr(y), nrhs, _stream(stream)))
+    return y
+
+
+def hbmc_to_hbmc(f: Factor, v, nrhs: int = 1, stream=None):
+    import torch
+    _vec_check(v, f.n, nrhs, "v")
+    vb = torch.empty(f.n_pad * nrhs, dtype=torch.float64, device=v.device)
+    _check("hbmc_to_hbmc", lib().hbmc_to_hbmc(f.handle, _dptr(v), _dptr(vb), nrhs, _stream(stream)))
+    return vb
+
+
+def hbmc_from_hbmc(f: Factor, vb, nrhs: int = 1, stream=None):
+    import torch
+    _vec_check(vb, f.n_pad, nrhs, "vb")
+    v = torch.empty(f.n * nrhs, dtype=torch.float64, device=vb.device)
+    _check("hbmc_from_hbmc", lib().hbmc_from_hbmc(f.handle, _dptr(vb), _dptr(v), nrhs, _stream(stream)))
+    return v
+
+
+@dataclass
+class Stats:
+    iters: int
+    status: int
+    rel_res: float
+    true_rel_res: float
+
+
+def workspace(f: Factor, nrhs: int = 1, device="cuda"):
+    import torch
+    b = C.c_size_t(0)
+    _check("iccg_workspace_bytes", lib().iccg_workspace_bytes(f.handle, nrhs, C.byref(b)))
+    return torch.empty(max(b.value, 256), dtype=torch.uint8, device=device)
+
+
+def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 10000,
+               nrhs: int = 1, x0_zero: bool | None = None, check_every: int = 1,
+               use_graph: bool = False, work=None, stream=None):
+    """Solves A x = b (original numbering, device FP64).  Returns (x, stats)."""
+    import torch
+    _vec_check(b, f.n, nrhs, "b")
+    if x is None:
+        x = torch.zeros_like(b)
+        if x0_zero is None:
+            x0_zero = True
+    _vec_check(x, f.n, nrhs, "x")
+    if work is None:
+        work = workspace(f, nrhs, b.device)
+    opts = SolveOpts(1 if x0_zero else 0, max(1, int(check_every)), 1 if use_graph else 0, 0)
+    stats = (SolveStats * nrhs)()
+    code = lib().iccg_solve(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
+                            C.byref(opts), stats, _dptr(work), work.numel(), _stream(stream))
+    _check("iccg_solve", code, ok=(HBMC_OK, HBMC_ENOCONV))
+    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res) for s in stats]
+    return x, (out[0] if nrhs == 1 else out)
+
+
+@dataclass
+class Solver:
+    """Ordering, factor and matrix of one system, uploaded to the device."""
+    order: Order
+    factor: Factor
+    matrix: Matrix
+
+    @staticmethod
+    def setup(A, bs: int, w: int, precision: int = HBMC_F64, shift: float = 0.0,
+              device="cuda") -> "Solver":
+        o = hbmc_order(A, bs, w)
+        f = ic0_factor(o, A, precision, shift).upload(device)
+        m = hbmc_matrix_create(o, A).upload(device)
+        return Solver(o, f, m)
+
+    def solve(self, b, x=None, **kw):
+        return iccg_solve(self.factor, self.matrix, b, x, **kw)

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path against the oracle, through the C ABI.
+
+Bars (stated per test):
+- ic0_apply FP64: ||z - z_ref|| / ||z_ref|| <= 1e-13 and every entry within
+  1e-12 * max|z_ref| (only the summation order differs from the oracle);
+- ic0_apply FP32 (FP32 factor and arithmetic): within 1e-5 of the oracle's
+  FP32 substitution, relative to max|z_ref| -- an FP32 rounding per operation
+  over chains of at most bs steps per color and a few colors;
+- hbmc_spmv: 1e-14 relative, entry-wise;
+- iccg_solve FP64 at a fixed iteration count K: ||x - x_ref|| / ||x_ref||
+  <= 1e-10, and converged runs take the oracle's iteration count +-1.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from paper_1908_00741_amd import hbmc, inputs
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a, np.float64)).cuda()
+
+
+def _host(t):
+    return t.cpu().numpy()
+
+
+APPLY_CASES = [
+    ("c1_grid64_bs4_w8", lambda: inputs.grid2d_5pt(64), 4, 8),
+    ("grid_ragged_bs4_w8", lambda: inputs.grid2d_5pt(37, 11), 4, 8),
+    ("diff3d_20_bs8_w64", lambda: inputs.diffusion3d(20, 1.0, 2), 8, 64),
+    ("diff3d_24_bs8_w16", lambda: inputs.diffusion3d(24, 1.0, 3), 8, 16),
+    ("knn_6000_bs8_w64", lambda: inputs.knn_laplacian(6000, 13, 4, 5), 8, 64),
+    ("knn_3000_bs4_w8", lambda: inputs.knn_laplacian(3000, 13, 6, 7), 4, 8),
+    ("random_bs1_w64_mc", lambda: inputs.random_spd(1500, 0.004, 7), 1, 64),
+    ("random_bs2_w32", lambda: inputs.random_spd(999, 0.006, 8), 2, 32),
+    ("random_bs16_w4", lambda: inputs.random_spd(2000, 0.003, 9), 16, 4),
+    ("random_bs32_w2", lambda: inputs.random_spd(1200, 0.004, 10), 32, 2),
+    ("random_w1_bmc", lambda: inputs.random_spd(700, 0.008, 11), 8, 1),
+    ("path_single", lambda: inputs.path_1d(1), 8, 64),
+    ("path_short", lambda: inputs.path_1d(5), 4, 8),
+]
+
+
+def _apply_case(torch, orc, A, bs, w, precision):
+    s = orc.system(A, bs, w)
+    o = hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ic0_factor(o, A, precision).upload()
+    rng = np.random.default_rng(42)
+    r = rng.uniform(-1, 1, s.ordr.n_pad)
+    dummy = np.setdiff1d(np.arange(s.ordr.n_pad), s.ordr.perm)
+    r[dummy] = 0.0
+    z = _host(hbmc.ic0_apply(f, _dev(torch, r)))
+    torch.cuda.synchronize()
+    zref = orc.apply(s.Ab, s.d, s.fac, r, "f64" if precision == hbmc.HBMC_F64 else "f32")
+    return z, zref, dummy
+
+
+@pytest.mark.parametrize("name,make,bs,w", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
+def test_apply_f64(torch, orc, name, make, bs, w):
+    print(f"case {name}", flush=True)
+    z, zref, dummy = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F64)
+    scale = np.abs(zref).max()
+    assert np.linalg.norm(z - zref) <= 1e-13 * np.linalg.norm(zref)
+    assert np.abs(z - zref).max() <= 1e-12 * scale
+    assert np.all(z[dummy] == 0.0)
+
+
+@pytest.mark.parametrize("name,make,bs,w", APPLY_CASES[:6], ids=[c[0] for c in APPLY_CASES[:6]])
+def test_apply_f32(torch, orc, name, make, bs, w):
+    print(f"case {name}", flush=True)
+    z, zref, _ = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F32)
+    assert np.abs(z - zref).max() <= 1e-5 * np.abs(zref).max()
+
+
+def test_apply_full_size_128(torch, orc):
+    """128^3 lognormal diffusion, bs=8, w=64: the benchmark's launch setup."""
+    print("case full_128", flush=True)
+    A = inputs.diffusion3d(128, 1.0, 2)
+    z, zref, _ = _apply_case(torch, orc, A, 8, 64, hbmc.HBMC_F64)
+    assert np.linalg.norm(z - zref) <= 1e-13 * np.linalg.norm(zref)
+    assert np.abs(z - zref).max() <= 1e-12 * np.abs(zref).max()
+
+
+@pytest.mark.parametrize("name,make,bs,w", APPLY_CASES[:6], ids=[c[0] for c in APPLY_CASES[:6]])
+def test_spmv(torch, orc, name, make, bs, w):
+    A = make()
+    s = orc.system(A, bs, w)
+    o = hbmc.hbmc_order(A, bs, w)
+    m = hbmc.hbmc_matrix_create(o, A).upload()
+    x = np.random.default_rng(5).uniform(-1, 1, s.ordr.n_pad)
+    y = _host(hbmc.hbmc_spmv(m, _dev(torch, x)))
+    yref = orc.spmv(s.Ab, x)
+    assert np.abs(y - yref).max() <= 1e-14 * np.abs(s.Ab.val).max() * np.abs(x).max() * 8
+
+
+def test_permutation_roundtrip(torch, orc):
+    A = inputs.random_spd(333, 0.01, 12)
+    o = hbmc.hbmc_order(A, 4, 8)
+    f = hbmc.ic0_factor(o, A).upload()
+    v = np.random.default_rng(1).standard_normal(A.n)
+    vb = hbmc.hbmc_to_hbmc(f, _dev(torch, v))
+    perm, _ = o.perm()
+    expect = np.zeros(o.n_pad); expect[perm] = v
+    assert np.array_equal(_host(vb), expect)
+    assert np.array_equal(_host(hbmc.hbmc_from_hbmc(f, vb)), v)
+
+
+SOLVE_CASES = [
+    ("c1_grid64", lambda: (inputs.grid2d_5pt(64), None), 4, 8),
+    ("diff3d_24", lambda: (inputs.diffusion3d(24, 1.0, 2), 3), 8, 64),
+    ("knn_6000", lambda: (inputs.knn_laplacian(6000, 13, 4, 5), 6), 8, 64),
+    ("random_ragged", lambda: (inputs.random_spd(1001, 0.004, 13), 14), 4, 8),
+]
+
+
+def _rhs(A, seed):
+    return inputs.row_sums(A) if seed is None else inputs.uniform_rhs(A.n, seed)
+
+
+@pytest.mark.parametrize("name,make,bs,w", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_fixed_iterations(torch, orc, name, make, bs, w):
+    print(f"case {name}", flush=True)
+    A, seed = make()
+    b = _rhs(A, seed)
+    s = orc.system(A, bs, w)
+    solver = hbmc.Solver.setup(A, bs, w)
+    for K in (1, 7, 30):
+        ref = s.solve(b, tol=0.0, maxit=K)
+        x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K)
+        assert st.iters == K and st.status == hbmc.HBMC_ENOCONV
+        x = _host(x)
+        assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), K
+
+
+@pytest.mark.parametrize("name,make,bs,w", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
+def test_solve_converges_like_oracle(torch, orc, name, make, bs, w):
+    print(f"case {name}", flush=True)
+    A, seed = make()
+    b = _rhs(A, seed)
+    ref = orc.system(A, bs, w).solve(b, tol=1e-7)
+    solver = hbmc.Solver.setup(A, bs, w)
+    x, st = solver.solve(_dev(torch, b), tol=1e-7)
+    assert st.status == hbmc.HBMC_OK
+    assert abs(st.iters - ref.iters) <= 1
+    assert st.rel_res < 1e-7
+    xh = _host(x)
+    true = np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b)
+    assert abs(true - st.true_rel_res) <= 1e-3 * true + 1e-15
+    assert np.linalg.norm(xh - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
+
+
+def test_solve_full_size_128(torch, orc):
+    """128^3, bs=8, w=64: fixed-K parity against the oracle, and the converged
+    iteration count against the oracle's (stored by tests/golden/make_iters.py)."""
+    print("case solve_full_128", flush=True)
+    A = inputs.diffusion3d(128, 1.0, 2)
+    b = inputs.uniform_rhs(A.n, 3)
+    s = orc.system(A, 8, 64)
+    solver = hbmc.Solver.setup(A, 8, 64)
+    K = 10
+    ref = s.solve(b, tol=0.0, maxit=K)
+    x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K)
+    assert np.linalg.norm(_host(x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    golden = json.load(open(os.path.join(GOLDEN, "iterations.json")))["diffusion128_s1_bs8_w64"]
+    x, st = solver.solve(_dev(torch, b), tol=1e-7)
+    assert st.status == hbmc.HBMC_OK and abs(st.iters - golden["iters"]) <= 1
+    assert st.true_rel_res < 1.5e-7
+
+
+def test_solve_zero_rhs(torch):
+    A = inputs.grid2d_5pt(16)
+    solver = hbmc.Solver.setup(A, 4, 8)
+    b = torch.zeros(A.n, dtype=torch.float64, device="cuda")
+    x0 = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    x, st = solver.solve(b, x0, x0_zero=False)
+    assert st.iters == 0 and st.status == hbmc.HBMC_OK
+    assert not _host(x).any()
+
+
+def test_solve_warm_start_exact(torch):
+    """x0 = the exact solution of b = A 1: zero iterations."""
+    A = inputs.grid2d_5pt(32)
+    solver = hbmc.Solver.setup(A, 4, 8)
+    b = _dev(torch, inputs.row_sums(A))
+    x0 = torch.ones(A.n, dtype=torch.float64, device="cuda")
+    x, st = solver.solve(b, x0, x0_zero=False, tol=1e-7)
+    assert st.iters == 0 and np.allclose(_host(x), 1.0)
+
+
+def test_solve_maxit_status(torch):
+    A = inputs.diffusion3d(16, 1.0, 2)
+    solver = hbmc.Solver.setup(A, 8, 64)
+    b = _dev(torch, inputs.uniform_rhs(A.n, 1))
+    _, st = solver.solve(b, tol=1e-12, maxit=3)
+    assert st.status == hbmc.HBMC_ENOCONV and st.iters == 3

@@ -1,0 +1,144 @@
+"""Host side of the library against the oracle (no GPU needed).
+
+- the C ABI loads and exports every function include/hbmc.h declares;
+- hbmc_order is bit-exact with the oracle's ordering (perm, color starts,
+  color count, n_pad) on every workload shape and on ragged/random graphs;
+- the IC(0) factor agrees with the oracle's to 1e-14 (FP64);
+- error paths return the documented status codes.
+"""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from paper_1908_00741_amd import hbmc, inputs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_exports_every_declared_symbol():
+    header = open(os.path.join(ROOT, "include", "hbmc.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b([a-z0-9_]+)\s*\(", header)) - {"defined"}
+    declared = {d for d in declared if d.startswith(("hbmc_", "ic0_", "iccg_"))}
+    assert declared == set(hbmc.SYMBOLS)
+    L = hbmc.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+CASES = [
+    ("c1_grid64", lambda: inputs.grid2d_5pt(64), 4, 8),
+    ("grid_ragged", lambda: inputs.grid2d_5pt(37, 11), 4, 8),
+    ("diff3d_20", lambda: inputs.diffusion3d(20, 1.0, 2), 8, 64),
+    ("diff3d_13_bs4", lambda: inputs.diffusion3d(13, 0.5, 3), 4, 16),
+    ("knn_5000", lambda: inputs.knn_laplacian(5000, 13, 4, 5), 8, 64),
+    ("random", lambda: inputs.random_spd(777, 0.01, 6), 5, 4),
+    ("random_bs1", lambda: inputs.random_spd(300, 0.02, 7), 1, 64),
+    ("random_bs32", lambda: inputs.random_spd(1000, 0.005, 8), 32, 2),
+    ("path", lambda: inputs.path_1d(101), 4, 8),
+    ("single", lambda: inputs.path_1d(1), 8, 64),
+]
+
+
+@pytest.mark.parametrize("name,make,bs,w", CASES, ids=[c[0] for c in CASES])
+def test_order_bit_exact(orc, name, make, bs, w):
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w)
+    ref = orc.order(A, bs, w)
+    perm, cs = o.perm()
+    assert o.n_colors == ref.ncolors
+    assert o.n_pad == ref.n_pad
+    assert o.n_blocks == ref.nblocks
+    assert np.array_equal(cs, ref.color_start)
+    assert np.array_equal(perm, ref.perm)
+
+
+@pytest.mark.parametrize("N,sigma,seed", [(128, 1.0, 2), (96, 0.5, 10)])
+def test_order_bit_exact_full_size_grids(orc, N, sigma, seed):
+    """The 128^3 (sigma 1) and 96^3 (sigma 0.5) diffusion workloads at full size."""
+    A = inputs.diffusion3d(N, sigma, seed)
+    o = hbmc.hbmc_order(A, 8, 64)
+    ref = orc.order(A, 8, 64)
+    perm, cs = o.perm()
+    assert np.array_equal(perm, ref.perm) and np.array_equal(cs, ref.color_start)
+
+
+@pytest.mark.parametrize("name,make,bs,w", CASES[:8], ids=[c[0] for c in CASES[:8]])
+def test_factor_matches_oracle(orc, name, make, bs, w):
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ic0_factor(o, A)
+    d, rp, ci, v = f.export()
+    s = orc.system(A, bs, w)
+    Ab = sp.csr_matrix((s.fac, s.Ab.col, s.Ab.rowptr), shape=(s.Ab.n, s.Ab.n))
+    Lref = sp.tril(Ab, k=-1).tocsr()
+    Lref.sort_indices()
+    assert np.array_equal(rp, Lref.indptr) and np.array_equal(ci, Lref.indices)
+    assert np.allclose(v, Lref.data, rtol=1e-14, atol=0)
+    assert np.allclose(d, s.d, rtol=1e-14, atol=0)
+
+
+def test_factor_shift(orc):
+    A = inputs.random_spd(200, 0.03, 3)
+    o = hbmc.hbmc_order(A, 4, 8)
+    d, *_ = hbmc.ic0_factor(o, A, shift=0.3).export()
+    s = orc.system(A, 4, 8, shift=0.3)
+    assert np.allclose(d, s.d, rtol=1e-14, atol=0)
+
+
+def _bad(A, **kw):
+    v = A.val.copy()
+    for k, x in kw.items():
+        v[int(k[1:])] = x
+    return inputs.CSR(A.n, A.rowptr, A.col, v)
+
+
+def test_errors():
+    A = inputs.grid2d_5pt(6)
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(A, 0, 8)
+    assert e.value.code == hbmc.HBMC_EINVAL
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(A, 4, 3)          # w must divide 64
+    assert e.value.code == hbmc.HBMC_EINVAL
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(A, 33, 8)
+    assert e.value.code == hbmc.HBMC_EINVAL
+    o = hbmc.hbmc_order(A, 4, 8)
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ic0_factor(o, _bad(A, p1=-0.25))   # value asymmetry
+    assert e.value.code == hbmc.HBMC_ENOTSYM
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ic0_factor(o, _bad(A, p0=-1.0))    # negative diagonal
+    assert e.value.code == hbmc.HBMC_EDIAG
+    # pattern asymmetry: drop one off-diagonal entry
+    S = A.to_scipy().tolil()
+    S[0, 1] = 0
+    S = S.tocsr(); S.eliminate_zeros()
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(inputs.from_scipy(S), 4, 8)
+    assert e.value.code == hbmc.HBMC_ENOTSYM
+    # missing diagonal
+    S = A.to_scipy().tolil()
+    S[3, 3] = 0
+    S = S.tocsr(); S.eliminate_zeros()
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(inputs.from_scipy(S), 4, 8)
+    assert e.value.code == hbmc.HBMC_EDIAG
+    # unsorted columns
+    col = A.col.copy()
+    col[[0, 1]] = col[[1, 0]]
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.hbmc_order(inputs.CSR(A.n, A.rowptr, col, A.val), 4, 8)
+    assert e.value.code == hbmc.HBMC_EINVAL
+
+
+def test_breakdown():
+    A = inputs.from_scipy(sp.csr_matrix(np.array([[1.0, 2.0], [2.0, 1.0]])))
+    o = hbmc.hbmc_order(A, 1, 1)
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ic0_factor(o, A)
+    assert e.value.code == hbmc.HBMC_EBREAKDOWN

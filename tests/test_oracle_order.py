@@ -27,7 +27,7 @@ def _matrix(spec):
     raise ValueError(spec)
 
 
-@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "*.json"))),
+@pytest.mark.parametrize("path", sorted(glob.glob(os.path.join(GOLDEN, "order_*.json"))),
                          ids=os.path.basename)
 def test_hand_derived(orc, path):
     g = json.load(open(path))
