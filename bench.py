@@ -49,6 +49,9 @@ def main() -> int:
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run one 256 MiB device-to-device copy first (a kernel of known "
+                         "traffic, for scaling hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -63,6 +66,12 @@ def main() -> int:
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda:0")
+    if args.calibrate:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)    # 256 MiB
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     N, bs, w = args.N, 8, 64
     log(f"[bench] building 128^3 workload N={N}")
     A = inputs.diffusion3d(N, 1.0, 2)

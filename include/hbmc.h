@@ -204,6 +204,12 @@ int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, 
                int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
                hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
 
+/* Residual history of the last iccg_solve that ran with record_history on
+ * this workspace: hist[k] = ||r_k|| / ||b|| for k = 0..count-1 (k = 0 is the
+ * initial residual), count <= 65536.  Synchronous copy to host memory. */
+int iccg_history(const void *work, size_t work_bytes, const hbmc_factor_t *f, double *hist,
+                 int32_t count, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -93,35 +93,103 @@ int ic0_rows(const Csr &a, int64_t n, double shift, std::vector<int64_t> &lrp,
     return HBMC_OK;
 }
 
-// A list of (column, value) couplings per row, packed as sliced ELL with
-// slices of kTileLanes rows; missing slots get column -1 and value 0.
-void pack_ext(const std::vector<std::vector<std::pair<int32_t, double>>> &rows, int64_t row0,
-              int64_t row1, Sell &s) {
-    const int64_t nslices = (row1 - row0 + kTileLanes - 1) / kTileLanes;
-    for (int64_t g = 0; g < nslices; ++g) {
-        size_t len = 0;
-        for (int64_t r = row0 + g * kTileLanes; r < std::min(row1, row0 + (g + 1) * kTileLanes); ++r)
-            len = std::max(len, rows[r].size());
-        const int64_t base = s.off.back();
-        s.off.push_back(int32_t(base + len));
-        s.val.resize((base + len) * kTileLanes, 0.0);
-        s.col.resize((base + len) * kTileLanes, -1);
-        for (int64_t r = row0 + g * kTileLanes; r < std::min(row1, row0 + (g + 1) * kTileLanes); ++r) {
-            const int lane = int((r - row0) % kTileLanes);
-            for (size_t t = 0; t < rows[r].size(); ++t) {
-                s.col[(base + t) * kTileLanes + lane] = rows[r][t].first;
-                s.val[(base + t) * kTileLanes + lane] = rows[r][t].second;
-            }
-        }
-    }
-}
-
 template <class T>
 std::vector<T> cast(const std::vector<double> &v) {
     return std::vector<T>(v.begin(), v.end());
 }
 
+template <class T>
+size_t add_packed(ImageBuilder &im, const Packed &p, bool f32, PackedOffsets &o) {
+    o.soff = im.add(p.soff);
+    o.sbase = im.add(p.sbase);
+    o.smask = im.add(p.smask);
+    o.sval = f32 ? im.add(cast<float>(p.sval)) : im.add(p.sval);
+    o.ioff = im.add(p.ioff);
+    o.icol = im.add(p.icol);
+    o.ival = f32 ? im.add(cast<float>(p.ival)) : im.add(p.ival);
+    return o.soff;
+}
+
 }  // namespace
+
+int Packed::add_group(const std::vector<const Couplings *> &lanes, int64_t limit, int budget) {
+    const int nl = int(lanes.size());
+    // every coupling (lane j, column c) proposes the strided base c - j
+    struct Entry { int64_t key; int lane; int idx; };
+    std::vector<Entry> all;
+    for (int j = 0; j < nl; ++j)
+        if (lanes[j])
+            for (int t = 0; t < int(lanes[j]->size()); ++t)
+                all.push_back({int64_t((*lanes[j])[t].first) - j, j, t});
+    entries += int64_t(all.size());
+    std::sort(all.begin(), all.end(), [](const Entry &a, const Entry &b) {
+        return a.key != b.key ? a.key < b.key : a.lane < b.lane;
+    });
+    // bases shared by enough lanes become strided slots, most shared first
+    struct Cand { int64_t key; size_t first, count; };
+    std::vector<Cand> cands;
+    for (size_t i = 0; i < all.size();) {
+        size_t k = i;
+        while (k < all.size() && all[k].key == all[i].key) ++k;
+        const int64_t key = all[i].key;
+        if (int(k - i) >= kMinStridedLanes && key >= 0 && key + kTileLanes <= limit)
+            cands.push_back({key, i, k - i});
+        i = k;
+    }
+    std::stable_sort(cands.begin(), cands.end(),
+                     [](const Cand &a, const Cand &b) { return a.count > b.count; });
+    if (int(cands.size()) > std::max(budget, 0)) cands.resize(std::max(budget, 0));
+    std::vector<std::vector<uint8_t>> used(nl);
+    for (int j = 0; j < nl; ++j)
+        if (lanes[j]) used[j].assign(lanes[j]->size(), 0);
+    for (const Cand &c : cands) {
+        const int64_t slot = int64_t(sbase.size());
+        sbase.push_back(int32_t(c.key));
+        uint64_t mask = 0;
+        sval.resize((slot + 1) * kTileLanes, 0.0);
+        for (size_t i = c.first; i < c.first + c.count; ++i) {
+            const Entry &e = all[i];
+            mask |= uint64_t(1) << e.lane;
+            sval[slot * kTileLanes + e.lane] = (*lanes[e.lane])[e.idx].second;
+            used[e.lane][e.idx] = 1;
+        }
+        smask.push_back(mask);
+    }
+    soff.push_back(int32_t(sbase.size()));
+    max_strided = std::max(max_strided, int32_t(cands.size()));
+    // the rest, per lane in column order, as indexed slots
+    size_t len = 0;
+    for (int j = 0; j < nl; ++j)
+        if (lanes[j]) {
+            size_t left = 0;
+            for (uint8_t u : used[j]) left += !u;
+            len = std::max(len, left);
+        }
+    const int64_t base = ioff.back();
+    ioff.push_back(int32_t(base + len));
+    icol.resize((base + len) * kTileLanes, -1);
+    ival.resize((base + len) * kTileLanes, 0.0);
+    for (int j = 0; j < nl; ++j) {
+        if (!lanes[j]) continue;
+        int64_t t = 0;
+        for (size_t i = 0; i < lanes[j]->size(); ++i)
+            if (!used[j][i]) {
+                icol[(base + t) * kTileLanes + j] = (*lanes[j])[i].first;
+                ival[(base + t) * kTileLanes + j] = (*lanes[j])[i].second;
+                ++t;
+            }
+    }
+    max_indexed = std::max(max_indexed, int32_t(len));
+    return int(cands.size());
+}
+
+void Packed::finish() {
+    sbase.push_back(0);
+    smask.push_back(0);
+    sval.resize(sval.size() + kTileLanes, 0.0);
+    icol.resize(icol.size() + kTileLanes, -1);
+    ival.resize(ival.size() + kTileLanes, 0.0);
+}
 
 extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
                           const double *val, int32_t precision, double shift, hbmc_factor_t **out) {
@@ -160,7 +228,7 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         // couplings of each row: forward (lower) and backward (upper, scaled
         // by diaginv of the row: U = I + D^-1 L^T), split into couplings to
         // other colors (ext) and inside the level-1 block (int)
-        std::vector<std::vector<std::pair<int32_t, double>>> fe(n), fi(n), be(n), bi(n);
+        std::vector<Couplings> fe(n), fi(n), be(n), bi(n);
         for (int64_t r = 0; r < n; ++r) {
             const int64_t lb = (r - f->color_start[color[r]]) / l1;
             for (int64_t p = f->lrp[r]; p < f->lrp[r + 1]; ++p) {
@@ -184,41 +252,65 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         }
         // be and bi were filled in ascending r, so they are already sorted
 
-        // forward/backward ext: per color, 64-row slices from the color start
-        f->slice_base.assign(f->nc + 1, 0);
+        // Layout of the substitutions: per color, the chain lanes (one per BMC
+        // block, lam = level-1 block * w + m) are cut into tiles of 64 lanes;
+        // for each (tile, step l) a sliced-ELL slot list holds, slot-major,
+        // one entry per lane: the couplings of row  S_c + (lam / w) bs w +
+        // l w + lam % w.  Missing entries have column -1 and value 0.  Each
+        // array ends with one extra all-padding slot that loads may target
+        // instead of branching.
         f->tile_base.assign(f->nc + 1, 0);
-        f->fext.off.assign(1, 0);
-        f->bext.off.assign(1, 0);
         for (int c = 0; c < f->nc; ++c) {
-            const int64_t r0 = f->color_start[c], r1 = f->color_start[c + 1];
-            f->slice_base[c + 1] = f->slice_base[c] + (r1 - r0 + kTileLanes - 1) / kTileLanes;
-            const int64_t lanes = (r1 - r0) / bs;   // = level-1 blocks * w
+            const int64_t lanes = (f->color_start[c + 1] - f->color_start[c]) / bs;
             f->tile_base[c + 1] = f->tile_base[c] + (lanes + kTileLanes - 1) / kTileLanes;
-            pack_ext(fe, r0, r1, f->fext);
-            pack_ext(be, r0, r1, f->bext);
         }
-        // int: per tile (kTileLanes chain lanes) and step l, slot-major over lanes
-        auto pack_int = [&](const std::vector<std::vector<std::pair<int32_t, double>>> &rows,
-                            Sell &s, int32_t &max_slots) {
+        // couplings to other colors: one Packed group per (tile, step)
+        std::vector<const Couplings *> lanes_f, lanes_b;
+        for (int c = 0; c < f->nc; ++c) {
+            const int64_t r0 = f->color_start[c];
+            const int64_t lanes = (f->color_start[c + 1] - r0) / bs;
+            for (int64_t t0 = 0; t0 < lanes; t0 += kTileLanes) {
+                // the kernel fetches a tile's strided-slot metadata one slot per lane
+                int budget_f = kTileLanes, budget_b = kTileLanes;
+                for (int l = 0; l < bs; ++l) {
+                    lanes_f.assign(kTileLanes, nullptr);
+                    lanes_b.assign(kTileLanes, nullptr);
+                    for (int64_t lam = t0; lam < std::min(lanes, t0 + kTileLanes); ++lam) {
+                        const int64_t row = r0 + (lam / w) * l1 + int64_t(l) * w + lam % w;
+                        lanes_f[lam - t0] = &fe[row];
+                        lanes_b[lam - t0] = &be[row];
+                    }
+                    budget_f -= f->fext.add_group(lanes_f, n, budget_f);
+                    budget_b -= f->bext.add_group(lanes_b, n, budget_b);
+                }
+            }
+        }
+        f->fext.finish();
+        f->bext.finish();
+        // couplings inside the level-1 blocks: per (tile, step) a list of
+        // slots, one entry per lane (column = source step, -1 = none)
+        auto pack_lanes = [&](const std::vector<Couplings> &rows, Sell &s, int32_t &max_slots,
+                              int32_t &max_step) {
             s.off.assign(1, 0);
             max_slots = 0;
+            max_step = 0;
             for (int c = 0; c < f->nc; ++c) {
                 const int64_t r0 = f->color_start[c];
                 const int64_t lanes = (f->color_start[c + 1] - r0) / bs;
                 for (int64_t t0 = 0; t0 < lanes; t0 += kTileLanes) {
+                    const int64_t t1 = std::min(lanes, t0 + kTileLanes);
                     int32_t tile_slots = 0;
                     for (int l = 0; l < bs; ++l) {
                         auto row_of = [&](int64_t lam) {
                             return r0 + (lam / w) * l1 + int64_t(l) * w + lam % w;
                         };
                         size_t len = 0;
-                        for (int64_t lam = t0; lam < std::min(lanes, t0 + kTileLanes); ++lam)
-                            len = std::max(len, rows[row_of(lam)].size());
+                        for (int64_t lam = t0; lam < t1; ++lam) len = std::max(len, rows[row_of(lam)].size());
                         const int64_t base = s.off.back();
                         s.off.push_back(int32_t(base + len));
                         s.val.resize((base + len) * kTileLanes, 0.0);
-                        s.col.resize((base + len) * kTileLanes, l);   // padding reads its own step
-                        for (int64_t lam = t0; lam < std::min(lanes, t0 + kTileLanes); ++lam) {
+                        s.col.resize((base + len) * kTileLanes, -1);
+                        for (int64_t lam = t0; lam < t1; ++lam) {
                             const auto &e = rows[row_of(lam)];
                             for (size_t t = 0; t < e.size(); ++t) {
                                 s.col[(base + t) * kTileLanes + (lam - t0)] = e[t].first;
@@ -226,28 +318,24 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
                             }
                         }
                         tile_slots += int32_t(len);
+                        max_step = std::max(max_step, int32_t(len));
                     }
                     max_slots = std::max(max_slots, tile_slots);
                 }
             }
+            s.val.resize(s.val.size() + kTileLanes, 0.0);   // the padding slot
+            s.col.resize(s.col.size() + kTileLanes, -1);
         };
-        pack_int(fi, f->fint, f->max_int_slots_f);
-        pack_int(bi, f->bint, f->max_int_slots_b);
+        pack_lanes(fi, f->fint, f->max_int_slots_f, f->max_int_step_f);
+        pack_lanes(bi, f->bint, f->max_int_slots_b, f->max_int_step_b);
 
         // device image
         auto &im = f->image;
-        auto add_tri = [&](const Sell &e, const Sell &i, TriOffsets &t) {
-            t.ext_off = im.add(e.off);
-            t.ext_col = im.add(e.col);
+        auto add_tri = [&](const Packed &e, const Sell &i, TriOffsets &t) {
+            add_packed<double>(im, e, precision == HBMC_F32, t.ext);
             t.int_off = im.add(i.off);
             t.int_lp = im.add(i.col);
-            if (precision == HBMC_F64) {
-                t.ext_val = im.add(e.val);
-                t.int_val = im.add(i.val);
-            } else {
-                t.ext_val = im.add(cast<float>(e.val));
-                t.int_val = im.add(cast<float>(i.val));
-            }
+            t.int_val = precision == HBMC_F64 ? im.add(i.val) : im.add(cast<float>(i.val));
         };
         f->off_dinv = precision == HBMC_F64 ? im.add(dinv) : im.add(cast<float>(dinv));
         f->off_perm = im.add(f->perm);
@@ -279,7 +367,11 @@ extern "C" int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes) {
     return HBMC_OK;
 }
 
-extern "C" void hbmc_factor_destroy(hbmc_factor_t *f) { delete f; }
+extern "C" void hbmc_factor_destroy(hbmc_factor_t *f) {
+    if (!f) return;
+    release_graphs(f);
+    delete f;
+}
 
 extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
                                   const double *val, hbmc_matrix_t **out) {
@@ -295,18 +387,22 @@ extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, 
         m->n_pad = o->n_pad;
         const Csr a = permute(*o, rowptr, col, val);
         m->diag.assign(m->n_pad, 0.0);
-        std::vector<std::vector<std::pair<int32_t, double>>> rows(m->n_pad);
+        std::vector<Couplings> rows(m->n_pad);
         for (int64_t r = 0; r < m->n_pad; ++r)
             for (int64_t p = a.rp[r]; p < a.rp[r + 1]; ++p) {
                 if (a.ci[p] == r) m->diag[r] = a.v[p];
                 else rows[r].emplace_back(a.ci[p], a.v[p]);
             }
-        m->off.off.assign(1, 0);
-        pack_ext(rows, 0, m->n_pad, m->off);
+        // one Packed group per 64-row slice
+        std::vector<const Couplings *> lanes;
+        for (int64_t r0 = 0; r0 < m->n_pad; r0 += kTileLanes) {
+            lanes.assign(kTileLanes, nullptr);
+            for (int64_t r = r0; r < std::min(m->n_pad, r0 + kTileLanes); ++r) lanes[r - r0] = &rows[r];
+            m->off.add_group(lanes, m->n_pad, kTileLanes);
+        }
+        m->off.finish();
         m->off_diag = m->image.add(m->diag);
-        m->off_soff = m->image.add(m->off.off);
-        m->off_val = m->image.add(m->off.val);
-        m->off_col = m->image.add(m->off.col);
+        add_packed<double>(m->image, m->off, false, m->offs);
         m->image.bytes.resize((m->image.bytes.size() + 255) & ~size_t(255));
         *out = m;
         return HBMC_OK;

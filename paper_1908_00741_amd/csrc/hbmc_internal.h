@@ -15,10 +15,12 @@ namespace hbmc {
 int fail(int code, const char *fmt, ...);
 void clear_error();
 
-// Rows of one phase are processed in tiles of kTileLanes lanes x bs steps;
-// the sliced-ELL slices are kTileLanes rows high.  kTileLanes is the
-// wavefront width of gfx950.
+// A color is processed in tiles of kTileLanes chain lanes (one lane per BMC
+// block) x bs steps; each tile is one wavefront of gfx950.  The SpMV uses
+// sliced ELL with slices of kTileLanes consecutive rows.
 constexpr int kTileLanes = 64;
+// A base shared by at least this many lanes of a group makes a strided slot.
+constexpr int kMinStridedLanes = 48;
 
 // Checks a CSR pattern: sizes, sorted in-range columns, diagonal present,
 // symmetric pattern.  Values (if given) must be symmetric with a positive
@@ -32,6 +34,45 @@ struct Sell {
     std::vector<double> val;    // [slots * kTileLanes]
     std::vector<int32_t> col;   // [slots * kTileLanes]
     int64_t slots() const { return off.empty() ? 0 : off.back(); }
+};
+
+// Enqueues z = M^-1 r on stream (a hipStream_t).  When done is not null the
+// kernels return at once while *done != 0 (used inside captured CG loops).
+int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *stream,
+                 const int32_t *done);
+// Destroys the hipGraph executables cached by iccg_solve for this factor.
+void release_graphs(::hbmc_factor_s *f);
+// Unique id for each upload of a device image (keys the graph cache).
+uint64_t next_uid();
+
+// Couplings of groups of kTileLanes rows, one row per lane, in two kinds of
+// slots.  A strided slot has one base per slot: lane j couples to column
+// base + j when bit j of the slot's lane mask is set.  On HBMC-ordered
+// structured grids most couplings line up this way, because the 64 lanes
+// are 64 consecutive BMC blocks whose neighbours are consecutive too; such
+// a slot needs no index array and its loads do not wait for indices.  What
+// does not line up goes to indexed slots (one column per lane, -1 = none).
+// Each array ends with one all-padding slot that loads may target instead
+// of branching.
+using Couplings = std::vector<std::pair<int32_t, double>>;
+struct Packed {
+    std::vector<int32_t> soff{0};   // [groups + 1] strided slots per group
+    std::vector<int32_t> sbase;     // [strided + 1]
+    std::vector<uint64_t> smask;    // [strided + 1]
+    std::vector<double> sval;       // [(strided + 1) * kTileLanes]
+    std::vector<int32_t> ioff{0};   // [groups + 1] indexed slots per group
+    std::vector<int32_t> icol;      // [(indexed + 1) * kTileLanes]
+    std::vector<double> ival;       // [(indexed + 1) * kTileLanes]
+    int32_t max_strided = 0, max_indexed = 0;   // per group
+    int64_t entries = 0;                        // couplings stored
+    // lanes[j]: couplings of lane j's row (sorted by column), or null.
+    // Columns base + j of strided slots stay below limit; at most budget
+    // strided slots are made (the rest of the couplings go to indexed slots).
+    // Returns the number of strided slots made.
+    int add_group(const std::vector<const Couplings *> &lanes, int64_t limit, int budget);
+    void finish();   // appends the padding slots
+    int64_t strided() const { return soff.back(); }
+    int64_t indexed() const { return ioff.back(); }
 };
 
 // Byte layout of a device image: every array starts on a 256-byte boundary.
@@ -51,9 +92,14 @@ struct hbmc_order_s {
     std::vector<int64_t> color_start;  // [nc + 1]
 };
 
-// Offsets (bytes, inside the device image) of one triangular direction.
+// Offsets (bytes, inside a device image) of a Packed layout.
+struct PackedOffsets {
+    size_t soff, sbase, smask, sval, ioff, icol, ival;
+};
+
+// Offsets of one triangular direction.
 struct TriOffsets {
-    size_t ext_off, ext_val, ext_col;   // per 64-row slice: couplings to other colors
+    PackedOffsets ext;                  // per (tile, step): couplings to other colors
     size_t int_off, int_val, int_lp;    // per (tile, step): couplings inside the level-1 block
 };
 
@@ -61,7 +107,6 @@ struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int64_t n_pad = 0;
     std::vector<int64_t> color_start;
-    std::vector<int64_t> slice_base;   // [nc + 1] first global slice of each color
     std::vector<int64_t> tile_base;    // [nc + 1] first global tile of each color
     std::vector<int32_t> perm, iperm;
     // FP64 factor: strictly lower L in CSR over HBMC indices, and d
@@ -69,24 +114,36 @@ struct hbmc_factor_s {
     std::vector<int32_t> lcol;
     std::vector<double> lval, d;
     // substitution layout
-    hbmc::Sell fext, bext;   // forward: L to earlier colors; backward: U to later colors
+    hbmc::Packed fext, bext;   // forward: L to earlier colors; backward: U to later colors
     hbmc::Sell fint, bint;   // inside level-1 blocks; col = source step (0..bs-1)
     int32_t max_int_slots_f = 0, max_int_slots_b = 0;   // per tile, summed over steps
+    int32_t max_int_step_f = 0, max_int_step_b = 0;     // per (tile, step)
     // device image
     hbmc::ImageBuilder image;
     size_t off_dinv = 0, off_perm = 0, off_iperm = 0;
     TriOffsets fwd{}, bwd{};
     void *dev = nullptr;
     size_t dev_bytes = 0;
+    uint64_t uid = 0;
+    // captured CG iteration graphs: (matrix upload, workspace, iterations) -> exec
+    struct Graph {
+        uint64_t matrix_uid;
+        const void *work;
+        int32_t iters;
+        void *exec;
+    };
+    std::vector<Graph> graphs;
 };
 
 struct hbmc_matrix_s {
     int32_t n = 0;
     int64_t n_pad = 0;
     std::vector<double> diag;   // [n_pad]
-    hbmc::Sell off;             // off-diagonal entries, 64-row slices from row 0
+    hbmc::Packed off;           // off-diagonal entries, 64-row slices from row 0
     hbmc::ImageBuilder image;
-    size_t off_diag = 0, off_soff = 0, off_val = 0, off_col = 0;
+    size_t off_diag = 0;
+    PackedOffsets offs{};
     void *dev = nullptr;
     size_t dev_bytes = 0;
+    uint64_t uid = 0;
 };

@@ -26,7 +26,7 @@ SYMBOLS = (
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
     "hbmc_factor_upload", "hbmc_factor_destroy", "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
-    "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve",
+    "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
 )
 
 
@@ -87,6 +87,7 @@ def lib():
         L.hbmc_from_hbmc.argtypes = [P, P, P, i32, P]
         L.iccg_workspace_bytes.argtypes = [P, i32, P]
         L.iccg_solve.argtypes = [P, P, P, P, i32, f64, i32, P, P, P, sz, P]
+        L.iccg_history.argtypes = [P, sz, P, P, i32, P]
         _lib = L
     return _lib
 
@@ -303,9 +304,10 @@ def workspace(f: Factor, nrhs: int = 1, device="cuda"):
 
 
 def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 10000,
-               nrhs: int = 1, x0_zero: bool | None = None, check_every: int = 1,
-               use_graph: bool = False, work=None, stream=None):
-    """Solves A x = b (original numbering, device FP64).  Returns (x, stats)."""
+               nrhs: int = 1, x0_zero: bool | None = None, check_every: int = 0,
+               use_graph: bool = True, history: bool = False, work=None, stream=None):
+    """Solves A x = b (original numbering, device FP64).  Returns (x, stats),
+    or (x, stats, hist) with history=True."""
     import torch
     _vec_check(b, f.n, nrhs, "b")
     if x is None:
@@ -315,12 +317,18 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
     _vec_check(x, f.n, nrhs, "x")
     if work is None:
         work = workspace(f, nrhs, b.device)
-    opts = SolveOpts(1 if x0_zero else 0, max(1, int(check_every)), 1 if use_graph else 0, 0)
+    opts = SolveOpts(1 if x0_zero else 0, int(check_every), 1 if use_graph else 0,
+                     1 if history else 0)
     stats = (SolveStats * nrhs)()
     code = lib().iccg_solve(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
                             C.byref(opts), stats, _dptr(work), work.numel(), _stream(stream))
     _check("iccg_solve", code, ok=(HBMC_OK, HBMC_ENOCONV))
     out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res) for s in stats]
+    if history:
+        h = np.empty(out[0].iters + 1)
+        _check("iccg_history", lib().iccg_history(_dptr(work), work.numel(), f.handle, _ptr(h),
+                                                  len(h), _stream(stream)))
+        return x, (out[0] if nrhs == 1 else out), h
     return x, (out[0] if nrhs == 1 else out)
 
 

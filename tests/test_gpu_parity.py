@@ -137,9 +137,9 @@ def test_solve_fixed_iterations(torch, orc, name, make, bs, w):
     b = _rhs(A, seed)
     s = orc.system(A, bs, w)
     solver = hbmc.Solver.setup(A, bs, w)
-    for K in (1, 7, 30):
+    for K, graph in ((1, True), (7, False), (30, True)):
         ref = s.solve(b, tol=0.0, maxit=K)
-        x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K)
+        x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K, use_graph=graph)
         assert st.iters == K and st.status == hbmc.HBMC_ENOCONV
         x = _host(x)
         assert np.linalg.norm(x - ref.x) <= 1e-10 * np.linalg.norm(ref.x), K
@@ -206,3 +206,52 @@ def test_solve_maxit_status(torch):
     b = _dev(torch, inputs.uniform_rhs(A.n, 1))
     _, st = solver.solve(b, tol=1e-12, maxit=3)
     assert st.status == hbmc.HBMC_ENOCONV and st.iters == 3
+
+
+def test_graph_replay_matches_eager(torch):
+    """The captured iteration graph, replayed many times (with eager work and
+    synchronizations between replays), gives bit-identical results to eager
+    launches, whatever the replay length."""
+    A = inputs.diffusion3d(24, 1.0, 2)
+    b = _dev(torch, inputs.uniform_rhs(A.n, 3))
+    solver = hbmc.Solver.setup(A, 8, 64)
+    x_e, st_e = solver.solve(b, use_graph=False, check_every=1)
+    results = []
+    for check in (16, 5, 16, 1):
+        x_g, st_g = solver.solve(b, use_graph=True, check_every=check)
+        torch.cuda.synchronize()
+        _ = (x_g * 2).sum().item()          # eager work between replays
+        results.append((x_g.clone(), st_g))
+    for x_g, st_g in results:
+        assert st_g.iters == st_e.iters and st_g.status == hbmc.HBMC_OK
+        assert torch.equal(x_g, x_e)
+        assert st_g.rel_res == st_e.rel_res
+
+
+def test_history_matches_oracle(torch, orc):
+    A = inputs.knn_laplacian(4000, 13, 4, 5)
+    b = inputs.uniform_rhs(A.n, 6)
+    ref = orc.system(A, 8, 64).solve(b, tol=1e-7)
+    solver = hbmc.Solver.setup(A, 8, 64)
+    x, st, hist = solver.solve(_dev(torch, b), tol=1e-7, history=True)
+    k = min(len(hist), len(ref.hist))
+    assert abs(len(hist) - len(ref.hist)) <= 1
+    assert np.allclose(np.log10(hist[:k]), np.log10(ref.hist[:k]), atol=1e-6)
+
+
+@pytest.mark.parametrize("name,make,bs", [
+    ("diff3d_32", lambda: inputs.diffusion3d(32, 1.0, 2), 8),
+    ("knn_20000", lambda: inputs.knn_laplacian(20000, 13, 4, 5), 8),
+    ("grid2d_ragged", lambda: inputs.grid2d_5pt(101, 77), 4),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_hbmc_bmc_equivalent_on_device(torch, name, make, bs):
+    """HBMC (w = 64, 16, 8) and BMC (w = 1) converge in the same number of
+    iterations up to rounding (Section 4.2.1; Table "number-ite")."""
+    A = make()
+    b = _dev(torch, inputs.uniform_rhs(A.n, 9))
+    its = {}
+    for w in (1, 8, 16, 64):
+        _, st = hbmc.Solver.setup(A, bs, w).solve(b, tol=1e-7)
+        assert st.status == hbmc.HBMC_OK
+        its[w] = st.iters
+    assert max(its.values()) - min(its.values()) <= 1, its
