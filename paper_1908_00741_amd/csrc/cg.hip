@@ -96,10 +96,11 @@ __device__ inline uint64_t readlane64(uint64_t v, int lane) {
 // One row of y = A x.  A wavefront is one 64-row group, so the group index
 // is uniform; the group's strided-slot bases and masks (at most 64) come in
 // with one vector load, one slot per lane, and are broadcast with readlane.
-__device__ inline double spmv_row(const Mat &m, const double *__restrict__ x, int64_t row) {
+template <class X>
+__device__ inline double spmv_row_with(const Mat &m, X x, int64_t row) {
     const int64_t g = __builtin_amdgcn_readfirstlane(int(row >> 6));
     const int lane = int(row & 63);
-    double acc = m.diag[row] * x[row];
+    double acc = m.diag[row] * x(row);
     const int32_t s0 = m.soff[g], ns = m.soff[g + 1] - s0;
     const int64_t ms = s0 + (lane < ns ? lane : 0);
     const int32_t mbase = m.sbase[ms];
@@ -109,7 +110,7 @@ __device__ inline double spmv_row(const Mat &m, const double *__restrict__ x, in
         const int32_t base = __builtin_amdgcn_readlane(mbase, k);
         const bool on = (readlane64(mmask, k) >> lane) & 1;
         const double v = m.sval[(s0 + k) * int64_t(kLanes) + lane];
-        const double xv = x[base + lane];
+        const double xv = x(base + lane);
         acc = on ? acc + v * xv : acc;
     }
 #pragma unroll 4
@@ -117,10 +118,14 @@ __device__ inline double spmv_row(const Mat &m, const double *__restrict__ x, in
         const int64_t e = s * kLanes + lane;
         const int32_t c = m.icol[e];
         const double v = m.ival[e];
-        const double xv = x[c >= 0 ? c : 0];
+        const double xv = x(c >= 0 ? c : 0);
         acc = c >= 0 ? acc + v * xv : acc;
     }
     return acc;
+}
+
+__device__ inline double spmv_row(const Mat &m, const double *__restrict__ x, int64_t row) {
+    return spmv_row_with(m, [=](int64_t i) { return x[i]; }, row);
 }
 
 // one element per thread (the grid covers n)
@@ -164,7 +169,7 @@ __global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int g, Cg
     if (!isfinite(st->res)) st->done = kBreakdown;
 }
 
-// p = z; partial of (r, z)
+// p = z; partial of (r, z)   (beta = 0 for the first iteration)
 __global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, const double *__restrict__ r,
                                                    const double *__restrict__ z,
                                                    double *__restrict__ p, double *part) {
@@ -179,19 +184,26 @@ __global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, const double *__re
 
 __global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, int g, CgState *st) {
     const double t = total(part, g);
-    if (threadIdx.x == 0) st->rho = t;
+    if (threadIdx.x == 0) { st->rho = t; st->beta = 0.0; }
 }
 
-// q = A p; partial of (p, q)
-__global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, const double *__restrict__ p,
-                                                     double *__restrict__ q, double *part,
-                                                     const CgState *st) {
+// p = z + beta p_old (formed on the fly, also at the columns the row
+// couples to), written to p_new; q = A p; partial of (p, q)
+__global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, const double *__restrict__ z,
+                                                       const double *__restrict__ p_old,
+                                                       double *__restrict__ p_new,
+                                                       double *__restrict__ q, double *part,
+                                                       const CgState *st) {
     if (st->done) return;
+    const double beta = st->beta;
     double s = 0.0;
     GRID_STRIDE(row, m.n) {
-        const double qi = spmv_row(m, p, row);
+        auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
+        const double pi = pv(row);
+        const double qi = spmv_row_with(m, pv, row);
+        p_new[row] = pi;
         q[row] = qi;
-        s += p[row] * qi;
+        s += pi * qi;
     }
     s = block_sum(s);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -207,29 +219,15 @@ __global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int g, C
     st->alpha = st->rho / sigma;
 }
 
-// x += alpha p; r -= alpha q; partial of ||r||^2
-__global__ void __launch_bounds__(kBlock) k_xr(int64_t n, const double *__restrict__ p,
-                                               const double *__restrict__ q,
-                                               double *__restrict__ x, double *__restrict__ r,
-                                               double *part, const CgState *st) {
+// After the preconditioning step: ||r||^2 and (r, z) from the per-tile
+// partials; one more iteration done; stopping test ||r|| / ||b|| < tol;
+// then beta = rho' / rho, rho = rho' for the next direction.
+__global__ void __launch_bounds__(kFin) k_fin_rr_beta(const double *part_rr, const double *part_rz,
+                                                      int ntiles, CgState *st, double *hist,
+                                                      int32_t hist_len) {
     if (st->done) return;
-    const double alpha = st->alpha;
-    double s = 0.0;
-    GRID_STRIDE(i, n) {
-        x[i] = x[i] + alpha * p[i];
-        const double ri = r[i] - alpha * q[i];
-        r[i] = ri;
-        s += ri * ri;
-    }
-    s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// ||r||^2; one more iteration done; stopping test ||r|| / ||b|| < tol
-__global__ void __launch_bounds__(kFin) k_fin_rr(const double *part, int g, CgState *st,
-                                                   double *hist, int32_t hist_len) {
-    if (st->done) return;
-    const double rr = total(part, g);
+    const double rr = total(part_rr, ntiles);
+    const double rz = total(part_rz, ntiles);
     if (threadIdx.x) return;
     st->rr = rr;
     st->it += 1;
@@ -238,34 +236,10 @@ __global__ void __launch_bounds__(kFin) k_fin_rr(const double *part, int g, CgSt
     if (!isfinite(st->res)) st->done = kBreakdown;
     else if (st->res < st->tol) st->done = kConverged;
     else if (st->it >= st->maxit) st->done = kMaxIt;
-}
-
-// partial of (r, z)
-__global__ void __launch_bounds__(kBlock) k_rz(int64_t n, const double *__restrict__ r,
-                                               const double *__restrict__ z, double *part,
-                                               const CgState *st) {
-    if (st->done) return;
-    double s = 0.0;
-    GRID_STRIDE(i, n) s += r[i] * z[i];
-    s = block_sum(s);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
-}
-
-// rho' = (r, z); beta = rho' / rho; rho = rho'
-__global__ void __launch_bounds__(kFin) k_fin_beta(const double *part, int g, CgState *st) {
-    if (st->done) return;
-    const double t = total(part, g);
-    if (threadIdx.x) return;
-    st->beta = t / st->rho;
-    st->rho = t;
-}
-
-// p = z + beta p
-__global__ void __launch_bounds__(kBlock) k_p(int64_t n, const double *__restrict__ z,
-                                              double *__restrict__ p, const CgState *st) {
-    if (st->done) return;
-    const double beta = st->beta;
-    GRID_STRIDE(i, n) p[i] = z[i] + beta * p[i];
+    else {
+        st->beta = rz / st->rho;
+        st->rho = rz;
+    }
 }
 
 // partial of ||b - q||^2 (true residual)
@@ -317,48 +291,59 @@ std::atomic<uint64_t> g_uid{1};
 
 // Workspace: b, x, r, z, p, q in HBMC order, partial sums, the CG state,
 // the true-residual slot and the residual history.
+// Workspace: b, x, r, z, p (two, used in turn), q in HBMC order, partial
+// sums (per workgroup and per tile), the CG state, the true-residual slot
+// and the residual history.
 struct Work {
-    double *bb, *xb, *r, *z, *p, *q, *part, *resid, *hist;
+    double *bb, *xb, *r, *z, *p[2], *q, *part, *part_rr, *part_rz, *resid, *hist;
     CgState *st;
     int32_t hist_len;
 };
 
 constexpr int32_t kHistLen = 65536;
 
-size_t work_layout(int64_t n_pad, Work *w, void *base) {
-    const size_t vec = (size_t(n_pad) * sizeof(double) + 255) & ~size_t(255);
-    const size_t part = (size_t(2) * grid_for(n_pad) * sizeof(double) + 255) & ~size_t(255);
+size_t work_layout(int64_t n_pad, int64_t ntiles, Work *w, void *base) {
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const size_t vec = up(size_t(n_pad) * sizeof(double));
+    const size_t part = up(size_t(2) * grid_for(n_pad) * sizeof(double));
+    const size_t tp = up(size_t(ntiles) * sizeof(double));
     const size_t hist = size_t(kHistLen) * sizeof(double);
-    const size_t total = 6 * vec + part + 256 + 256 + hist;
+    const size_t total = 7 * vec + part + 2 * tp + 256 + 256 + hist;
     if (w && base) {
         auto *b = static_cast<uint8_t *>(base);
-        double **v[6] = {&w->bb, &w->xb, &w->r, &w->z, &w->p, &w->q};
-        for (int i = 0; i < 6; ++i) *v[i] = reinterpret_cast<double *>(b + i * vec);
-        w->part = reinterpret_cast<double *>(b + 6 * vec);
-        w->st = reinterpret_cast<CgState *>(b + 6 * vec + part);
-        w->resid = reinterpret_cast<double *>(b + 6 * vec + part + 256);
-        w->hist = reinterpret_cast<double *>(b + 6 * vec + part + 512);
+        double **v[7] = {&w->bb, &w->xb, &w->r, &w->z, &w->p[0], &w->p[1], &w->q};
+        for (int i = 0; i < 7; ++i) *v[i] = reinterpret_cast<double *>(b + i * vec);
+        size_t at = 7 * vec;
+        w->part = reinterpret_cast<double *>(b + at); at += part;
+        w->part_rr = reinterpret_cast<double *>(b + at); at += tp;
+        w->part_rz = reinterpret_cast<double *>(b + at); at += tp;
+        w->st = reinterpret_cast<CgState *>(b + at); at += 256;
+        w->resid = reinterpret_cast<double *>(b + at); at += 256;
+        w->hist = reinterpret_cast<double *>(b + at);
         w->hist_len = kHistLen;
     }
     return total;
 }
 
-// One CG iteration (everything after the first preconditioning step).
+// One CG iteration (everything after the first preconditioning step); the
+// direction is read from p[parity] and written to p[1 - parity].
+//   q = A p, p = z + beta p_old  |  alpha = rho / (p, q)  |
+//   x += alpha p, r -= alpha q, z = M^-1 r, partials of ||r||^2 and (r, z)  |
+//   stopping test, beta
 int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipStream_t s,
-                      bool history) {
+                      bool history, int parity) {
     const int64_t n = f->n_pad;
     const int g = grid_for(n);
-    hipLaunchKernelGGL(k_spmv_dot, dim3(g), dim3(kBlock), 0, s, m, w.p, w.q, w.part, w.st);
+    const int ntiles = int(f->tile_base[f->nc]);
+    double *p_old = w.p[parity], *p_new = w.p[1 - parity];
+    hipLaunchKernelGGL(k_spmv_dot_p, dim3(g), dim3(kBlock), 0, s, m, w.z, p_old, p_new, w.q, w.part, w.st);
     hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(kFin), 0, s, w.part, g, w.st);
-    hipLaunchKernelGGL(k_xr, dim3(g), dim3(kBlock), 0, s, n, w.p, w.q, w.xb, w.r, w.part, w.st);
-    hipLaunchKernelGGL(k_fin_rr, dim3(1), dim3(kFin), 0, s, w.part, g, w.st,
-                       history ? w.hist : nullptr, w.hist_len);
     HIP_TRY(hipGetLastError());
-    int st = apply_launch(f, w.r, w.z, s, &w.st->done);
+    const ApplyCg cg{w.xb, p_new, w.q, w.r, &w.st->alpha, w.part_rr, w.part_rz};
+    int st = apply_launch(f, w.r, w.z, s, &w.st->done, &cg);
     if (st) return st;
-    hipLaunchKernelGGL(k_rz, dim3(g), dim3(kBlock), 0, s, n, w.r, w.z, w.part, w.st);
-    hipLaunchKernelGGL(k_fin_beta, dim3(1), dim3(kFin), 0, s, w.part, g, w.st);
-    hipLaunchKernelGGL(k_p, dim3(g), dim3(kBlock), 0, s, n, w.z, w.p, w.st);
+    hipLaunchKernelGGL(k_fin_rr_beta, dim3(1), dim3(kFin), 0, s, w.part_rr, w.part_rz, ntiles, w.st,
+                       history ? w.hist : nullptr, w.hist_len);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -388,7 +373,7 @@ int get_graph(hbmc_factor_s *f, const hbmc_matrix_s *A, const Mat &m, const Work
     if (!cs) return fail(HBMC_EHIP, "cannot create a capture stream");
     HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int st = HBMC_OK;
-    for (int k = 0; k < iters && st == HBMC_OK; ++k) st = enqueue_iteration(f, m, w, cs, history);
+    for (int k = 0; k < iters && st == HBMC_OK; ++k) st = enqueue_iteration(f, m, w, cs, history, k & 1);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &graph);
     if (st) { if (graph) hipGraphDestroy(graph); return st; }
@@ -463,7 +448,7 @@ extern "C" int hbmc_from_hbmc(const hbmc_factor_t *f, const double *vb, double *
 extern "C" int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes) {
     if (!f || !bytes) return fail(HBMC_EINVAL, "null argument");
     if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
-    *bytes = work_layout(f->n_pad, nullptr, nullptr);
+    *bytes = work_layout(f->n_pad, f->tile_base[f->nc], nullptr, nullptr);
     return HBMC_OK;
 }
 
@@ -478,13 +463,16 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     if (A->n_pad != f->n_pad || A->n != f->n) return fail(HBMC_EINVAL, "matrix and factor sizes differ");
     if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
     if (maxit < 0 || !(tol >= 0.0)) return fail(HBMC_EINVAL, "bad tol or maxit");
-    if (work_bytes < work_layout(f->n_pad, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
+    const int64_t ntiles = f->tile_base[f->nc];
+    if (work_bytes < work_layout(f->n_pad, ntiles, nullptr, nullptr))
+        return fail(HBMC_EINVAL, "workspace too small");
     Work w{};
-    work_layout(f->n_pad, &w, work);
+    work_layout(f->n_pad, ntiles, &w, work);
     const bool x0_zero = opts && opts->x0_zero;
     const bool use_graph = opts && opts->use_graph;
     const bool history = opts && opts->record_history;
     int check = opts && opts->check_every > 0 ? opts->check_every : (use_graph ? 16 : 1);
+    if (use_graph) check = (check + 1) & ~1;   // graphs hold whole pairs of iterations
     auto s = static_cast<hipStream_t>(stream);
     const int64_t n = f->n_pad;
     const int g = grid_for(n);
@@ -507,18 +495,19 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     if (h.bb == 0.0) {
         hipLaunchKernelGGL(k_zero, dim3(g), dim3(kBlock), 0, s, n, w.xb);
     } else if (h.done == kRunning) {
-        int st = apply_launch(f, w.r, w.z, s, nullptr);
+        int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr);
         if (st) return st;
-        hipLaunchKernelGGL(k_init_p, dim3(g), dim3(kBlock), 0, s, n, w.r, w.z, w.p, w.part);
+        hipLaunchKernelGGL(k_init_p, dim3(g), dim3(kBlock), 0, s, n, w.r, w.z, w.p[0], w.part);
         hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(kFin), 0, s, w.part, g, w.st);
         HIP_TRY(hipGetLastError());
         hipGraphExec_t exec = nullptr;
         if (use_graph && (st = get_graph(f, A, m, w, work, check, history, &exec))) return st;
+        int parity = 0;
         while (h.done == kRunning) {
             if (use_graph) HIP_TRY(hipGraphLaunch(exec, s));
             else
-                for (int k = 0; k < check; ++k)
-                    if ((st = enqueue_iteration(f, m, w, s, history))) return st;
+                for (int k = 0; k < check; ++k, parity ^= 1)
+                    if ((st = enqueue_iteration(f, m, w, s, history, parity))) return st;
             HIP_TRY(hipMemcpyAsync(&h, w.st, sizeof h, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
         }
@@ -551,9 +540,11 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
 extern "C" int iccg_history(const void *work, size_t work_bytes, const hbmc_factor_t *f, double *hist,
                             int32_t count, void *stream) {
     if (!work || !f || !hist || count < 0) return fail(HBMC_EINVAL, "null argument");
-    if (work_bytes < work_layout(f->n_pad, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
+    const int64_t ntiles = f->tile_base[f->nc];
+    if (work_bytes < work_layout(f->n_pad, ntiles, nullptr, nullptr))
+        return fail(HBMC_EINVAL, "workspace too small");
     Work w{};
-    work_layout(f->n_pad, &w, const_cast<void *>(work));
+    work_layout(f->n_pad, ntiles, &w, const_cast<void *>(work));
     if (count > w.hist_len) return fail(HBMC_EINVAL, "history holds at most %d entries", w.hist_len);
     auto s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(hist, w.hist, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, s));

@@ -36,10 +36,23 @@ struct Sell {
     int64_t slots() const { return off.empty() ? 0 : off.back(); }
 };
 
+// CG work folded into the preconditioning step (see iccg_solve): before the
+// forward sweep reads r, each row gets x += alpha p, r -= alpha q, and
+// per-tile partial sums of ||r||^2 and (r, z) are written (tile order).
+struct ApplyCg {
+    double *x;
+    const double *p;
+    const double *q;
+    double *r;
+    const double *alpha;
+    double *part_rr;   // [tiles]
+    double *part_rz;   // [tiles]
+};
 // Enqueues z = M^-1 r on stream (a hipStream_t).  When done is not null the
 // kernels return at once while *done != 0 (used inside captured CG loops).
+// With cg, r is taken from cg->r after the update.
 int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *stream,
-                 const int32_t *done);
+                 const int32_t *done, const ApplyCg *cg);
 // Destroys the hipGraph executables cached by iccg_solve for this factor.
 void release_graphs(::hbmc_factor_s *f);
 // Unique id for each upload of a device image (keys the graph cache).

@@ -60,6 +60,20 @@ struct Tri {
     int64_t int_pad;
 };
 
+// CG work folded into the sweep (iccg_solve only; all null for ic0_apply):
+// the forward sweep of a color first applies x += alpha p, r -= alpha q to
+// the rows it reads and adds up ||r||^2; the sweeps that finish z add up
+// (r, z).  One partial sum per tile, in tile order.
+struct CgFuse {
+    double *x;
+    const double *p;
+    const double *q;
+    double *r;
+    const double *alpha;
+    double *part_rr;
+    double *part_rz;
+};
+
 struct Phase {
     int64_t row0, row1;   // rows of the color
     int64_t tile0;        // first global tile of the color
@@ -71,7 +85,14 @@ struct Phase {
     Tri f, b;
     const void *dinv;
     const int32_t *done;  // if set and *done != 0 the phase does nothing
+    CgFuse cg;
 };
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
 
 enum { kForward = 0, kBackward = 1, kLast = 2 };
 
@@ -193,7 +214,7 @@ __device__ inline void int_load(T (&v)[BS][MI], int32_t (&lp)[BS][MI], const Tri
 // registers.  MI == 0: any number, staged per wavefront in LDS when they fit
 // (each lane reads back only what it wrote, so no barrier is needed), else
 // read from global memory step by step.
-template <int BS, typename T, int MODE, int MI, int CH, int WAVES>
+template <int BS, typename T, int MODE, int MI, int CH, int WAVES, bool CG>
 __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double *__restrict__ r,
                                                           double *__restrict__ z) {
     if (ph.done && *ph.done) return;
@@ -220,11 +241,27 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
         if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, j);
     }
     T acc[BS], dv[BS];
+    double rn[BS];   // CG: the updated residual of the lane's rows
+    double rr = 0.0;
+    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
 #pragma unroll
     for (int l = 0; l < BS; ++l) {
         const int64_t row = rb + int64_t(l) * w;
-        acc[l] = T(MODE == kBackward ? z[row] : r[row]);
         if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
+        if (CG && MODE != kBackward) {
+            const double pv = ph.cg.p[row];
+            const double xn = ph.cg.x[row] + alpha * pv;
+            rn[l] = ph.cg.r[row] - alpha * ph.cg.q[row];
+            if (valid) { ph.cg.x[row] = xn; ph.cg.r[row] = rn[l]; rr += rn[l] * rn[l]; }
+            acc[l] = T(rn[l]);
+        } else {
+            acc[l] = T(MODE == kBackward ? z[row] : r[row]);
+            if (CG) rn[l] = ph.cg.r[row];   // backward: r of these rows is final
+        }
+    }
+    if (CG && MODE != kBackward) {
+        rr = wave_sum(rr);
+        if (j == 0) ph.cg.part_rr[ph.tile0 + tile] = rr;
     }
     ext_sweep<BS, CH, T>(acc, MODE == kBackward ? ph.b.ext : ph.f.ext, gt, j, z);
 
@@ -292,6 +329,13 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
             y[l] = a;
             if (valid) z[rb + int64_t(l) * w] = double(a);
         }
+        if (CG) {
+            double rz = 0.0;
+#pragma unroll
+            for (int l = 0; l < BS; ++l) rz += valid ? rn[l] * double(y[l]) : 0.0;
+            rz = wave_sum(rz);
+            if (j == 0) ph.cg.part_rz[ph.tile0 + tile] = rz;
+        }
     }
 }
 
@@ -313,9 +357,9 @@ Tri tri_of(const hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const S
                at<int32_t>(f->dev, o.int_lp), i.slots()};
 }
 
-template <int BS, typename T, int MI>
+template <int BS, typename T, int MI, bool CG>
 int launch_phases(const hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
-                  const int32_t *done) {
+                  const int32_t *done, const CgFuse &cg) {
     constexpr int CH = BS <= 4 ? 4 : (BS <= 8 ? 2 : 1);   // measured best on 128^3, bs 8
     constexpr int WAVES = MI > 0 ? 4 : 1;   // tiles per workgroup
     Phase ph{};
@@ -325,6 +369,7 @@ int launch_phases(const hbmc_factor_s *f, const double *r, double *z, hipStream_
     ph.b = tri_of(f, f->bwd, f->bext, f->bint);
     ph.dinv = at<void>(f->dev, f->off_dinv);
     ph.done = done;
+    ph.cg = cg;
     size_t lds = 0;
     if (MI == 0) {
         ph.lds_slots = std::max(std::max(f->max_int_slots_f, f->max_int_slots_b), 1);
@@ -346,33 +391,33 @@ int launch_phases(const hbmc_factor_s *f, const double *r, double *z, hipStream_
     const int nc = f->nc;
     int st;
     for (int c = 0; c + 1 < nc; ++c)
-        if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES>))) return st;
-    if ((st = run(nc - 1, k_sweep<BS, T, kLast, MI, CH, WAVES>))) return st;
+        if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG>))) return st;
+    if ((st = run(nc - 1, k_sweep<BS, T, kLast, MI, CH, WAVES, CG>))) return st;
     for (int c = nc - 2; c >= 0; --c)
-        if ((st = run(c, k_sweep<BS, T, kBackward, MI, CH, WAVES>))) return st;
+        if ((st = run(c, k_sweep<BS, T, kBackward, MI, CH, WAVES, CG>))) return st;
     return HBMC_OK;
 }
 
 // couplings per step inside a level-1 block: <= 1, <= 2, or more (LDS path)
-template <int BS, typename T>
+template <int BS, typename T, bool CG>
 int dispatch_mi(const hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
-                const int32_t *done) {
+                const int32_t *done, const CgFuse &cg) {
     const int mi = std::max(f->max_int_step_f, f->max_int_step_b);
-    if (mi <= 1) return launch_phases<BS, T, 1>(f, r, z, s, done);
-    if (BS <= 16 && mi <= 2) return launch_phases<BS, T, 2>(f, r, z, s, done);
-    return launch_phases<BS, T, 0>(f, r, z, s, done);
+    if (mi <= 1) return launch_phases<BS, T, 1, CG>(f, r, z, s, done, cg);
+    if (BS <= 16 && mi <= 2) return launch_phases<BS, T, 2, CG>(f, r, z, s, done, cg);
+    return launch_phases<BS, T, 0, CG>(f, r, z, s, done, cg);
 }
 
-template <typename T>
+template <typename T, bool CG>
 int dispatch_bs(const hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
-                const int32_t *done) {
+                const int32_t *done, const CgFuse &cg) {
     switch (f->bs) {
-        case 1: return dispatch_mi<1, T>(f, r, z, s, done);
-        case 2: return dispatch_mi<2, T>(f, r, z, s, done);
-        case 4: return dispatch_mi<4, T>(f, r, z, s, done);
-        case 8: return dispatch_mi<8, T>(f, r, z, s, done);
-        case 16: return dispatch_mi<16, T>(f, r, z, s, done);
-        case 32: return dispatch_mi<32, T>(f, r, z, s, done);
+        case 1: return dispatch_mi<1, T, CG>(f, r, z, s, done, cg);
+        case 2: return dispatch_mi<2, T, CG>(f, r, z, s, done, cg);
+        case 4: return dispatch_mi<4, T, CG>(f, r, z, s, done, cg);
+        case 8: return dispatch_mi<8, T, CG>(f, r, z, s, done, cg);
+        case 16: return dispatch_mi<16, T, CG>(f, r, z, s, done, cg);
+        case 32: return dispatch_mi<32, T, CG>(f, r, z, s, done, cg);
         default: return fail(HBMC_EINVAL, "bs = %d has no device kernel (1, 2, 4, 8, 16, 32)", f->bs);
     }
 }
@@ -380,10 +425,16 @@ int dispatch_bs(const hbmc_factor_s *f, const double *r, double *z, hipStream_t 
 }  // namespace
 
 int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void *stream,
-                       const int32_t *done) {
+                       const int32_t *done, const ApplyCg *cgp) {
     auto s = static_cast<hipStream_t>(stream);
-    return f->precision == HBMC_F64 ? dispatch_bs<double>(f, r, z, s, done)
-                                    : dispatch_bs<float>(f, r, z, s, done);
+    if (!cgp) {
+        const CgFuse none{};
+        return f->precision == HBMC_F64 ? dispatch_bs<double, false>(f, r, z, s, done, none)
+                                        : dispatch_bs<float, false>(f, r, z, s, done, none);
+    }
+    const CgFuse cg{cgp->x, cgp->p, cgp->q, cgp->r, cgp->alpha, cgp->part_rr, cgp->part_rz};
+    return f->precision == HBMC_F64 ? dispatch_bs<double, true>(f, cgp->r, z, s, done, cg)
+                                    : dispatch_bs<float, true>(f, cgp->r, z, s, done, cg);
 }
 
 // ---------------------------------------------------------------------------
@@ -412,5 +463,5 @@ extern "C" int ic0_apply(const hbmc_factor_t *f, const double *r, double *z, int
     if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
     if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
     if (r == z) return fail(HBMC_EINVAL, "z must not alias r");
-    return apply_launch(f, r, z, stream, nullptr);
+    return apply_launch(f, r, z, stream, nullptr, nullptr);
 }
