@@ -131,6 +131,21 @@ int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lower_rowptr,
 
 int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes);
 
+/* Kernel that runs the substitution phases (same results, different speed):
+ * HBMC_KERNEL_SWEEP -- one wavefront per 64 lanes walks all bs steps of its
+ *   level-1 blocks, loading every step's couplings itself (suits colors with
+ *   many level-1 blocks, e.g. large structured grids);
+ * HBMC_KERNEL_ROWS -- one workgroup of bs wavefronts per 64 lanes, one
+ *   wavefront per step for the couplings to other colors, then one
+ *   wavefront runs the chains (suits colors with few level-1 blocks or many
+ *   couplings per row; bs <= 16);
+ * HBMC_KERNEL_AUTO (default) -- ROWS when the colors average fewer than
+ *   1024 tiles of 64 lanes, else SWEEP. */
+#define HBMC_KERNEL_AUTO 0
+#define HBMC_KERNEL_SWEEP 1
+#define HBMC_KERNEL_ROWS 2
+int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel);
+
 /* Copies the factor's device image into dev[0, bytes) on stream (async).
  * dev must be 256-byte aligned and at least hbmc_factor_device_bytes long. */
 int hbmc_factor_upload(hbmc_factor_t *f, void *dev, size_t bytes, void *stream);

@@ -118,6 +118,7 @@ struct TriOffsets {
 
 struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
+    int32_t kernel = HBMC_KERNEL_AUTO;
     int64_t n_pad = 0;
     std::vector<int64_t> color_start;
     std::vector<int64_t> tile_base;    // [nc + 1] first global tile of each color

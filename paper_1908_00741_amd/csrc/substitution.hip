@@ -214,81 +214,52 @@ __device__ inline void int_load(T (&v)[BS][MI], int32_t (&lp)[BS][MI], const Tri
 // registers.  MI == 0: any number, staged per wavefront in LDS when they fit
 // (each lane reads back only what it wrote, so no barrier is needed), else
 // read from global memory step by step.
-template <int BS, typename T, int MODE, int MI, int CH, int WAVES, bool CG>
-__global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double *__restrict__ r,
-                                                          double *__restrict__ z) {
-    if (ph.done && *ph.done) return;
-    // the wavefront index is uniform: say so, so that everything indexed by
-    // the tile (slot offsets, strided bases and masks) uses scalar loads
-    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
-    const int j = threadIdx.x % kLanes;
-    const int64_t tile = int64_t(blockIdx.x) * WAVES + wave;
-    if (tile >= ph.ntile) return;
-    const int64_t lam = tile * kLanes + j;       // chain lane in the color
-    const bool valid = lam < ph.nlane;
-    const int w = ph.w;
-    // lanes past the color's last level-1 block (a partial last tile) work
-    // on the last lane's rows and store nothing
-    const int64_t lc = valid ? lam : ph.nlane - 1;
-    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
-    const int64_t gt = (ph.tile0 + tile) * BS;   // (tile, step 0) slot list
+// The bs-step chains of one lane (eqs. "y2-2", "y2-3"): forward (y) and/or
+// backward (z) sweeps inside the level-1 block, with acc holding each step's
+// right-hand side after the couplings to other colors.  Stores y (forward
+// phases) or z, and with CG the tile's (r, z) partial.  MI == 0: couplings
+// inside the block are staged into this wavefront's LDS region sv/sl (each
+// lane reads back only its own entries) when lds, else read in place.
+// Copies this lane's couplings inside the level-1 blocks of steps [l0, l1)
+// of the tile into an LDS region laid out like the slot lists (slot s of the
+// tile at s * 64 + lane).  Loads are issued in groups before the stores.
+template <typename T>
+__device__ inline void stage_steps(const Tri &E, int64_t gt, int l0, int l1, int j, T *sv, int32_t *sl) {
+    const int64_t ib = E.int_off[gt];
+    const int64_t s0 = E.int_off[gt + l0] - ib, s1 = E.int_off[gt + l1] - ib;
+    const T *val = static_cast<const T *>(E.int_val) + ib * kLanes;
+    const int32_t *lp = E.int_lp + ib * kLanes;
+#pragma unroll 4
+    for (int64_t s = s0; s < s1; ++s) {
+        sv[s * kLanes + j] = val[s * kLanes + j];
+        sl[s * kLanes + j] = lp[s * kLanes + j];
+    }
+}
 
+template <int BS, typename T, int MODE, int MI, bool CG>
+__device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], const double (&rn)[BS],
+                              const T (&fv)[BS][MI > 0 ? MI : 1], const int32_t (&fl)[BS][MI > 0 ? MI : 1],
+                              const T (&bv)[BS][MI > 0 ? MI : 1], const int32_t (&bl)[BS][MI > 0 ? MI : 1],
+                              T *sv, int32_t *sl, bool lds, int64_t gt, int j, int64_t rb, bool valid,
+                              double *__restrict__ z, int64_t gtile, T *svb = nullptr,
+                              int32_t *slb = nullptr) {
     constexpr int RM = MI > 0 ? MI : 1;
-    T fv[BS][RM], bv[BS][RM];
-    int32_t fl[BS][RM], bl[BS][RM];
-    if constexpr (MI > 0) {
-        if (MODE != kBackward) int_load<BS, RM, T>(fv, fl, ph.f, gt, j);
-        if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, j);
-    }
-    T acc[BS], dv[BS];
-    double rn[BS];   // CG: the updated residual of the lane's rows
-    double rr = 0.0;
-    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
-#pragma unroll
-    for (int l = 0; l < BS; ++l) {
-        const int64_t row = rb + int64_t(l) * w;
-        if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
-        if (CG && MODE != kBackward) {
-            const double pv = ph.cg.p[row];
-            const double xn = ph.cg.x[row] + alpha * pv;
-            rn[l] = ph.cg.r[row] - alpha * ph.cg.q[row];
-            if (valid) { ph.cg.x[row] = xn; ph.cg.r[row] = rn[l]; rr += rn[l] * rn[l]; }
-            acc[l] = T(rn[l]);
-        } else {
-            acc[l] = T(MODE == kBackward ? z[row] : r[row]);
-            if (CG) rn[l] = ph.cg.r[row];   // backward: r of these rows is final
-        }
-    }
-    if (CG && MODE != kBackward) {
-        rr = wave_sum(rr);
-        if (j == 0) ph.cg.part_rr[ph.tile0 + tile] = rr;
-    }
-    ext_sweep<BS, CH, T>(acc, MODE == kBackward ? ph.b.ext : ph.f.ext, gt, j, z);
-
-    // general path: this wavefront's couplings inside the level-1 blocks,
-    // in LDS when they fit (lds_slots > 0), else read in place
-    extern __shared__ __align__(16) unsigned char smem[];
-    const bool lds = ph.lds_slots > 0;
-    T *sv = reinterpret_cast<T *>(smem) + int64_t(wave) * ph.lds_slots * kLanes;
-    int32_t *sl = reinterpret_cast<int32_t *>(reinterpret_cast<T *>(smem) +
-                                              int64_t(WAVES) * ph.lds_slots * kLanes) +
-                  int64_t(wave) * ph.lds_slots * kLanes;
+    const int w = ph.w;
+    // svb: couplings already staged by the caller (forward at sv/sl,
+    // backward at svb/slb); else staged here, one direction at a time
+    const bool staged = svb != nullptr;
     auto stage = [&](const Tri &E) -> int64_t {
         const int64_t ib = E.int_off[gt];
-        if (!lds) return 0;
-        const int64_t n = E.int_off[gt + BS] - ib;
-        const T *val = static_cast<const T *>(E.int_val);
-        for (int64_t s = 0; s < n; ++s) {
-            sv[s * kLanes + j] = val[(ib + s) * kLanes + j];
-            sl[s * kLanes + j] = E.int_lp[(ib + s) * kLanes + j];
-        }
+        if (lds && !staged) stage_steps<T>(E, gt, 0, BS, j, sv, sl);
         return ib;
     };
     auto ival = [&](const Tri &E, int64_t s) -> T {
-        return lds ? sv[s * kLanes + j] : static_cast<const T *>(E.int_val)[s * kLanes + j];
+        if (!lds) return static_cast<const T *>(E.int_val)[(s + E.int_off[gt]) * kLanes + j];
+        return (staged && &E == &ph.b ? svb : sv)[s * kLanes + j];
     };
     auto ilp = [&](const Tri &E, int64_t s) -> int32_t {
-        return lds ? sl[s * kLanes + j] : E.int_lp[s * kLanes + j];
+        if (!lds) return E.int_lp[(s + E.int_off[gt]) * kLanes + j];
+        return (staged && &E == &ph.b ? slb : sl)[s * kLanes + j];
     };
 
     T y[BS];
@@ -334,9 +305,161 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
 #pragma unroll
             for (int l = 0; l < BS; ++l) rz += valid ? rn[l] * double(y[l]) : 0.0;
             rz = wave_sum(rz);
-            if (j == 0) ph.cg.part_rz[ph.tile0 + tile] = rz;
+            if (j == 0) ph.cg.part_rz[gtile] = rz;
         }
     }
+}
+
+// Loads the right-hand side of one row (r, or y for a backward phase); with
+// CG in a forward phase first applies x += alpha p, r -= alpha q to it.
+template <typename T, int MODE, bool CG>
+__device__ inline T row_rhs(const Phase &ph, const double *__restrict__ r, const double *__restrict__ z,
+                            int64_t row, bool valid, double alpha, double &rn, double &rr) {
+    if (CG && MODE != kBackward) {
+        const double pv = ph.cg.p[row];
+        const double xn = ph.cg.x[row] + alpha * pv;
+        rn = ph.cg.r[row] - alpha * ph.cg.q[row];
+        if (valid) { ph.cg.x[row] = xn; ph.cg.r[row] = rn; rr += rn * rn; }
+        return T(rn);
+    }
+    if (CG) rn = ph.cg.r[row];   // backward: r of these rows is final
+    return T(MODE == kBackward ? z[row] : r[row]);
+}
+
+// One color phase, one wavefront per tile (tile = blockIdx.x * WAVES + wave):
+// the wavefront loads the couplings of all bs steps itself, then runs the
+// chains.  Best when a color has many tiles.
+// MODE kForward: y of color c; kBackward: z of color c; kLast: y then z of
+// the last color.  z holds y of the colors whose forward sweep is done and
+// z of the colors whose backward sweep is done.
+// MI > 0: at most MI couplings per step inside a level-1 block, held in
+// registers.  MI == 0: any number, staged per wavefront in LDS when they fit.
+template <int BS, typename T, int MODE, int MI, int CH, int WAVES, bool CG>
+__global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double *__restrict__ r,
+                                                          double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    // the wavefront index is uniform: say so, so that everything indexed by
+    // the tile (slot offsets, strided bases and masks) uses scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
+    const int j = threadIdx.x % kLanes;
+    const int64_t tile = int64_t(blockIdx.x) * WAVES + wave;
+    if (tile >= ph.ntile) return;
+    const int64_t lam = tile * kLanes + j;       // chain lane in the color
+    const bool valid = lam < ph.nlane;
+    const int w = ph.w;
+    // lanes past the color's last level-1 block (a partial last tile) work
+    // on the last lane's rows and store nothing
+    const int64_t lc = valid ? lam : ph.nlane - 1;
+    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
+    const int64_t gt = (ph.tile0 + tile) * BS;   // (tile, step 0) slot list
+
+    constexpr int RM = MI > 0 ? MI : 1;
+    T fv[BS][RM], bv[BS][RM];
+    int32_t fl[BS][RM], bl[BS][RM];
+    if constexpr (MI > 0) {
+        if (MODE != kBackward) int_load<BS, RM, T>(fv, fl, ph.f, gt, j);
+        if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, j);
+    }
+    T acc[BS], dv[BS];
+    double rn[BS];   // CG: the updated residual of the lane's rows
+    double rr = 0.0;
+    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
+#pragma unroll
+    for (int l = 0; l < BS; ++l) {
+        const int64_t row = rb + int64_t(l) * w;
+        if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
+        acc[l] = row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn[l], rr);
+    }
+    if (CG && MODE != kBackward) {
+        rr = wave_sum(rr);
+        if (j == 0) ph.cg.part_rr[ph.tile0 + tile] = rr;
+    }
+    ext_sweep<BS, CH, T>(acc, MODE == kBackward ? ph.b.ext : ph.f.ext, gt, j, z);
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *sv = reinterpret_cast<T *>(smem) + int64_t(wave) * ph.lds_slots * kLanes;
+    int32_t *sl = reinterpret_cast<int32_t *>(reinterpret_cast<T *>(smem) +
+                                              int64_t(WAVES) * ph.lds_slots * kLanes) +
+                  int64_t(wave) * ph.lds_slots * kLanes;
+    chains<BS, T, MODE, MI, CG>(ph, acc, dv, rn, fv, fl, bv, bl, sv, sl, ph.lds_slots > 0, gt, j, rb,
+                                valid, z, ph.tile0 + tile);
+}
+
+// One color phase, one workgroup per tile with one wavefront per step: each
+// wavefront folds in the couplings to other colors of its step for the 64
+// lanes, the partial right-hand sides meet in LDS, and wavefront 0 runs the
+// chains.  Eight times the wavefronts of k_sweep, each with one step's loads:
+// best when a color has few tiles or its steps have many couplings.
+template <int BS, typename T, int MODE, int MI, int CH, bool CG>
+__global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph, const double *__restrict__ r,
+                                                      double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    const int l = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);   // this wave's step
+    const int j = threadIdx.x % kLanes;
+    const int64_t tile = blockIdx.x;
+    const int64_t lam = tile * kLanes + j;
+    const bool valid = lam < ph.nlane;
+    const int w = ph.w;
+    const int64_t lc = valid ? lam : ph.nlane - 1;
+    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
+    const int64_t gt = (ph.tile0 + tile) * BS;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *srn = reinterpret_cast<double *>(smem);          // [BS][64] (CG)
+    double *srr = srn + BS * kLanes;                         // [BS]     (CG)
+    T *sq = reinterpret_cast<T *>(srr + BS);                 // [BS][64]
+    T *sd = sq + BS * kLanes;                                // [BS][64]
+    T *svf = sd + BS * kLanes;                               // [lds_slots][64] (MI == 0)
+    T *svb = svf + ph.lds_slots * kLanes;                    // [lds_slots][64]
+    int32_t *slf = reinterpret_cast<int32_t *>(svb + ph.lds_slots * kLanes);
+    int32_t *slb = slf + ph.lds_slots * kLanes;
+
+    constexpr int RM = MI > 0 ? MI : 1;
+    T fv[BS][RM], bv[BS][RM];
+    int32_t fl[BS][RM], bl[BS][RM];
+    if constexpr (MI > 0) {
+        if (l == 0) {
+            if (MODE != kBackward) int_load<BS, RM, T>(fv, fl, ph.f, gt, j);
+            if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, j);
+        }
+    }
+    const int64_t row = rb + int64_t(l) * w;
+    double rn1 = 0.0, rr = 0.0;
+    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
+    T acc1[1] = {row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn1, rr)};
+    if (MODE != kBackward) sd[l * kLanes + j] = static_cast<const T *>(ph.dinv)[row];
+    if (MI == 0 && ph.lds_slots > 0) {   // this step's couplings inside the block
+        if (MODE != kBackward) stage_steps<T>(ph.f, gt, l, l + 1, j, svf, slf);
+        if (MODE != kForward) stage_steps<T>(ph.b, gt, l, l + 1, j, svb, slb);
+    }
+    ext_sweep<1, CH, T>(acc1, MODE == kBackward ? ph.b.ext : ph.f.ext, gt + l, j, z);
+    sq[l * kLanes + j] = acc1[0];
+    if (CG) {
+        srn[l * kLanes + j] = rn1;
+        if (MODE != kBackward) {
+            rr = wave_sum(rr);
+            if (j == 0) srr[l] = rr;
+        }
+    }
+    __syncthreads();
+    if (l != 0) return;
+
+    T acc[BS], dv[BS];
+    double rn[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        acc[k] = sq[k * kLanes + j];
+        dv[k] = MODE != kBackward ? sd[k * kLanes + j] : T(1);
+        rn[k] = CG ? srn[k * kLanes + j] : 0.0;
+    }
+    if (CG && MODE != kBackward && j == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < BS; ++k) t += srr[k];
+        ph.cg.part_rr[ph.tile0 + tile] = t;
+    }
+    chains<BS, T, MODE, MI, CG>(ph, acc, dv, rn, fv, fl, bv, bl, svf, slf, ph.lds_slots > 0, gt, j, rb,
+                                valid, z, ph.tile0 + tile, svb, slb);
 }
 
 // ---------------------------------------------------------------------------
@@ -357,11 +480,24 @@ Tri tri_of(const hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const S
                at<int32_t>(f->dev, o.int_lp), i.slots()};
 }
 
+// Which kernel runs the phases: one wavefront per tile (k_sweep) or one
+// workgroup of bs wavefronts per tile (k_rows).  Automatic choice: k_rows
+// when the colors have few tiles on average (fewer than 1024: a phase would
+// not fill the chip with one wavefront per tile).
+bool use_rows(const hbmc_factor_s *f, int bs) {
+    if (bs > 16) return false;                      // bs wavefronts per workgroup
+    if (f->kernel == HBMC_KERNEL_SWEEP) return false;
+    if (f->kernel == HBMC_KERNEL_ROWS) return true;
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc);
+}
+
 template <int BS, typename T, int MI, bool CG>
 int launch_phases(const hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
                   const int32_t *done, const CgFuse &cg) {
     constexpr int CH = BS <= 4 ? 4 : (BS <= 8 ? 2 : 1);   // measured best on 128^3, bs 8
-    constexpr int WAVES = MI > 0 ? 4 : 1;   // tiles per workgroup
+    constexpr int WAVES = MI > 0 ? 4 : 1;                 // k_sweep: tiles per workgroup
+    constexpr int CHR = 16;                               // k_rows: slots per chunk
+    const bool rows = use_rows(f, BS);
     Phase ph{};
     ph.w = f->w;
     ph.lw = __builtin_ctz(unsigned(f->w));
@@ -370,31 +506,45 @@ int launch_phases(const hbmc_factor_s *f, const double *r, double *z, hipStream_
     ph.dinv = at<void>(f->dev, f->off_dinv);
     ph.done = done;
     ph.cg = cg;
+    const size_t tw = sizeof(T) + sizeof(int32_t);
     size_t lds = 0;
+    ph.lds_slots = 0;
     if (MI == 0) {
         ph.lds_slots = std::max(std::max(f->max_int_slots_f, f->max_int_slots_b), 1);
-        lds = size_t(WAVES) * ph.lds_slots * kLanes * (sizeof(T) + sizeof(int32_t));
-        if (lds > kMaxLds) { ph.lds_slots = 0; lds = 0; }
+        const size_t per = size_t(ph.lds_slots) * kLanes * tw;
+        if ((rows ? 2 * per + size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS : WAVES * per) > kMaxLds)
+            ph.lds_slots = 0;
     }
-    auto run = [&](int c, auto kernel) -> int {
+    if (rows)
+        lds = size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + 2 * size_t(ph.lds_slots) * kLanes * tw;
+    else
+        lds = size_t(WAVES) * ph.lds_slots * kLanes * tw;
+    auto run = [&](int c, auto sweep, auto rowk) -> int {
         ph.row0 = f->color_start[c];
         ph.row1 = f->color_start[c + 1];
         ph.tile0 = f->tile_base[c];
         ph.ntile = f->tile_base[c + 1] - f->tile_base[c];
         ph.nlane = (ph.row1 - ph.row0) / BS;
         if (ph.ntile == 0) return HBMC_OK;
-        const unsigned grid = unsigned((ph.ntile + WAVES - 1) / WAVES);
-        hipLaunchKernelGGL(kernel, dim3(grid), dim3(WAVES * kLanes), lds, s, ph, r, z);
+        if (rows) {
+            hipLaunchKernelGGL(rowk, dim3(unsigned(ph.ntile)), dim3(BS * kLanes), lds, s, ph, r, z);
+        } else {
+            const unsigned grid = unsigned((ph.ntile + WAVES - 1) / WAVES);
+            hipLaunchKernelGGL(sweep, dim3(grid), dim3(WAVES * kLanes), lds, s, ph, r, z);
+        }
         HIP_TRY(hipGetLastError());
         return HBMC_OK;
     };
     const int nc = f->nc;
     int st;
     for (int c = 0; c + 1 < nc; ++c)
-        if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG>))) return st;
-    if ((st = run(nc - 1, k_sweep<BS, T, kLast, MI, CH, WAVES, CG>))) return st;
+        if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG>,
+                      k_rows<BS, T, kForward, MI, CHR, CG>))) return st;
+    if ((st = run(nc - 1, k_sweep<BS, T, kLast, MI, CH, WAVES, CG>,
+                  k_rows<BS, T, kLast, MI, CHR, CG>))) return st;
     for (int c = nc - 2; c >= 0; --c)
-        if ((st = run(c, k_sweep<BS, T, kBackward, MI, CH, WAVES, CG>))) return st;
+        if ((st = run(c, k_sweep<BS, T, kBackward, MI, CH, WAVES, CG>,
+                      k_rows<BS, T, kBackward, MI, CHR, CG>))) return st;
     return HBMC_OK;
 }
 
@@ -455,6 +605,15 @@ extern "C" int hbmc_factor_upload(hbmc_factor_t *f, void *dev, size_t bytes, voi
     f->dev = dev;
     f->dev_bytes = bytes;
     f->uid = next_uid();
+    return HBMC_OK;
+}
+
+extern "C" int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel) {
+    if (!f) return fail(HBMC_EINVAL, "null handle");
+    if (kernel != HBMC_KERNEL_AUTO && kernel != HBMC_KERNEL_SWEEP && kernel != HBMC_KERNEL_ROWS)
+        return fail(HBMC_EINVAL, "unknown kernel %d", kernel);
+    f->kernel = kernel;
+    release_graphs(f);
     return HBMC_OK;
 }
 

@@ -19,12 +19,13 @@ LIB_PATH = os.path.join(PKG, "libhbmc.so")
 HBMC_OK, HBMC_EINVAL, HBMC_ENOTSYM, HBMC_EDIAG, HBMC_EBREAKDOWN = 0, -1, -2, -3, -4
 HBMC_EHIP, HBMC_ENOMEM, HBMC_ENOTREADY, HBMC_ENOCONV = -5, -6, -7, 1
 HBMC_F64, HBMC_F32 = 0, 1
+HBMC_KERNEL_AUTO, HBMC_KERNEL_SWEEP, HBMC_KERNEL_ROWS = 0, 1, 2
 
 # every symbol include/hbmc.h declares
 SYMBOLS = (
     "hbmc_last_error", "hbmc_order", "hbmc_order_info", "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
-    "hbmc_factor_upload", "hbmc_factor_destroy", "ic0_apply", "hbmc_matrix_create",
+    "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
 )
@@ -74,6 +75,7 @@ def lib():
         L.hbmc_factor_export.argtypes = [P, P, P, P, P, P]
         L.hbmc_factor_device_bytes.argtypes = [P, P]
         L.hbmc_factor_upload.argtypes = [P, P, sz, P]
+        L.hbmc_factor_set_kernel.argtypes = [P, i32]
         L.hbmc_factor_destroy.argtypes = [P]
         L.hbmc_factor_destroy.restype = None
         L.ic0_apply.argtypes = [P, P, P, i32, P]
@@ -182,6 +184,10 @@ class Factor:
         b = C.c_size_t(0)
         _check("hbmc_factor_device_bytes", lib().hbmc_factor_device_bytes(self._h, C.byref(b)))
         return b.value
+
+    def set_kernel(self, kernel: int):
+        _check("hbmc_factor_set_kernel", lib().hbmc_factor_set_kernel(self._h, int(kernel)))
+        return self
 
     def upload(self, device="cuda", stream=None):
         import torch
@@ -341,9 +347,9 @@ class Solver:
 
     @staticmethod
     def setup(A, bs: int, w: int, precision: int = HBMC_F64, shift: float = 0.0,
-              device="cuda") -> "Solver":
+              device="cuda", kernel: int = HBMC_KERNEL_AUTO) -> "Solver":
         o = hbmc_order(A, bs, w)
-        f = ic0_factor(o, A, precision, shift).upload(device)
+        f = ic0_factor(o, A, precision, shift).set_kernel(kernel).upload(device)
         m = hbmc_matrix_create(o, A).upload(device)
         return Solver(o, f, m)
 

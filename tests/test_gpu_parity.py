@@ -54,10 +54,14 @@ APPLY_CASES = [
 ]
 
 
-def _apply_case(torch, orc, A, bs, w, precision):
+KERNELS = [hbmc.HBMC_KERNEL_SWEEP, hbmc.HBMC_KERNEL_ROWS]
+KIDS = ["sweep", "rows"]
+
+
+def _apply_case(torch, orc, A, bs, w, precision, kernel=hbmc.HBMC_KERNEL_AUTO):
     s = orc.system(A, bs, w)
     o = hbmc.hbmc_order(A, bs, w)
-    f = hbmc.ic0_factor(o, A, precision).upload()
+    f = hbmc.ic0_factor(o, A, precision).set_kernel(kernel).upload()
     rng = np.random.default_rng(42)
     r = rng.uniform(-1, 1, s.ordr.n_pad)
     dummy = np.setdiff1d(np.arange(s.ordr.n_pad), s.ordr.perm)
@@ -68,20 +72,22 @@ def _apply_case(torch, orc, A, bs, w, precision):
     return z, zref, dummy
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KIDS)
 @pytest.mark.parametrize("name,make,bs,w", APPLY_CASES, ids=[c[0] for c in APPLY_CASES])
-def test_apply_f64(torch, orc, name, make, bs, w):
-    print(f"case {name}", flush=True)
-    z, zref, dummy = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F64)
+def test_apply_f64(torch, orc, name, make, bs, w, kernel):
+    print(f"case {name} kernel {kernel}", flush=True)
+    z, zref, dummy = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F64, kernel)
     scale = np.abs(zref).max()
     assert np.linalg.norm(z - zref) <= 1e-13 * np.linalg.norm(zref)
     assert np.abs(z - zref).max() <= 1e-12 * scale
     assert np.all(z[dummy] == 0.0)
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KIDS)
 @pytest.mark.parametrize("name,make,bs,w", APPLY_CASES[:6], ids=[c[0] for c in APPLY_CASES[:6]])
-def test_apply_f32(torch, orc, name, make, bs, w):
-    print(f"case {name}", flush=True)
-    z, zref, _ = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F32)
+def test_apply_f32(torch, orc, name, make, bs, w, kernel):
+    print(f"case {name} kernel {kernel}", flush=True)
+    z, zref, _ = _apply_case(torch, orc, make(), bs, w, hbmc.HBMC_F32, kernel)
     assert np.abs(z - zref).max() <= 1e-5 * np.abs(zref).max()
 
 
@@ -130,13 +136,14 @@ def _rhs(A, seed):
     return inputs.row_sums(A) if seed is None else inputs.uniform_rhs(A.n, seed)
 
 
+@pytest.mark.parametrize("kernel", KERNELS, ids=KIDS)
 @pytest.mark.parametrize("name,make,bs,w", SOLVE_CASES, ids=[c[0] for c in SOLVE_CASES])
-def test_solve_fixed_iterations(torch, orc, name, make, bs, w):
-    print(f"case {name}", flush=True)
+def test_solve_fixed_iterations(torch, orc, name, make, bs, w, kernel):
+    print(f"case {name} kernel {kernel}", flush=True)
     A, seed = make()
     b = _rhs(A, seed)
     s = orc.system(A, bs, w)
-    solver = hbmc.Solver.setup(A, bs, w)
+    solver = hbmc.Solver.setup(A, bs, w, kernel=kernel)
     for K, graph in ((1, True), (7, False), (30, True)):
         ref = s.solve(b, tol=0.0, maxit=K)
         x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K, use_graph=graph)
