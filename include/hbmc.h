@@ -93,8 +93,24 @@ typedef struct {
     int32_t n_colors;
     int32_t bs;
     int32_t w;
-    int32_t reserved;
+    int32_t n_systems;  /* independent systems (hbmc_order_batch), else 1   */
 } hbmc_order_info_t;
+
+/* hbmc_order_batch: nsys independent SPD systems given as one block-diagonal
+ * CSR; system s owns rows [sys_ptr[s], sys_ptr[s+1]) and may not couple
+ * outside them (HBMC_EINVAL otherwise).  Each system is ordered exactly as
+ * hbmc_order would order it alone; the union is laid out color by color,
+ * each color holding the systems' unknowns of that color one system after
+ * another, each system's part padded with dummy blocks to a multiple of
+ * lcm(64, 256 / gcd(256, bs)) BMC blocks: whole wavefronts of 64 lanes that
+ * also fill whole 256-row parts of the CG reductions.  sys_ptr: host,
+ * nsys + 1 entries, 0 = sys_ptr[0] < sys_ptr[1] < ... < sys_ptr[nsys] = n
+ * (HBMC_EINVAL otherwise); read during the call only.  Every later call (factor, apply,
+ * solve) then treats all systems at once: one launch per color phase, and
+ * iccg_solve runs an independent CG per system (own scalars, own stopping
+ * test, one stats entry per system). */
+int hbmc_order_batch(int32_t nsys, const int64_t *sys_ptr, int32_t n, const int64_t *rowptr,
+                     const int32_t *col, int32_t bs, int32_t w, hbmc_order_t **out);
 
 int hbmc_order_info(const hbmc_order_t *h, hbmc_order_info_t *info);
 
@@ -195,9 +211,11 @@ int hbmc_from_hbmc(const hbmc_factor_t *f, const double *v_hbmc, double *v, int3
  * device FP64 in the caller's numbering, [n][nrhs].  work: device scratch of
  * iccg_workspace_bytes(f, nrhs).  Synchronous: returns when x is written.
  * b = 0 gives x = 0 after 0 iterations.
- * Returns HBMC_OK, HBMC_ENOCONV (maxit reached for some right-hand side),
- * HBMC_EBREAKDOWN, or an error; per-RHS details go to stats[nrhs] if not
- * NULL.
+ * For a batch ordering (hbmc_order_batch) each system runs its own CG with
+ * its own stopping test; the call returns when all have stopped.
+ * Returns HBMC_OK, HBMC_ENOCONV (maxit reached for some system or
+ * right-hand side), HBMC_EBREAKDOWN, or an error; details go to
+ * stats[n_systems * nrhs] (system-major) if not NULL.
  */
 typedef struct {
     int32_t x0_zero;       /* 1: ignore x on input, start from 0              */
@@ -219,8 +237,8 @@ int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, 
                int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
                hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
 
-/* Residual history of the last iccg_solve that ran with record_history on
- * this workspace: hist[k] = ||r_k|| / ||b|| for k = 0..count-1 (k = 0 is the
+/* Residual history (of system 0 in a batch) of the last iccg_solve that ran
+ * with record_history on this workspace: hist[k] = ||r_k|| / ||b|| for k = 0..count-1 (k = 0 is the
  * initial residual), count <= 65536.  Synchronous copy to host memory. */
 int iccg_history(const void *work, size_t work_bytes, const hbmc_factor_t *f, double *hist,
                  int32_t count, void *stream);

@@ -11,6 +11,7 @@ is silent.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from dataclasses import dataclass
@@ -124,6 +125,58 @@ def order(A, bs: int, w: int) -> Ordering:
         raise OracleError("orc_hbmc_perm", st)
     return Ordering(n, bs, w, members, nblocks, block_of, color, nc.value, perm, cstart,
                     int(npad.value))
+
+
+@dataclass
+class BatchOrdering:
+    n: int
+    n_pad: int
+    ncolors: int
+    perm: np.ndarray         # [n] original -> batch HBMC index
+    color_start: np.ndarray  # [ncolors+1]
+    seg: np.ndarray          # [ncolors, nsys+1] rows of (color, system)
+    systems: list            # per-system Ordering
+
+
+def batch_unit(bs: int) -> int:
+    """Padding of a batch segment, in BMC blocks: whole groups of 64 blocks
+    (a wavefront of lanes) that also fill whole parts of 256 rows."""
+    return math.lcm(64, 256 // math.gcd(256, bs))
+
+
+def order_batch(mats, bs: int, w: int) -> BatchOrdering:
+    """Independent systems ordered together: each system is ordered alone
+    (blocking, coloring, HBMC reordering of Section 3); the union is laid out
+    color by color, and inside a color system after system, each system's
+    share of the color padded with dummy blocks to a multiple of
+    batch_unit(bs) BMC blocks.  Inside its segment a system's unknowns keep the offsets they
+    have from the start of that color in the system's own ordering (the
+    HBMC offset of the q-th block of a color depends only on q, bs and w)."""
+    subs = [order(A, bs, w) for A in mats]
+    nsys = len(subs)
+    nc = max(o.ncolors for o in subs)
+    counts = np.zeros((nc, nsys), np.int64)          # BMC blocks of (color, system)
+    for s, o in enumerate(subs):
+        counts[: o.ncolors, s] = np.bincount(o.color, minlength=o.ncolors)
+    unit = batch_unit(bs)
+    padded = (counts + unit - 1) // unit * unit * bs
+    seg = np.zeros((nc, nsys + 1), np.int64)
+    color_start = np.zeros(nc + 1, np.int64)
+    at = 0
+    for c in range(nc):
+        color_start[c] = at
+        for s in range(nsys):
+            seg[c, s] = at
+            at += padded[c, s]
+        seg[c, nsys] = at
+    color_start[nc] = at
+    perm = np.empty(sum(o.n for o in subs), np.int64)
+    first = 0
+    for s, o in enumerate(subs):
+        c_of = o.color[o.block_of]                   # color of each unknown
+        perm[first: first + o.n] = seg[c_of, s] + (o.perm - o.color_start[c_of])
+        first += o.n
+    return BatchOrdering(int(perm.size), int(at), nc, perm.astype(np.int32), color_start, seg, subs)
 
 
 @dataclass

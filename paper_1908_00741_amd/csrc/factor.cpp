@@ -209,6 +209,8 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         f->color_start = o->color_start;
         f->perm = o->perm;
         f->iperm = o->iperm;
+        f->nsys = o->nsys;
+        f->sys_ptr = o->sys_ptr;
         const Csr a = permute(*o, rowptr, col, val);
         st = ic0_rows(a, f->n_pad, shift, f->lrp, f->lcol, f->lval, f->d);
         if (st) { delete f; return st; }
@@ -329,6 +331,45 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         pack_lanes(fi, f->fint, f->max_int_slots_f, f->max_int_step_f);
         pack_lanes(bi, f->bint, f->max_int_slots_b, f->max_int_step_b);
 
+        // systems: each tile and each kPartRows-row part lies in one system
+        // (a single system trivially; batches pad every system's share of a
+        // color to whole tiles of kTileLanes lanes and whole parts)
+        {
+            const int nsys = f->nsys, nc = f->nc;
+            const int64_t ntiles = f->tile_base[nc];
+            const int64_t nparts = (n + kPartRows - 1) / kPartRows;
+            const int64_t trows = int64_t(kTileLanes) * bs;
+            auto sys_of_row = [&](int64_t row) -> int32_t {
+                if (nsys == 1) return 0;
+                int c = int(std::upper_bound(f->color_start.begin(), f->color_start.end(), row) -
+                            f->color_start.begin()) - 1;
+                const int64_t *sg = &o->seg[int64_t(c) * (nsys + 1)];
+                return int32_t(std::upper_bound(sg, sg + nsys + 1, row) - sg) - 1;
+            };
+            f->tile_sys.assign(ntiles, 0);
+            for (int c = 0; c < nc; ++c)
+                for (int64_t t = f->tile_base[c]; t < f->tile_base[c + 1]; ++t)
+                    f->tile_sys[t] = sys_of_row(f->color_start[c] + (t - f->tile_base[c]) * trows);
+            f->part_sys.assign(nparts, 0);
+            for (int64_t g = 0; g < nparts; ++g) f->part_sys[g] = sys_of_row(g * kPartRows);
+            // tile and part ranges of each (system, color); a tile or part
+            // that a color ends inside (one system) is counted with the color
+            // it starts in
+            f->sys_tiles.assign(int64_t(nsys) * nc * 2, 0);
+            f->sys_parts.assign(int64_t(nsys) * nc * 2, 0);
+            auto ceil_div = [](int64_t a, int64_t b) { return (a + b - 1) / b; };
+            for (int sy = 0; sy < nsys; ++sy)
+                for (int c = 0; c < nc; ++c) {
+                    const int64_t a = o->seg[int64_t(c) * (nsys + 1) + sy];
+                    const int64_t b = o->seg[int64_t(c) * (nsys + 1) + sy + 1];
+                    const int64_t k = (int64_t(sy) * nc + c) * 2;
+                    f->sys_tiles[k] = int32_t(f->tile_base[c] + ceil_div(a - f->color_start[c], trows));
+                    f->sys_tiles[k + 1] = int32_t(f->tile_base[c] + ceil_div(b - f->color_start[c], trows));
+                    f->sys_parts[k] = int32_t(ceil_div(a, kPartRows));
+                    f->sys_parts[k + 1] = int32_t(ceil_div(b, kPartRows));
+                }
+        }
+
         // device image
         auto &im = f->image;
         auto add_tri = [&](const Packed &e, const Sell &i, TriOffsets &t) {
@@ -340,6 +381,10 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         f->off_dinv = precision == HBMC_F64 ? im.add(dinv) : im.add(cast<float>(dinv));
         f->off_perm = im.add(f->perm);
         f->off_iperm = im.add(f->iperm);
+        f->off_tile_sys = im.add(f->tile_sys);
+        f->off_part_sys = im.add(f->part_sys);
+        f->off_sys_tiles = im.add(f->sys_tiles);
+        f->off_sys_parts = im.add(f->sys_parts);
         add_tri(f->fext, f->fint, f->fwd);
         add_tri(f->bext, f->bint, f->bwd);
         im.bytes.resize((im.bytes.size() + 255) & ~size_t(255));

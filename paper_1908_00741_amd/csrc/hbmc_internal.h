@@ -19,6 +19,9 @@ void clear_error();
 // block) x bs steps; each tile is one wavefront of gfx950.  The SpMV uses
 // sliced ELL with slices of kTileLanes consecutive rows.
 constexpr int kTileLanes = 64;
+// Rows per partial sum of the CG vector kernels (one workgroup of those
+// kernels); a batch keeps every part inside one system.
+constexpr int kPartRows = 256;
 // A base shared by at least this many lanes of a group makes a strided slot.
 constexpr int kMinStridedLanes = 48;
 
@@ -36,6 +39,14 @@ struct Sell {
     int64_t slots() const { return off.empty() ? 0 : off.back(); }
 };
 
+// CG state of one system, kept on the device between kernels.
+struct CgState {
+    double rho, alpha, beta, sigma, rr, bb, res, tol;
+    int32_t it, maxit, done, pad;
+};
+// Stop flag values
+enum { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIt = 3 };
+
 // CG work folded into the preconditioning step (see iccg_solve): before the
 // forward sweep reads r, each row gets x += alpha p, r -= alpha q, and
 // per-tile partial sums of ||r||^2 and (r, z) are written (tile order).
@@ -44,9 +55,10 @@ struct ApplyCg {
     const double *p;
     const double *q;
     double *r;
-    const double *alpha;
-    double *part_rr;   // [tiles]
-    double *part_rz;   // [tiles]
+    const CgState *st;          // [systems]: alpha, and done (tiles of done systems are skipped)
+    const int32_t *tile_sys;    // [tiles] system of each tile
+    double *part_rr;            // [tiles]
+    double *part_rz;            // [tiles]
 };
 // Enqueues z = M^-1 r on stream (a hipStream_t).  When done is not null the
 // kernels return at once while *done != 0 (used inside captured CG loops).
@@ -98,8 +110,10 @@ struct ImageBuilder {
 }  // namespace hbmc
 
 struct hbmc_order_s {
-    int32_t n = 0, bs = 0, w = 0, nc = 0;
+    int32_t n = 0, bs = 0, w = 0, nc = 0, nsys = 1;
     int64_t n_pad = 0, nblocks = 0;
+    std::vector<int64_t> sys_ptr;      // [nsys + 1] original rows of each system
+    std::vector<int64_t> seg;          // [nc * (nsys + 1)] HBMC rows of (color, system)
     std::vector<int32_t> perm;         // [n]    original -> HBMC
     std::vector<int32_t> iperm;        // [n_pad] HBMC -> original, -1 for dummies
     std::vector<int64_t> color_start;  // [nc + 1]
@@ -119,8 +133,14 @@ struct TriOffsets {
 struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int32_t kernel = HBMC_KERNEL_AUTO;
+    int32_t nsys = 1;
     int64_t n_pad = 0;
     std::vector<int64_t> color_start;
+    std::vector<int64_t> sys_ptr;      // [nsys + 1] original rows of each system
+    // systems: tile and 64-row group -> system; per system and color the
+    // ranges of its tiles and groups ([nsys][nc][2])
+    std::vector<int32_t> tile_sys, part_sys, sys_tiles, sys_parts;
+    size_t off_tile_sys = 0, off_part_sys = 0, off_sys_tiles = 0, off_sys_parts = 0;
     std::vector<int64_t> tile_base;    // [nc + 1] first global tile of each color
     std::vector<int32_t> perm, iperm;
     // FP64 factor: strictly lower L in CSR over HBMC indices, and d

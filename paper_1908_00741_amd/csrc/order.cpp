@@ -2,6 +2,7 @@
 // secondary reordering (Sections 4.1-4.3; blocking and coloring heuristics
 // of Section 5.1).
 #include <algorithm>
+#include <numeric>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -166,56 +167,121 @@ int32_t color_blocks(int32_t n, const int64_t *rp, const int32_t *ci, int32_t bs
 
 }  // namespace
 
-extern "C" int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
-                          int32_t w, hbmc_order_t **out) {
+// Orders nsys independent systems stored as one block-diagonal CSR (rows
+// [sys_ptr[s], sys_ptr[s+1]) of system s couple only among themselves).  Each
+// system is blocked, colored and reordered exactly as it would be alone; the
+// union is laid out color-major: color c holds, system after system, that
+// system's color-c unknowns.  With one system each color is padded to a
+// multiple of w blocks (Section 4.3); with several, each system's part of a
+// color is padded to a multiple of kTileLanes blocks, so that no tile of
+// kTileLanes lanes (one lane per BMC block) spans two systems.
+// unit: padding of each (color, system) segment, in BMC blocks
+static int order_systems(int32_t nsys, const int64_t *sys_ptr, int32_t n, const int64_t *rowptr,
+                         const int32_t *col, int32_t bs, int32_t w, bool batch, hbmc_order_t **out) {
     clear_error();
     if (!out) return fail(HBMC_EINVAL, "out is NULL");
     *out = nullptr;
     if (bs < 1 || bs > 32) return fail(HBMC_EINVAL, "bs must be in [1, 32] (got %d)", bs);
     if (w < 1 || w > kTileLanes || kTileLanes % w != 0)
         return fail(HBMC_EINVAL, "w must divide %d (got %d)", kTileLanes, w);
+    if (nsys < 1 || !sys_ptr) return fail(HBMC_EINVAL, "need at least one system");
+    if (sys_ptr[0] != 0 || sys_ptr[nsys] != n) return fail(HBMC_EINVAL, "system offsets must run from 0 to n");
+    for (int32_t s = 0; s < nsys; ++s)
+        if (sys_ptr[s + 1] <= sys_ptr[s]) return fail(HBMC_EINVAL, "system %d is empty", s);
     int st = check_csr(n, rowptr, col, nullptr);
     if (st) return st;
     try {
         auto *h = new hbmc_order_s;
-        h->n = n; h->bs = bs; h->w = w;
-        std::vector<int32_t> members, color;
-        build_blocks(n, rowptr, col, bs, members);
-        h->nc = color_blocks(n, rowptr, col, bs, members, color);
-        h->nblocks = int64_t(color.size());
-        // blocks of each color in ascending id
-        std::vector<std::vector<int32_t>> of_color(h->nc);
-        for (int64_t b = 0; b < h->nblocks; ++b) of_color[color[b]].push_back(int32_t(b));
-        // padding: every color to a multiple of w blocks, i.e. of bs*w unknowns
-        h->color_start.assign(h->nc + 1, 0);
-        for (int32_t c = 0; c < h->nc; ++c) {
-            const int64_t padded = (int64_t(of_color[c].size()) + w - 1) / w * w;
-            h->color_start[c + 1] = h->color_start[c] + padded * bs;
+        h->n = n; h->bs = bs; h->w = w; h->nsys = nsys;
+        h->sys_ptr.assign(sys_ptr, sys_ptr + nsys + 1);
+        // padding unit in blocks: w for one system (Section 3); in a batch,
+        // whole tiles of kTileLanes blocks that also fill whole parts of
+        // kPartRows rows, so that no tile and no part spans two systems
+        const int64_t unit = batch ? std::lcm<int64_t>(kTileLanes, kPartRows / std::gcd(kPartRows, bs)) : w;
+        // per system: blocks (global unknown ids) and their colors
+        std::vector<std::vector<int32_t>> members(nsys), color(nsys);
+        std::vector<int64_t> lrp;
+        std::vector<int32_t> lci;
+        h->nc = 0;
+        h->nblocks = 0;
+        for (int32_t s = 0; s < nsys; ++s) {
+            const int64_t a = sys_ptr[s], b = sys_ptr[s + 1];
+            const int32_t ns = int32_t(b - a);
+            lrp.assign(ns + 1, 0);
+            lci.clear();
+            for (int64_t i = a; i < b; ++i) {
+                for (int64_t p = rowptr[i]; p < rowptr[i + 1]; ++p) {
+                    if (col[p] < a || col[p] >= b) {
+                        delete h;
+                        return fail(HBMC_EINVAL, "row %lld of system %d couples outside it", (long long)i, s);
+                    }
+                    lci.push_back(int32_t(col[p] - a));
+                }
+                lrp[i - a + 1] = int64_t(lci.size());
+            }
+            build_blocks(ns, lrp.data(), lci.data(), bs, members[s]);
+            const int32_t nc = color_blocks(ns, lrp.data(), lci.data(), bs, members[s], color[s]);
+            for (auto &u : members[s]) u += int32_t(a);
+            h->nc = std::max(h->nc, nc);
+            h->nblocks += int64_t(color[s].size());
         }
-        h->n_pad = h->color_start[h->nc];
+        // segment of (color c, system s): rows seg[c * (nsys + 1) + s] ..
+        h->seg.assign(int64_t(h->nc) * (nsys + 1), 0);
+        h->color_start.assign(h->nc + 1, 0);
+        std::vector<std::vector<std::vector<int32_t>>> of_color(h->nc, std::vector<std::vector<int32_t>>(nsys));
+        for (int32_t s = 0; s < nsys; ++s)
+            for (int64_t b = 0; b < int64_t(color[s].size()); ++b) of_color[color[s][b]][s].push_back(int32_t(b));
+        int64_t at = 0;
+        for (int32_t c = 0; c < h->nc; ++c) {
+            h->color_start[c] = at;
+            for (int32_t s = 0; s < nsys; ++s) {
+                h->seg[int64_t(c) * (nsys + 1) + s] = at;
+                const int64_t padded = (int64_t(of_color[c][s].size()) + unit - 1) / unit * unit;
+                at += padded * bs;
+            }
+            h->seg[int64_t(c) * (nsys + 1) + nsys] = at;
+        }
+        h->color_start[h->nc] = at;
+        h->n_pad = at;
         if (h->n_pad > INT32_MAX) { delete h; return fail(HBMC_EINVAL, "n_pad exceeds int32"); }
         h->perm.assign(n, -1);
         h->iperm.assign(h->n_pad, -1);
-        // the q-th block of color c is BMC block m = q mod w of level-1 block
-        // k' = q / w; its j-th member goes to S_c + k' bs w + j w + m
-        for (int32_t c = 0; c < h->nc; ++c) {
-            const auto &list = of_color[c];
-            for (size_t q = 0; q < list.size(); ++q) {
-                const int64_t kp = int64_t(q) / w, m = int64_t(q) % w;
-                const int64_t first = int64_t(list[q]) * bs;
-                for (int32_t j = 0; j < bs && first + j < n; ++j) {
-                    const int64_t dst = h->color_start[c] + kp * bs * w + int64_t(j) * w + m;
-                    const int32_t u = members[first + j];
-                    h->perm[u] = int32_t(dst);
-                    h->iperm[dst] = u;
+        // the q-th block of (color c, system s) is BMC block m = q mod w of
+        // level-1 block k' = q / w of that segment; its j-th member goes to
+        // segment start + k' bs w + j w + m
+        for (int32_t c = 0; c < h->nc; ++c)
+            for (int32_t s = 0; s < nsys; ++s) {
+                const auto &list = of_color[c][s];
+                const int64_t s0 = h->seg[int64_t(c) * (nsys + 1) + s];
+                const int64_t ns = sys_ptr[s + 1] - sys_ptr[s];
+                for (size_t q = 0; q < list.size(); ++q) {
+                    const int64_t kp = int64_t(q) / w, m = int64_t(q) % w;
+                    const int64_t first = int64_t(list[q]) * bs;
+                    for (int32_t j = 0; j < bs && first + j < ns; ++j) {
+                        const int64_t dst = s0 + kp * bs * w + int64_t(j) * w + m;
+                        const int32_t u = members[s][first + j];
+                        h->perm[u] = int32_t(dst);
+                        h->iperm[dst] = u;
+                    }
                 }
             }
-        }
         *out = h;
         return HBMC_OK;
     } catch (const std::bad_alloc &) {
         return fail(HBMC_ENOMEM, "out of host memory in hbmc_order");
     }
+}
+
+extern "C" int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
+                          int32_t w, hbmc_order_t **out) {
+    const int64_t sys_ptr[2] = {0, n};
+    if (n < 1) return fail(HBMC_EINVAL, "n must be >= 1 (got %d)", n);
+    return order_systems(1, sys_ptr, n, rowptr, col, bs, w, false, out);
+}
+
+extern "C" int hbmc_order_batch(int32_t nsys, const int64_t *sys_ptr, int32_t n, const int64_t *rowptr,
+                                const int32_t *col, int32_t bs, int32_t w, hbmc_order_t **out) {
+    return order_systems(nsys, sys_ptr, n, rowptr, col, bs, w, true, out);
 }
 
 extern "C" int hbmc_order_info(const hbmc_order_t *h, hbmc_order_info_t *info) {
@@ -226,7 +292,7 @@ extern "C" int hbmc_order_info(const hbmc_order_t *h, hbmc_order_info_t *info) {
     info->n_colors = h->nc;
     info->bs = h->bs;
     info->w = h->w;
-    info->reserved = 0;
+    info->n_systems = h->nsys;
     return HBMC_OK;
 }
 

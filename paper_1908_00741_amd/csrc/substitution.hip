@@ -69,7 +69,8 @@ struct CgFuse {
     const double *p;
     const double *q;
     double *r;
-    const double *alpha;
+    const CgState *st;         // per system: alpha, done
+    const int32_t *tile_sys;   // system of each tile
     double *part_rr;
     double *part_rz;
 };
@@ -344,6 +345,8 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
     const int j = threadIdx.x % kLanes;
     const int64_t tile = int64_t(blockIdx.x) * WAVES + wave;
     if (tile >= ph.ntile) return;
+    const CgState *cs = CG ? &ph.cg.st[ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
+    if (CG && cs->done) return;                  // this tile's system has stopped
     const int64_t lam = tile * kLanes + j;       // chain lane in the color
     const bool valid = lam < ph.nlane;
     const int w = ph.w;
@@ -363,7 +366,7 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
     T acc[BS], dv[BS];
     double rn[BS];   // CG: the updated residual of the lane's rows
     double rr = 0.0;
-    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
+    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
 #pragma unroll
     for (int l = 0; l < BS; ++l) {
         const int64_t row = rb + int64_t(l) * w;
@@ -397,6 +400,8 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
     const int l = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);   // this wave's step
     const int j = threadIdx.x % kLanes;
     const int64_t tile = blockIdx.x;
+    const CgState *cs = CG ? &ph.cg.st[ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
+    if (CG && cs->done) return;                  // the whole workgroup: one tile
     const int64_t lam = tile * kLanes + j;
     const bool valid = lam < ph.nlane;
     const int w = ph.w;
@@ -425,7 +430,7 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
     }
     const int64_t row = rb + int64_t(l) * w;
     double rn1 = 0.0, rr = 0.0;
-    const double alpha = CG && MODE != kBackward ? *ph.cg.alpha : 0.0;
+    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
     T acc1[1] = {row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn1, rr)};
     if (MODE != kBackward) sd[l * kLanes + j] = static_cast<const T *>(ph.dinv)[row];
     if (MI == 0 && ph.lds_slots > 0) {   // this step's couplings inside the block
@@ -582,7 +587,7 @@ int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void 
         return f->precision == HBMC_F64 ? dispatch_bs<double, false>(f, r, z, s, done, none)
                                         : dispatch_bs<float, false>(f, r, z, s, done, none);
     }
-    const CgFuse cg{cgp->x, cgp->p, cgp->q, cgp->r, cgp->alpha, cgp->part_rr, cgp->part_rz};
+    const CgFuse cg{cgp->x, cgp->p, cgp->q, cgp->r, cgp->st, cgp->tile_sys, cgp->part_rr, cgp->part_rz};
     return f->precision == HBMC_F64 ? dispatch_bs<double, true>(f, cgp->r, z, s, done, cg)
                                     : dispatch_bs<float, true>(f, cgp->r, z, s, done, cg);
 }

@@ -23,7 +23,7 @@ HBMC_KERNEL_AUTO, HBMC_KERNEL_SWEEP, HBMC_KERNEL_ROWS = 0, 1, 2
 
 # every symbol include/hbmc.h declares
 SYMBOLS = (
-    "hbmc_last_error", "hbmc_order", "hbmc_order_info", "hbmc_order_perm",
+    "hbmc_last_error", "hbmc_order", "hbmc_order_batch", "hbmc_order_info", "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
     "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
@@ -40,7 +40,7 @@ class HbmcError(RuntimeError):
 class OrderInfo(C.Structure):
     _fields_ = [("n", C.c_int64), ("n_pad", C.c_int64), ("n_blocks", C.c_int64),
                 ("n_colors", C.c_int32), ("bs", C.c_int32), ("w", C.c_int32),
-                ("reserved", C.c_int32)]
+                ("n_systems", C.c_int32)]
 
 
 class SolveOpts(C.Structure):
@@ -67,6 +67,7 @@ def lib():
         P, i32, i64, f64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
         L.hbmc_last_error.restype = C.c_char_p
         L.hbmc_order.argtypes = [i32, P, P, i32, i32, P]
+        L.hbmc_order_batch.argtypes = [i32, P, i32, P, P, i32, i32, P]
         L.hbmc_order_info.argtypes = [P, P]
         L.hbmc_order_perm.argtypes = [P, P, P]
         L.hbmc_order_destroy.argtypes = [P]
@@ -129,6 +130,7 @@ class Order:
         _check("hbmc_order_info", lib().hbmc_order_info(self._h, C.byref(info)))
         self.n, self.n_pad, self.n_blocks = info.n, info.n_pad, info.n_blocks
         self.n_colors, self.bs, self.w = info.n_colors, info.bs, info.w
+        self.n_systems = info.n_systems
 
     @property
     def handle(self):
@@ -153,13 +155,24 @@ def hbmc_order(A, bs: int, w: int) -> Order:
     return Order(h, A)
 
 
+def hbmc_order_batch(A, sys_ptr, bs: int, w: int) -> Order:
+    """Batch of independent systems: A is block diagonal and system s owns rows
+    sys_ptr[s] .. sys_ptr[s + 1] - 1."""
+    rp, ci, _ = _csr_arrays(A)
+    sp = np.ascontiguousarray(sys_ptr, np.int64)
+    h = C.c_void_p()
+    _check("hbmc_order_batch", lib().hbmc_order_batch(len(sp) - 1, _ptr(sp), A.n, _ptr(rp), _ptr(ci),
+                                                      bs, w, C.byref(h)))
+    return Order(h, A)
+
+
 class Factor:
     """Handle of ic0_factor; ``upload()`` places it in device memory."""
 
     def __init__(self, handle, order: Order, precision: int):
         self._h = handle
         self.n, self.n_pad, self.bs, self.w = order.n, order.n_pad, order.bs, order.w
-        self.n_colors = order.n_colors
+        self.n_colors, self.n_systems = order.n_colors, order.n_systems
         self.precision = precision
         self.dev = None
 
@@ -313,7 +326,8 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
                nrhs: int = 1, x0_zero: bool | None = None, check_every: int = 0,
                use_graph: bool = True, history: bool = False, work=None, stream=None):
     """Solves A x = b (original numbering, device FP64).  Returns (x, stats),
-    or (x, stats, hist) with history=True."""
+    or (x, stats, hist) with history=True; stats is a list (system-major,
+    then right-hand side) unless there is one system and one right-hand side."""
     import torch
     _vec_check(b, f.n, nrhs, "b")
     if x is None:
@@ -325,7 +339,8 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
         work = workspace(f, nrhs, b.device)
     opts = SolveOpts(1 if x0_zero else 0, int(check_every), 1 if use_graph else 0,
                      1 if history else 0)
-    stats = (SolveStats * nrhs)()
+    nst = f.n_systems * nrhs
+    stats = (SolveStats * nst)()
     code = lib().iccg_solve(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
                             C.byref(opts), stats, _dptr(work), work.numel(), _stream(stream))
     _check("iccg_solve", code, ok=(HBMC_OK, HBMC_ENOCONV))
@@ -334,21 +349,22 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
         h = np.empty(out[0].iters + 1)
         _check("iccg_history", lib().iccg_history(_dptr(work), work.numel(), f.handle, _ptr(h),
                                                   len(h), _stream(stream)))
-        return x, (out[0] if nrhs == 1 else out), h
-    return x, (out[0] if nrhs == 1 else out)
+        return x, (out[0] if nst == 1 else out), h
+    return x, (out[0] if nst == 1 else out)
 
 
 @dataclass
 class Solver:
-    """Ordering, factor and matrix of one system, uploaded to the device."""
+    """Ordering, factor and matrix of one system (or of a batch of independent
+    systems, with sys_ptr), uploaded to the device."""
     order: Order
     factor: Factor
     matrix: Matrix
 
     @staticmethod
     def setup(A, bs: int, w: int, precision: int = HBMC_F64, shift: float = 0.0,
-              device="cuda", kernel: int = HBMC_KERNEL_AUTO) -> "Solver":
-        o = hbmc_order(A, bs, w)
+              device="cuda", kernel: int = HBMC_KERNEL_AUTO, sys_ptr=None) -> "Solver":
+        o = hbmc_order(A, bs, w) if sys_ptr is None else hbmc_order_batch(A, sys_ptr, bs, w)
         f = ic0_factor(o, A, precision, shift).set_kernel(kernel).upload(device)
         m = hbmc_matrix_create(o, A).upload(device)
         return Solver(o, f, m)

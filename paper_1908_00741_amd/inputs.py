@@ -256,3 +256,23 @@ def gaussian_sources_rhs(N: int, theta: np.ndarray) -> np.ndarray:
 def batch_sizes(count: int = 128, seed: int = 7, lo: int = 16, hi: int = 64) -> np.ndarray:
     """Edge lengths N_s ~ U{lo..hi} of a batch of Poisson systems."""
     return np.random.default_rng(seed).integers(lo, hi + 1, size=count)
+
+
+def block_diag(mats) -> tuple[CSR, np.ndarray]:
+    """One block-diagonal CSR holding independent systems one after another,
+    and sys_ptr (system s owns rows sys_ptr[s] .. sys_ptr[s + 1] - 1)."""
+    sizes = np.array([m.n for m in mats], np.int64)
+    sys_ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    rp = [np.zeros(1, np.int64)]
+    at = 0
+    for m in mats:
+        rp.append(np.asarray(m.rowptr[1:], np.int64) + at)
+        at += int(m.rowptr[-1])
+    col = np.concatenate([np.asarray(m.col, np.int64) + o for m, o in zip(mats, sys_ptr[:-1])])
+    val = np.concatenate([np.asarray(m.val, np.float64) for m in mats])
+    return CSR(int(sys_ptr[-1]), np.concatenate(rp), col.astype(np.int32), val), sys_ptr
+
+
+def poisson_batch(count: int = 128, seed: int = 7, lo: int = 16, hi: int = 64):
+    """The uneven batch: Poisson systems on N_s^3 grids, N_s ~ U{lo..hi}."""
+    return block_diag([poisson3d(int(N)) for N in batch_sizes(count, seed, lo, hi)])
