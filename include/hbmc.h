@@ -162,6 +162,14 @@ int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes);
 #define HBMC_KERNEL_ROWS 2
 int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel);
 
+/* Right-hand-side tile for nrhs > 1 (same results up to the order of the
+ * partial sums, different speed): nr right-hand sides per wavefront, which
+ * then covers 64/nr level-1-block lanes, nr lanes per lane of the factor
+ * sharing its loads.  nr in {4, 8, 16}, or 0 (default) for automatic: 4
+ * below eight right-hand sides, else 8.  HBMC_EINVAL for other values.
+ * With nrhs > 1 the SWEEP kernel runs. */
+int hbmc_factor_set_rhs_tile(hbmc_factor_t *f, int32_t nr);
+
 /* Copies the factor's device image into dev[0, bytes) on stream (async).
  * dev must be 256-byte aligned and at least hbmc_factor_device_bytes long. */
 int hbmc_factor_upload(hbmc_factor_t *f, void *dev, size_t bytes, void *stream);

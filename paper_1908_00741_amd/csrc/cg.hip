@@ -72,16 +72,16 @@ struct Sys {
     int32_t nc, nsys;
 };
 
-// Fixed-order total of one system's partials (one per part, or one per
+// Fixed-order total of one system's partials (one per part, or tmul per
 // tile), by one workgroup of kFin threads; valid in thread 0.  Each thread
 // issues kLoads independent loads before it adds them (in index order), so
 // that the latency of the partials' loads is paid once per kLoads, not once
 // per partial.
 constexpr int kLoads = 16;
-__device__ inline double sys_total(const double *part, const int32_t *ranges, int nc, int s) {
+__device__ inline double sys_total(const double *part, const int32_t *ranges, int nc, int s, int tmul) {
     double acc = 0.0;
     for (int c = 0; c < nc; ++c) {
-        const int a = ranges[(s * nc + c) * 2], b = ranges[(s * nc + c) * 2 + 1];
+        const int a = ranges[(s * nc + c) * 2] * tmul, b = ranges[(s * nc + c) * 2 + 1] * tmul;
         for (int i0 = a + int(threadIdx.x); i0 < b; i0 += kFin * kLoads) {
             double v[kLoads];
 #pragma unroll
@@ -94,7 +94,7 @@ __device__ inline double sys_total(const double *part, const int32_t *ranges, in
 }
 
 // Abar: diagonal plus off-diagonal couplings in 64-row groups of strided
-// and indexed slots (a wavefront is one group).
+// and indexed slots (a wavefront covers rows of one group).
 struct Mat {
     const double *diag;
     const int32_t *soff;
@@ -113,38 +113,62 @@ __device__ inline uint64_t readlane64(uint64_t v, int lane) {
     return (uint64_t(hi) << 32) | lo;
 }
 
-// Rows of the vector kernels: one thread per row, one part of kPartRows
-// rows per workgroup.  In the last part (n need not be a multiple of it) a
-// wavefront whose 64 rows all lie past n does no work; in the wavefront that
-// holds row n - 1 all 64 lanes stay active (the SpMV broadcasts slot
-// metadata from any lane), the lanes past n computing on row n - 1 and
+// Sum over the lanes j' of the wavefront with j' = j mod NR (the lanes of
+// one right-hand side).
+template <int NR>
+__device__ inline double rhs_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= NR; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Elements of the vector kernels.  Vectors are [n][K] (the K right-hand
+// sides of a row adjacent).  A workgroup covers one part of kPartRows rows
+// for NR right-hand sides (group blockIdx.y), in NR rounds m; in a round a
+// wavefront covers 64/NR consecutive rows of one 64-row group, lane j taking
+// row j / NR and right-hand side j % NR.  In the last part (n need not be a
+// multiple of it) a wavefront whose rows all lie past n does no work; in the
+// wavefront that holds row n - 1 all lanes stay active (the SpMV broadcasts
+// slot metadata from any lane), the lanes past n computing on row n - 1 and
 // storing nothing.  Every thread still reaches the workgroup's reduction.
-struct RowOf {
-    int64_t row;     // this thread's row
+struct Elem {
+    int64_t row;     // this lane's row
     int64_t rc;      // the row it reads (row, or n - 1 past the end)
-    int64_t g;       // its 64-row group (wave-uniform)
+    int64_t g;       // 64-row group (wave-uniform)
+    int64_t e;       // element index rc * K + q
+    int jc;          // row within the group
+    int q;           // right-hand side (clamped to K - 1)
     bool wave_on;    // the wavefront has rows below n
-    bool valid;      // row < n
+    bool valid;      // row < n and right-hand side < K
 };
-__device__ inline RowOf row_of(int64_t n) {
-    RowOf r;
-    r.row = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    r.g = __builtin_amdgcn_readfirstlane(int(r.row >> 6));
-    r.wave_on = r.g * kLanes < n;
-    r.valid = r.row < n;
-    r.rc = r.valid ? r.row : n - 1;
+template <int NR>
+__device__ inline Elem elem(int64_t n, int K, int m) {
+    if (NR == 1) K = 1;   // one right-hand side: compile-time stride
+    Elem r;
+    const int wave = threadIdx.x >> 6, j = threadIdx.x & 63;
+    const int64_t base = int64_t(blockIdx.x) * kPartRows + m * (kPartRows / NR) + wave * (kLanes / NR);
+    const int q0 = int(blockIdx.y) * NR + j % NR;
+    r.row = base + j / NR;
+    r.g = __builtin_amdgcn_readfirstlane(int(base >> 6));
+    r.jc = int(r.row & 63);
+    r.q = q0 < K ? q0 : K - 1;
+    r.wave_on = base < n;
+    r.valid = r.row < n && q0 < K;
+    r.rc = r.row < n ? r.row : n - 1;
+    r.e = r.rc * K + r.q;
     return r;
 }
 
-// One row of y = A x with x(i) given by an accessor; all 64 lanes of the
-// group must be active.  The group's strided-slot bases and masks (at most
-// 64) come in with one vector load, one slot per lane, and are broadcast
-// with readlane.
+// One row of y = A x for one right-hand side, x(i) given by an accessor of
+// element indices; all 64 lanes of the wavefront must be active.  The
+// group's strided-slot bases and masks (at most 64) come in with one vector
+// load, one slot per lane, and are broadcast with readlane.
 template <class X>
-__device__ inline double spmv_row_with(const Mat &m, X x, const RowOf &r) {
+__device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) {
     const int64_t g = r.g;
     const int lane = int(threadIdx.x & 63);
-    double acc = m.diag[r.rc] * x(r.rc);
+    const int jc = r.jc;
+    double acc = m.diag[r.rc] * x(r.e);
     const int32_t s0 = m.soff[g], ns = m.soff[g + 1] - s0;
     const int64_t ms = s0 + (lane < ns ? lane : 0);
     const int32_t mbase = m.sbase[ms];
@@ -152,66 +176,92 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const RowOf &r) {
 #pragma unroll 4
     for (int k = 0; k < ns; ++k) {
         const int32_t base = __builtin_amdgcn_readlane(mbase, k);
-        const bool on = (readlane64(mmask, k) >> lane) & 1;
-        const double v = m.sval[(s0 + k) * int64_t(kLanes) + lane];
-        const double xv = x(base + lane);
+        const bool on = (readlane64(mmask, k) >> jc) & 1;
+        const double v = m.sval[(s0 + k) * int64_t(kLanes) + jc];
+        const double xv = x((base + jc) * int64_t(K) + r.q);
         acc = on ? acc + v * xv : acc;
     }
 #pragma unroll 4
     for (int64_t s = m.ioff[g]; s < m.ioff[g + 1]; ++s) {
-        const int64_t e = s * kLanes + lane;
+        const int64_t e = s * kLanes + jc;
         const int32_t c = m.icol[e];
         const double v = m.ival[e];
-        const double xv = x(c >= 0 ? c : 0);
+        const double xv = x((c >= 0 ? c : 0) * int64_t(K) + r.q);
         acc = c >= 0 ? acc + v * xv : acc;
     }
     return acc;
 }
 
-__global__ void __launch_bounds__(kBlock) k_spmv(Mat m, const double *__restrict__ x,
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_spmv(Mat m, int K, const double *__restrict__ x,
                                                  double *__restrict__ y) {
-    const RowOf r = row_of(m.n);
-    if (!r.wave_on) return;
-    const double v = spmv_row_with(m, [=](int64_t i) { return x[i]; }, r);
-    if (r.valid) y[r.row] = v;
+    if (NR == 1) K = 1;
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(m.n, K, mm);
+        if (!r.wave_on) continue;
+        const double v = spmv_row_with(m, [=](int64_t i) { return x[i]; }, r, K);
+        if (r.valid) y[r.row * K + r.q] = v;
+    }
 }
 
-// the part's partial sum of a vector kernel (all threads of the workgroup)
-__device__ inline void store_part(double *part, double value) {
-    const double s = block_sum(value);
-    if (threadIdx.x == 0) part[blockIdx.x] = s;
+// The part's partial sum of each right-hand side of the workgroup's group:
+// part[q * np + part].  All threads of the workgroup call it.
+template <int NR>
+__device__ inline void store_part(double *part, int64_t np, int K, double v) {
+    __shared__ double sh[kBlock / kLanes][NR];
+    v = rhs_sum<NR>(v);
+    const int wave = threadIdx.x >> 6, j = threadIdx.x & 63;
+    if (j < NR) sh[wave][j] = v;
+    __syncthreads();
+    if (int(threadIdx.x) < NR) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < kBlock / kLanes; ++k) t += sh[k][threadIdx.x];
+        const int q = int(blockIdx.y) * NR + threadIdx.x;
+        if (q < K) part[q * np + blockIdx.x] = t;
+    }
+    __syncthreads();
 }
 
 // r = b - q; part partials of ||b||^2 and ||r||^2
-__global__ void __launch_bounds__(kBlock) k_init_r(int64_t n, const double *__restrict__ b,
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_init_r(int64_t n, int K, const double *__restrict__ b,
                                                    const double *__restrict__ q,
                                                    double *__restrict__ rv, double *part, int64_t np) {
-    const RowOf r = row_of(n);
+    if (NR == 1) K = 1;
     double sb = 0.0, sr = 0.0;
-    if (r.valid) {
-        const double ri = b[r.row] - q[r.row];
-        rv[r.row] = ri;
-        sb = b[r.row] * b[r.row];
-        sr = ri * ri;
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) {
+            const int64_t e = r.row * K + r.q;
+            const double ri = b[e] - q[e];
+            rv[e] = ri;
+            sb += b[e] * b[e];
+            sr += ri * ri;
+        }
     }
-    store_part(part, sb);
-    store_part(part + np, sr);
+    store_part<NR>(part, np, K, sb);
+    store_part<NR>(part + int64_t(K) * np, np, K, sr);
 }
 
-// one stopped system more; the last one raises the all-stopped flag
-__device__ inline void count_done(int32_t *ndone, int32_t *alldone, int nsys) {
-    if (atomicAdd(ndone, 1) + 1 == nsys) *alldone = 1;
+// one stopped (system, right-hand side) more; the last one raises the
+// all-stopped flag
+__device__ inline void count_done(int32_t *ndone, int32_t *alldone, int total) {
+    if (atomicAdd(ndone, 1) + 1 == total) *alldone = 1;
 }
 
-// per system: ||b||^2, ||r0||^2, the state, and whether it is already done
-__global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t np, Sys sys, CgState *st,
-                                                   double tol, int32_t maxit, double *hist,
+// per (system s, right-hand side q) = blockIdx.x = s * K + q: ||b||^2,
+// ||r0||^2, the state, and whether it is already done
+__global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t np, int K, Sys sys,
+                                                   CgState *st, double tol, int32_t maxit, double *hist,
                                                    int32_t *ndone, int32_t *alldone) {
-    const int s = blockIdx.x;
-    const double bb = sys_total(part, sys.parts, sys.nc, s);
-    const double rr = sys_total(part + np, sys.parts, sys.nc, s);
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    const double bb = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    const double rr = sys_total(part + (K + q) * np, sys.parts, sys.nc, s, 1);
     if (threadIdx.x) return;
-    CgState &c = st[s];
+    CgState &c = st[b];
     c.bb = bb;
     c.rr = rr;
     c.tol = tol;
@@ -220,92 +270,107 @@ __global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t n
     c.alpha = 0.0;
     c.beta = 0.0;
     c.res = bb > 0.0 ? sqrt(rr / bb) : 0.0;
-    if (hist && s == 0) hist[0] = c.res;
+    if (hist && b == 0) hist[0] = c.res;
     c.done = (bb == 0.0 || c.res < tol) ? kConverged : (maxit <= 0 ? kMaxIt : kRunning);
     if (!isfinite(c.res)) c.done = kBreakdown;
-    if (c.done) count_done(ndone, alldone, sys.nsys);
+    if (c.done) count_done(ndone, alldone, sys.nsys * K);
 }
 
 // p = z; part partials of (r, z)
-__global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, const double *__restrict__ rv,
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, int K, const double *__restrict__ rv,
                                                    const double *__restrict__ z,
-                                                   double *__restrict__ p, double *part) {
-    const RowOf r = row_of(n);
+                                                   double *__restrict__ p, double *part, int64_t np) {
+    if (NR == 1) K = 1;
     double s = 0.0;
-    if (r.valid) {
-        p[r.row] = z[r.row];
-        s = rv[r.row] * z[r.row];
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) {
+            const int64_t e = r.row * K + r.q;
+            p[e] = z[e];
+            s += rv[e] * z[e];
+        }
     }
-    store_part(part, s);
+    store_part<NR>(part, np, K, s);
 }
 
-__global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, Sys sys, CgState *st) {
-    const int s = blockIdx.x;
-    const double t = sys_total(part, sys.parts, sys.nc, s);
-    if (threadIdx.x == 0) { st[s].rho = t; st[s].beta = 0.0; }
+__global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, int64_t np, int K, Sys sys,
+                                                  CgState *st) {
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    if (threadIdx.x == 0) { st[b].rho = t; st[b].beta = 0.0; }
 }
 
 // p = z + beta p_old (formed on the fly, also at the columns the row
 // couples to), written to p_new; q = A p; part partials of (p, q)
-__global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, Sys sys, const double *__restrict__ z,
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, const double *__restrict__ z,
                                                        const double *__restrict__ p_old,
                                                        double *__restrict__ p_new,
-                                                       double *__restrict__ q, double *part,
+                                                       double *__restrict__ q, double *part, int64_t np,
                                                        const CgState *st, const int32_t *alldone) {
     if (*alldone) return;
-    const CgState &c = st[sys.part_sys[blockIdx.x]];
-    if (c.done) return;                       // workgroup-uniform: a part lies in one system
-    const RowOf r = row_of(m.n);
+    if (NR == 1) K = 1;
+    const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
+    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    const bool live = q0 < K && !c.done;          // a part lies in one system
+    if (NR == 1 && !live) return;                  // workgroup-uniform with one right-hand side
+    const double beta = c.beta;
+    auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
     double pq = 0.0;
-    if (r.wave_on) {
-        const double beta = c.beta;
-        auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
-        const double pi = pv(r.rc);
-        const double qi = spmv_row_with(m, pv, r);
-        if (r.valid) {
-            p_new[r.row] = pi;
-            q[r.row] = qi;
-            pq = pi * qi;
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(m.n, K, mm);
+        if (!r.wave_on || !__any(live)) continue;
+        const double pi = pv(r.e);
+        const double qi = spmv_row_with(m, pv, r, K);
+        if (r.valid && live) {
+            const int64_t e = r.row * K + r.q;
+            p_new[e] = pi;
+            q[e] = qi;
+            pq += pi * qi;
         }
     }
-    store_part(part, pq);
+    store_part<NR>(part, np, K, pq);
 }
 
 // sigma = (p, Ap); alpha = rho / sigma
-__global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, Sys sys, CgState *st,
-                                                    int32_t *ndone, int32_t *alldone) {
-    const int s = blockIdx.x;
-    CgState &c = st[s];
+__global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t np, int K, Sys sys,
+                                                    CgState *st, int32_t *ndone, int32_t *alldone) {
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    CgState &c = st[b];
     if (c.done) return;
-    const double sigma = sys_total(part, sys.parts, sys.nc, s);
+    const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
     if (threadIdx.x) return;
     c.sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         c.done = kBreakdown;
         c.it += 1;
-        count_done(ndone, alldone, sys.nsys);
+        count_done(ndone, alldone, sys.nsys * K);
         return;
     }
     c.alpha = c.rho / sigma;
 }
 
-// After the preconditioning step: ||r||^2 and (r, z) from the per-tile
-// partials; one more iteration done; stopping test ||r|| / ||b|| < tol;
-// then beta = rho' / rho, rho = rho' for the next direction.
+// After the preconditioning step: ||r||^2 and (r, z) from the partials per
+// (tile, sub-tile) (tmul sub-tiles per tile); one more iteration done;
+// stopping test ||r|| / ||b|| < tol; then beta = rho' / rho, rho = rho' for
+// the next direction.
 __global__ void __launch_bounds__(kFin) k_fin_rr_beta(const double *part_rr, const double *part_rz,
-                                                      Sys sys, CgState *st, double *hist,
-                                                      int32_t hist_len, int32_t *ndone,
-                                                      int32_t *alldone) {
-    const int s = blockIdx.x;
-    CgState &c = st[s];
+                                                      int64_t ptiles, int tmul, int K, Sys sys,
+                                                      CgState *st, double *hist, int32_t hist_len,
+                                                      int32_t *ndone, int32_t *alldone) {
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    CgState &c = st[b];
     if (c.done) return;
-    const double rr = sys_total(part_rr, sys.tiles, sys.nc, s);
-    const double rz = sys_total(part_rz, sys.tiles, sys.nc, s);
+    const double rr = sys_total(part_rr + q * ptiles, sys.tiles, sys.nc, s, tmul);
+    const double rz = sys_total(part_rz + q * ptiles, sys.tiles, sys.nc, s, tmul);
     if (threadIdx.x) return;
     c.rr = rr;
     c.it += 1;
     c.res = sqrt(rr / c.bb);
-    if (hist && s == 0 && c.it < hist_len) hist[c.it] = c.res;
+    if (hist && b == 0 && c.it < hist_len) hist[c.it] = c.res;
     if (!isfinite(c.res)) c.done = kBreakdown;
     else if (c.res < c.tol) c.done = kConverged;
     else if (c.it >= c.maxit) c.done = kMaxIt;
@@ -313,43 +378,57 @@ __global__ void __launch_bounds__(kFin) k_fin_rr_beta(const double *part_rr, con
         c.beta = rz / c.rho;
         c.rho = rz;
     }
-    if (c.done) count_done(ndone, alldone, sys.nsys);
+    if (c.done) count_done(ndone, alldone, sys.nsys * K);
 }
 
 // part partials of ||b - q||^2 (true residual)
-__global__ void __launch_bounds__(kBlock) k_resid(int64_t n, const double *__restrict__ b,
-                                                  const double *__restrict__ q, double *part) {
-    const RowOf r = row_of(n);
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_resid(int64_t n, int K, const double *__restrict__ b,
+                                                  const double *__restrict__ q, double *part, int64_t np) {
+    if (NR == 1) K = 1;
     double s = 0.0;
-    if (r.valid) { const double d = b[r.row] - q[r.row]; s = d * d; }
-    store_part(part, s);
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) { const int64_t e = r.row * K + r.q; const double d = b[e] - q[e]; s += d * d; }
+    }
+    store_part<NR>(part, np, K, s);
 }
 
-__global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, Sys sys, double *out) {
-    const int s = blockIdx.x;
-    const double t = sys_total(part, sys.parts, sys.nc, s);
-    if (threadIdx.x == 0) out[s] = t;
+__global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, int64_t np, int K, Sys sys,
+                                                    double *out) {
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    if (threadIdx.x == 0) out[b] = t;
 }
 
-__global__ void __launch_bounds__(kBlock) k_to_hbmc(int64_t n_pad, const int32_t *__restrict__ iperm,
+// element-wise kernels over [rows][K]
+__global__ void __launch_bounds__(kBlock) k_to_hbmc(int64_t n_pad, int K, const int32_t *__restrict__ iperm,
                                                     const double *__restrict__ v,
                                                     double *__restrict__ vb) {
-    const int64_t r = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (r < n_pad) { const int32_t i = iperm[r]; vb[r] = i >= 0 ? v[i] : 0.0; }
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n_pad * K) return;
+    const int64_t row = e / K;
+    const int32_t i = iperm[row];
+    vb[e] = i >= 0 ? v[int64_t(i) * K + (e - row * K)] : 0.0;
 }
 
-__global__ void __launch_bounds__(kBlock) k_from_hbmc(int64_t n, const int32_t *__restrict__ perm,
+__global__ void __launch_bounds__(kBlock) k_from_hbmc(int64_t n, int K, const int32_t *__restrict__ perm,
                                                       const double *__restrict__ vb,
                                                       double *__restrict__ v) {
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < n) v[i] = vb[perm[i]];
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n * K) return;
+    const int64_t i = e / K;
+    v[e] = vb[int64_t(perm[i]) * K + (e - i * K)];
 }
 
-// x = 0 on the rows of the systems whose right-hand side is zero
-__global__ void __launch_bounds__(kBlock) k_zero_b0(int64_t n, const int32_t *__restrict__ part_sys,
+// x = 0 for the (system, right-hand side) pairs whose right-hand side is zero
+__global__ void __launch_bounds__(kBlock) k_zero_b0(int64_t n_pad, int K, const int32_t *__restrict__ part_sys,
                                                     const CgState *st, double *__restrict__ x) {
-    const int64_t i = int64_t(blockIdx.x) * kBlock + threadIdx.x;
-    if (i < n && st[part_sys[blockIdx.x]].bb == 0.0) x[i] = 0.0;
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n_pad * K) return;
+    const int64_t row = e / K;
+    if (st[int64_t(part_sys[row / kPartRows]) * K + (e - row * K)].bb == 0.0) x[e] = 0.0;
 }
 
 __global__ void __launch_bounds__(kBlock) k_zero(int64_t n, double *__restrict__ v) {
@@ -360,8 +439,6 @@ __global__ void __launch_bounds__(kBlock) k_zero(int64_t n, double *__restrict__
 __global__ void k_zero_int(int32_t *a, int n) {
     if (int(threadIdx.x) < n) a[threadIdx.x] = 0;
 }
-
-inline int grid_for(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock - 1) / kBlock)); }
 
 template <class P>
 P *at(void *base, size_t off) {
@@ -383,33 +460,42 @@ Sys sys_of(const hbmc_factor_s *f) {
 
 std::atomic<uint64_t> g_uid{1};
 
-// Workspace: b, x, r, z, p (two, used in turn), q in HBMC order; partial
-// sums per part (two slots) and per tile (two); the CG state of each
-// system; the stopped-system counter and the all-stopped flag; the true
-// residuals; the residual history of system 0.
+// Workspace, for K right-hand sides: b, x, r, z, p (two, used in turn), q
+// in HBMC order ([n_pad][K]); partial sums per part (two slots) and per
+// (tile, sub-tile) (two); the CG state of each (system, right-hand side);
+// the stopped counter and the all-stopped flag; the true residuals; the
+// residual history of system 0, right-hand side 0.
 struct Work {
     double *bb, *xb, *r, *z, *p[2], *q, *part_g, *part_rr, *part_rz, *resid, *hist;
     CgState *st;
     int32_t *ndone, *alldone;
-    int64_t np;
+    int64_t np;        // parts
+    int64_t ptiles;    // tile partial slots per right-hand side
+    int32_t K, nr;     // right-hand sides; right-hand sides per wavefront
     int32_t hist_len;
 };
 
 constexpr int32_t kHistLen = 65536;
+constexpr int kMaxTile = 16;   // largest right-hand-side tile
 
-size_t work_layout(const hbmc_factor_s *f, Work *w, void *base) {
+// Byte layout of the workspace for K right-hand sides (tile partials sized
+// for the largest tile, so that the tile may change after allocation).
+size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t np = (f->n_pad + kPartRows - 1) / kPartRows;
-    const int64_t ntiles = f->tile_base[f->nc];
-    const size_t vec = up(size_t(f->n_pad) * sizeof(double));
-    const size_t pg = up(size_t(2) * np * sizeof(double));
-    const size_t tp = up(size_t(ntiles) * sizeof(double));
-    const size_t sts = up(size_t(f->nsys) * sizeof(CgState));
-    const size_t res = up(size_t(f->nsys) * sizeof(double));
+    const int64_t tmul = K == 1 ? 1 : kMaxTile;
+    const int64_t ptiles = f->tile_base[f->nc] * tmul;
+    const size_t vec = up(size_t(f->n_pad) * K * sizeof(double));
+    const size_t pg = up(size_t(2) * K * np * sizeof(double));
+    const size_t tp = up(size_t(ptiles) * K * sizeof(double));
+    const size_t sts = up(size_t(f->nsys) * K * sizeof(CgState));
+    const size_t res = up(size_t(f->nsys) * K * sizeof(double));
     const size_t hist = size_t(kHistLen) * sizeof(double);
-    const size_t total = 7 * vec + pg + 2 * tp + sts + 256 + res + hist;
+    const size_t total = hist + 7 * vec + pg + 2 * tp + sts + 256 + res;
     if (w && base) {
         auto *b = static_cast<uint8_t *>(base);
+        w->hist = reinterpret_cast<double *>(b);   // first: its place does not depend on K
+        b += hist;
         double **v[7] = {&w->bb, &w->xb, &w->r, &w->z, &w->p[0], &w->p[1], &w->q};
         for (int i = 0; i < 7; ++i) *v[i] = reinterpret_cast<double *>(b + i * vec);
         size_t a = 7 * vec;
@@ -419,13 +505,31 @@ size_t work_layout(const hbmc_factor_s *f, Work *w, void *base) {
         w->st = reinterpret_cast<CgState *>(b + a); a += sts;
         w->ndone = reinterpret_cast<int32_t *>(b + a);
         w->alldone = w->ndone + 1; a += 256;
-        w->resid = reinterpret_cast<double *>(b + a); a += res;
-        w->hist = reinterpret_cast<double *>(b + a);
+        w->resid = reinterpret_cast<double *>(b + a);
         w->hist_len = kHistLen;
         w->np = np;
+        w->K = K;
+        w->nr = rhs_tile(f, K);
+        w->ptiles = f->tile_base[f->nc] * w->nr;
     }
     return total;
 }
+
+// Launches a vector kernel template on the workgroups (parts of n_pad
+// rows, groups of NR right-hand sides): NR = 1 for one right-hand side, 4
+// for up to four, else 8.
+#define VEC_LAUNCH(kernel, n_pad, K, s, ...)                                                  \
+    do {                                                                                      \
+        const unsigned np_ = unsigned(((n_pad) + kPartRows - 1) / kPartRows);                 \
+        if ((K) == 1)                                                                         \
+            hipLaunchKernelGGL(kernel<1>, dim3(np_), dim3(kBlock), 0, s, __VA_ARGS__);        \
+        else if ((K) <= 4)                                                                    \
+            hipLaunchKernelGGL(kernel<4>, dim3(np_), dim3(kBlock), 0, s, __VA_ARGS__);        \
+        else                                                                                  \
+            hipLaunchKernelGGL(kernel<8>, dim3(np_, unsigned(((K) + 7) / 8)), dim3(kBlock), 0, \
+                               s, __VA_ARGS__);                                               \
+    } while (0)
+inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock - 1) / kBlock)); }
 
 // One CG iteration (everything after the first preconditioning step); the
 // direction is read from p[parity] and written to p[1 - parity].
@@ -434,20 +538,19 @@ size_t work_layout(const hbmc_factor_s *f, Work *w, void *base) {
 //   stopping test, beta
 int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipStream_t s,
                       bool history, int parity) {
-    const int g = grid_for(f->n_pad);
     const Sys sys = sys_of(f);
+    const int K = w.K;
+    const unsigned nst = unsigned(f->nsys) * K;
     double *p_old = w.p[parity], *p_new = w.p[1 - parity];
-    hipLaunchKernelGGL(k_spmv_dot_p, dim3(g), dim3(kBlock), 0, s, m, sys, w.z, p_old, p_new, w.q,
-                       w.part_g, w.st, w.alldone);
-    hipLaunchKernelGGL(k_fin_alpha, dim3(f->nsys), dim3(kFin), 0, s, w.part_g, sys, w.st, w.ndone,
+    VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+    hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st, w.ndone,
                        w.alldone);
     HIP_TRY(hipGetLastError());
-    const ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys),
-                     w.part_rr, w.part_rz};
-    int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg);
+    const ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz};
+    int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg, K);
     if (st) return st;
-    hipLaunchKernelGGL(k_fin_rr_beta, dim3(f->nsys), dim3(kFin), 0, s, w.part_rr, w.part_rz, sys, w.st,
-                       history ? w.hist : nullptr, w.hist_len, w.ndone, w.alldone);
+    hipLaunchKernelGGL(k_fin_rr_beta, dim3(nst), dim3(kFin), 0, s, w.part_rr, w.part_rz, w.ptiles, w.nr, K,
+                       sys, w.st, history ? w.hist : nullptr, w.hist_len, w.ndone, w.alldone);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -470,7 +573,8 @@ int get_graph(hbmc_factor_s *f, const hbmc_matrix_s *A, const Mat &m, const Work
               int iters, bool history, hipGraphExec_t *out) {
     const int32_t key = iters * (history ? -1 : 1);
     for (const auto &gph : f->graphs)
-        if (gph.matrix_uid == A->uid && gph.work == work && gph.iters == key) {
+        if (gph.matrix_uid == A->uid && gph.work == work && gph.iters == key && gph.K == w.K &&
+            gph.nr == w.nr) {
             *out = static_cast<hipGraphExec_t>(gph.exec);
             return HBMC_OK;
         }
@@ -487,7 +591,7 @@ int get_graph(hbmc_factor_s *f, const hbmc_matrix_s *A, const Mat &m, const Work
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
     hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(HBMC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
-    f->graphs.push_back({A->uid, work, key, exec});
+    f->graphs.push_back({A->uid, work, key, w.K, w.nr, exec});
     *out = exec;
     return HBMC_OK;
 }
@@ -495,7 +599,7 @@ int get_graph(hbmc_factor_s *f, const hbmc_matrix_s *A, const Mat &m, const Work
 int check_ready(const hbmc_factor_s *f, int32_t nrhs) {
     if (!f) return fail(HBMC_EINVAL, "null handle");
     if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
-    if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     return HBMC_OK;
 }
 
@@ -529,10 +633,10 @@ extern "C" int hbmc_matrix_upload(hbmc_matrix_t *m, void *dev, size_t bytes, voi
 extern "C" int hbmc_spmv(const hbmc_matrix_t *m, const double *x, double *y, int32_t nrhs, void *stream) {
     if (!m || !x || !y) return fail(HBMC_EINVAL, "null argument");
     if (!m->dev) return fail(HBMC_ENOTREADY, "matrix not uploaded");
-    if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     if (x == y) return fail(HBMC_EINVAL, "y must not alias x");
-    hipLaunchKernelGGL(k_spmv, dim3(grid_for(m->n_pad)), dim3(kBlock), 0,
-                       static_cast<hipStream_t>(stream), mat_of(m), x, y);
+    const int K = nrhs;
+    VEC_LAUNCH(k_spmv, m->n_pad, K, static_cast<hipStream_t>(stream), mat_of(m), K, x, y);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -541,8 +645,8 @@ extern "C" int hbmc_to_hbmc(const hbmc_factor_t *f, const double *v, double *vb,
     int st = check_ready(f, nrhs);
     if (st) return st;
     if (!v || !vb) return fail(HBMC_EINVAL, "null argument");
-    hipLaunchKernelGGL(k_to_hbmc, dim3(grid_for(f->n_pad)), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
-                       f->n_pad, at<int32_t>(f->dev, f->off_iperm), v, vb);
+    hipLaunchKernelGGL(k_to_hbmc, dim3(grid_elems(f->n_pad * nrhs)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), f->n_pad, nrhs, at<int32_t>(f->dev, f->off_iperm), v, vb);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -551,16 +655,17 @@ extern "C" int hbmc_from_hbmc(const hbmc_factor_t *f, const double *vb, double *
     int st = check_ready(f, nrhs);
     if (st) return st;
     if (!v || !vb) return fail(HBMC_EINVAL, "null argument");
-    hipLaunchKernelGGL(k_from_hbmc, dim3(grid_for(f->n)), dim3(kBlock), 0, static_cast<hipStream_t>(stream),
-                       int64_t(f->n), at<int32_t>(f->dev, f->off_perm), vb, v);
+    hipLaunchKernelGGL(k_from_hbmc, dim3(grid_elems(int64_t(f->n) * nrhs)), dim3(kBlock), 0,
+                       static_cast<hipStream_t>(stream), int64_t(f->n), nrhs, at<int32_t>(f->dev, f->off_perm),
+                       vb, v);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
 
 extern "C" int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes) {
     if (!f || !bytes) return fail(HBMC_EINVAL, "null argument");
-    if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
-    *bytes = work_layout(f, nullptr, nullptr);
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
+    *bytes = work_layout(f, nrhs, nullptr, nullptr);
     return HBMC_OK;
 }
 
@@ -573,11 +678,12 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
     if (!A->dev) return fail(HBMC_ENOTREADY, "matrix not uploaded");
     if (A->n_pad != f->n_pad || A->n != f->n) return fail(HBMC_EINVAL, "matrix and factor sizes differ");
-    if (nrhs != 1) return fail(HBMC_EINVAL, "nrhs = %d not supported", nrhs);
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     if (maxit < 0 || !(tol >= 0.0)) return fail(HBMC_EINVAL, "bad tol or maxit");
-    if (work_bytes < work_layout(f, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
+    const int K = nrhs;
+    if (work_bytes < work_layout(f, K, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
     Work w{};
-    work_layout(f, &w, work);
+    work_layout(f, K, &w, work);
     const bool x0_zero = opts && opts->x0_zero;
     const bool use_graph = opts && opts->use_graph;
     const bool history = opts && opts->record_history;
@@ -585,35 +691,36 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     if (use_graph) check = (check + 1) & ~1;   // graphs hold whole pairs of iterations
     auto s = static_cast<hipStream_t>(stream);
     const int64_t n = f->n_pad;
-    const int g = grid_for(n);
+    const int ge = grid_elems(n * K);
     const Mat m = mat_of(A);
     const Sys sys = sys_of(f);
+    const int32_t nst = f->nsys * K;
     const int32_t *iperm = at<int32_t>(f->dev, f->off_iperm);
     const int32_t *perm = at<int32_t>(f->dev, f->off_perm);
 
     hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, w.ndone, 2);
-    hipLaunchKernelGGL(k_to_hbmc, dim3(g), dim3(kBlock), 0, s, n, iperm, b, w.bb);
-    if (x0_zero) hipLaunchKernelGGL(k_zero, dim3(g), dim3(kBlock), 0, s, n, w.xb);
-    else hipLaunchKernelGGL(k_to_hbmc, dim3(g), dim3(kBlock), 0, s, n, iperm, x, w.xb);
-    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kBlock), 0, s, m, w.xb, w.q);
-    hipLaunchKernelGGL(k_init_r, dim3(g), dim3(kBlock), 0, s, n, w.bb, w.q, w.r, w.part_g, w.np);
-    hipLaunchKernelGGL(k_fin_init, dim3(f->nsys), dim3(kFin), 0, s, w.part_g, w.np, sys, w.st, tol, maxit,
+    hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, b, w.bb);
+    if (x0_zero) hipLaunchKernelGGL(k_zero, dim3(ge), dim3(kBlock), 0, s, n * K, w.xb);
+    else hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, x, w.xb);
+    VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
+    VEC_LAUNCH(k_init_r, n, K, s, n, K, w.bb, w.q, w.r, w.part_g, w.np);
+    hipLaunchKernelGGL(k_fin_init, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st, tol, maxit,
                        history ? w.hist : nullptr, w.ndone, w.alldone);
     HIP_TRY(hipGetLastError());
     int32_t hd[2] = {0, 0};
     HIP_TRY(hipMemcpyAsync(hd, w.ndone, sizeof hd, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
-    if (hd[0] < f->nsys) {
-        int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr);
+    if (hd[0] < nst) {
+        int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr, K);
         if (st) return st;
-        hipLaunchKernelGGL(k_init_p, dim3(g), dim3(kBlock), 0, s, n, w.r, w.z, w.p[0], w.part_g);
-        hipLaunchKernelGGL(k_fin_rho, dim3(f->nsys), dim3(kFin), 0, s, w.part_g, sys, w.st);
+        VEC_LAUNCH(k_init_p, n, K, s, n, K, w.r, w.z, w.p[0], w.part_g, w.np);
+        hipLaunchKernelGGL(k_fin_rho, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st);
         HIP_TRY(hipGetLastError());
         hipGraphExec_t exec = nullptr;
         if (use_graph && (st = get_graph(f, A, m, w, work, check, history, &exec))) return st;
         int parity = 0;
-        while (hd[0] < f->nsys) {
+        while (hd[0] < nst) {
             if (use_graph) HIP_TRY(hipGraphLaunch(exec, s));
             else
                 for (int k = 0; k < check; ++k, parity ^= 1)
@@ -622,21 +729,22 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
             HIP_TRY(hipStreamSynchronize(s));
         }
     }
-    // systems with b = 0 get x = 0; the solution back to the caller's
+    // pairs with b = 0 get x = 0; the solution back to the caller's
     // numbering; the true residuals
-    hipLaunchKernelGGL(k_zero_b0, dim3(g), dim3(kBlock), 0, s, n, sys.part_sys, w.st, w.xb);
-    hipLaunchKernelGGL(k_from_hbmc, dim3(grid_for(f->n)), dim3(kBlock), 0, s, int64_t(f->n), perm, w.xb, x);
-    hipLaunchKernelGGL(k_spmv, dim3(g), dim3(kBlock), 0, s, m, w.xb, w.q);
-    hipLaunchKernelGGL(k_resid, dim3(g), dim3(kBlock), 0, s, n, w.bb, w.q, w.part_g);
-    hipLaunchKernelGGL(k_fin_resid, dim3(f->nsys), dim3(kFin), 0, s, w.part_g, sys, w.resid);
+    hipLaunchKernelGGL(k_zero_b0, dim3(ge), dim3(kBlock), 0, s, n, K, sys.part_sys, w.st, w.xb);
+    hipLaunchKernelGGL(k_from_hbmc, dim3(grid_elems(int64_t(f->n) * K)), dim3(kBlock), 0, s, int64_t(f->n), K,
+                       perm, w.xb, x);
+    VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
+    VEC_LAUNCH(k_resid, n, K, s, n, K, w.bb, w.q, w.part_g, w.np);
+    hipLaunchKernelGGL(k_fin_resid, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.resid);
     HIP_TRY(hipGetLastError());
-    std::vector<CgState> hs(f->nsys);
-    std::vector<double> rt(f->nsys);
+    std::vector<CgState> hs(nst);
+    std::vector<double> rt(nst);
     HIP_TRY(hipMemcpyAsync(hs.data(), w.st, hs.size() * sizeof(CgState), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipMemcpyAsync(rt.data(), w.resid, rt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     int status = HBMC_OK;
-    for (int32_t k = 0; k < f->nsys; ++k) {
+    for (int32_t k = 0; k < nst; ++k) {
         const int sk = hs[k].done == kConverged ? HBMC_OK
                        : hs[k].done == kBreakdown ? HBMC_EBREAKDOWN : HBMC_ENOCONV;
         if (sk == HBMC_EBREAKDOWN) status = HBMC_EBREAKDOWN;
@@ -653,18 +761,17 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     return status;
 }
 
-// Residual history of system 0 from the last iccg_solve that ran with
-// record_history on this workspace: hist[k] = ||r_k|| / ||b||
-// (synchronous copy to host memory).
+// Residual history of system 0, right-hand side 0, from the last iccg_solve
+// that ran with record_history on this workspace: hist[k] = ||r_k|| / ||b||
+// (synchronous copy to host memory).  The history is at the start of the
+// workspace, whatever the number of right-hand sides.
 extern "C" int iccg_history(const void *work, size_t work_bytes, const hbmc_factor_t *f, double *hist,
                             int32_t count, void *stream) {
     if (!work || !f || !hist || count < 0) return fail(HBMC_EINVAL, "null argument");
-    if (work_bytes < work_layout(f, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
-    Work w{};
-    work_layout(f, &w, const_cast<void *>(work));
-    if (count > w.hist_len) return fail(HBMC_EINVAL, "history holds at most %d entries", w.hist_len);
+    if (count > kHistLen) return fail(HBMC_EINVAL, "history holds at most %d entries", kHistLen);
+    if (work_bytes < size_t(kHistLen) * sizeof(double)) return fail(HBMC_EINVAL, "workspace too small");
     auto s = static_cast<hipStream_t>(stream);
-    HIP_TRY(hipMemcpyAsync(hist, w.hist, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(hist, work, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     return HBMC_OK;
 }

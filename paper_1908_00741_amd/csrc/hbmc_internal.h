@@ -47,24 +47,28 @@ struct CgState {
 // Stop flag values
 enum { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIt = 3 };
 
-// CG work folded into the preconditioning step (see iccg_solve): before the
-// forward sweep reads r, each row gets x += alpha p, r -= alpha q, and
-// per-tile partial sums of ||r||^2 and (r, z) are written (tile order).
+// CG work folded into the preconditioning step (iccg_solve only): the
+// forward sweep of a color first applies x += alpha p, r -= alpha q to the
+// rows it reads and adds up ||r||^2; the sweeps that finish z add up (r, z).
+// Partial sums per (right-hand side, tile, sub-tile): [K][tiles * NR].
 struct ApplyCg {
     double *x;
     const double *p;
     const double *q;
     double *r;
-    const CgState *st;          // [systems]: alpha, and done (tiles of done systems are skipped)
+    const CgState *st;          // [systems][K]: alpha, and done (stopped ones are skipped)
     const int32_t *tile_sys;    // [tiles] system of each tile
-    double *part_rr;            // [tiles]
-    double *part_rz;            // [tiles]
+    double *part_rr;            // [K][tiles * NR]
+    double *part_rz;            // [K][tiles * NR]
 };
-// Enqueues z = M^-1 r on stream (a hipStream_t).  When done is not null the
-// kernels return at once while *done != 0 (used inside captured CG loops).
-// With cg, r is taken from cg->r after the update.
+// Enqueues z = M^-1 r for K right-hand sides ([n_pad][K]) on stream (a
+// hipStream_t).  When done is not null the kernels return at once while
+// *done != 0 (used inside captured CG loops).  With cg, r is taken from
+// cg->r after the update.
 int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *stream,
-                 const int32_t *done, const ApplyCg *cg);
+                 const int32_t *done, const ApplyCg *cg, int K);
+// Right-hand sides per wavefront (NR) used for K right-hand sides.
+int rhs_tile(const ::hbmc_factor_s *f, int K);
 // Destroys the hipGraph executables cached by iccg_solve for this factor.
 void release_graphs(::hbmc_factor_s *f);
 // Unique id for each upload of a device image (keys the graph cache).
@@ -133,6 +137,7 @@ struct TriOffsets {
 struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int32_t kernel = HBMC_KERNEL_AUTO;
+    int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;
     int64_t n_pad = 0;
     std::vector<int64_t> color_start;
@@ -159,11 +164,13 @@ struct hbmc_factor_s {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     uint64_t uid = 0;
-    // captured CG iteration graphs: (matrix upload, workspace, iterations) -> exec
+    // captured CG iteration graphs: (matrix upload, workspace, iterations
+    // and history flag, right-hand sides, right-hand-side tile) -> exec
     struct Graph {
         uint64_t matrix_uid;
         const void *work;
         int32_t iters;
+        int32_t K, nr;
         void *exec;
     };
     std::vector<Graph> graphs;

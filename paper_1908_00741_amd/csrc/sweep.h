@@ -1,0 +1,640 @@
+// Preconditioning step z = M^-1 r of the HBMC-ordered IC(0) method, gfx950:
+// the device kernels and their launcher, included by one translation unit
+// per block size (sweep_bs*.hip) so that the instantiations compile in
+// parallel.
+//
+// Forward substitution y = L^-1 r, then backward substitution z = U^-1 y
+// (Section 2), color by color (Section 4.2.2): one kernel launch per color
+// phase, the launch boundary being the synchronization between colors
+// (Section 4.4.3).  The last color runs its forward and backward sweeps in
+// one launch, since no later color feeds its backward sweep.
+//
+// Inside a phase a tile is 64 chain lanes, one per BMC block (64/w level-1
+// blocks of w lanes each); a chain walks the bs steps of eqs. "y2-2",
+// "y2-3", so at step l the 64 lanes solve 64 independent rows, as the w SIMD
+// lanes do in the paper.  The couplings to other colors (eq. "for3") do not
+// depend on the chain, so each lane first issues the loads of all of them
+// for all bs steps -- values, indices and the gathered y or z -- and only
+// then runs the chain in registers.  Wavefronts never wait for each other
+// inside a phase: there is no barrier on the main path.
+//
+// Several right-hand sides (vectors stored [n_pad][K], the K values of a row
+// adjacent): a wavefront covers 64/NR chains of a tile for NR right-hand
+// sides, lane j taking chain j / NR and right-hand side j % NR of its group.
+// The NR lanes of a chain load the same factor entries (one access serves
+// them) and their y/z gathers are adjacent in memory; the wavefronts of the
+// K/NR right-hand-side groups of a tile are neighbours in the grid, so they
+// share the factor through the caches and HBM delivers it about once per
+// apply.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "hbmc_internal.h"
+
+namespace hbmc {
+
+// Launches the phases of one apply for factors of block size BS (defined in
+// sweep_bs<BS>.hip).  K right-hand sides, nr of them per wavefront.
+int launch_bs1(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+               const ApplyCg *cg, int K, int nr);
+int launch_bs2(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+               const ApplyCg *cg, int K, int nr);
+int launch_bs4(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+               const ApplyCg *cg, int K, int nr);
+int launch_bs8(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+               const ApplyCg *cg, int K, int nr);
+int launch_bs16(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+                const ApplyCg *cg, int K, int nr);
+int launch_bs32(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+                const ApplyCg *cg, int K, int nr);
+
+}  // namespace hbmc
+
+#ifdef HBMC_SWEEP_KERNELS
+namespace {
+
+using namespace hbmc;
+
+#define SWEEP_TRY(call)                                                               \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(HBMC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+constexpr int kLanes = kTileLanes;
+constexpr size_t kMaxLds = 64 * 1024;      // LDS budget of one workgroup (general path)
+
+// Device pointers of a Packed layout (strided and indexed slots per group),
+// each array with a trailing all-padding slot.
+struct Ext {
+    const int32_t *soff;
+    const int32_t *sbase;
+    const uint64_t *smask;
+    const void *sval;
+    const int32_t *ioff;
+    const int32_t *icol;
+    const void *ival;
+    int64_t spad, ipad;   // index of the padding slots
+};
+
+// One direction: couplings to other colors (ext) and inside the level-1
+// block (int).
+struct Tri {
+    Ext ext;
+    const int32_t *int_off;
+    const void *int_val;
+    const int32_t *int_lp;
+    int64_t int_pad;
+};
+
+struct Phase {
+    int64_t row0, row1;   // rows of the color
+    int64_t tile0;        // first global tile of the color
+    int64_t ntile;        // tiles of the color
+    int64_t nlane;        // chain lanes of the color (level-1 blocks * w)
+    int64_t ptiles;       // CG partial slots per right-hand side (all tiles * NR)
+    int32_t w;
+    int32_t lw;           // log2(w)
+    int32_t lds_slots;    // general path: LDS slots per wavefront
+    int32_t K;            // right-hand sides (row stride of the vectors)
+    int32_t G;            // right-hand-side groups: ceil(K / NR)
+    Tri f, b;
+    const void *dinv;
+    const int32_t *done;  // if set and *done != 0 the phase does nothing
+    ApplyCg cg;
+};
+
+// Sum over the lanes j' of the wavefront with j' = j mod NR (the lanes of
+// one right-hand side).
+template <int NR>
+__device__ inline double rhs_sum(double v) {
+#pragma unroll
+    for (int o = 32; o >= NR; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+enum { kForward = 0, kBackward = 1, kLast = 2 };
+
+// y[idx] among the compile-time candidates lo <= idx < hi, else 0.
+template <int BS, typename T>
+__device__ inline T pick(const T (&y)[BS], int idx, int lo, int hi) {
+    T r = T(0);
+#pragma unroll
+    for (int i = 0; i < BS; ++i)
+        if (i >= lo && i < hi) r = idx == i ? y[i] : r;
+    return r;
+}
+
+__device__ inline uint64_t readlane64(uint64_t v, int lane) {
+    const uint32_t lo = __builtin_amdgcn_readlane(uint32_t(v), lane);
+    const uint32_t hi = __builtin_amdgcn_readlane(uint32_t(v >> 32), lane);
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// Where a lane's values live: chain lane jc of the tile (factor entries are
+// [slot][64] by chain lane), right-hand side q (vector entry row * K + q).
+struct Lane {
+    int jc;
+    int q;
+    int K;
+    __device__ int64_t at(int64_t row) const { return row * K + q; }
+};
+
+// acc[l] -= sum of the couplings to other colors of step l, for all steps.
+// Chunks of CH slots: within a chunk every step's slot loads are issued
+// before any of them is used; a slot past a step's count reads the padding
+// slot, whose empty lane mask (strided) or column -1 (indexed) drops the
+// product.  Strided slots read z[base + jc]; the bases and lane masks of the
+// tile's strided slots (at most 64) are fetched by one vector load, one slot
+// per lane, and broadcast with readlane, so no load waits on another.
+// Indexed slots first load the lane's column.
+template <int BS, int CH, typename T>
+__device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
+                                 const double *__restrict__ z) {
+    const int jc = L.jc;
+    int32_t so[BS + 1], io[BS + 1];
+#pragma unroll
+    for (int l = 0; l <= BS; ++l) {
+        so[l] = E.soff[gt + l];
+        io[l] = E.ioff[gt + l];
+    }
+    {
+        const T *val = static_cast<const T *>(E.sval);
+        const int nst = so[BS] - so[0];
+        const int64_t mslot = so[0] + (j < nst ? j : 0);
+        const int32_t mbase = E.sbase[mslot];
+        const uint64_t mmask = E.smask[mslot];
+        int smax = 0;
+#pragma unroll
+        for (int l = 0; l < BS; ++l) smax = max(smax, so[l + 1] - so[l]);
+        for (int c0 = 0; c0 < smax; c0 += CH) {
+            T v[BS][CH], g[BS][CH];
+            bool on[BS][CH];
+#pragma unroll
+            for (int l = 0; l < BS; ++l)
+#pragma unroll
+                for (int k = 0; k < CH; ++k) {
+                    const bool has = c0 + k < so[l + 1] - so[l];
+                    const int q = has ? so[l] + c0 + k - so[0] : 0;
+                    const int32_t base = has ? __builtin_amdgcn_readlane(mbase, q) : 0;
+                    const uint64_t mask = has ? readlane64(mmask, q) : 0;
+                    const int64_t slot = has ? so[l] + c0 + k : E.spad;
+                    on[l][k] = (mask >> jc) & 1;
+                    v[l][k] = val[slot * kLanes + jc];
+                    g[l][k] = T(z[L.at(base + jc)]);
+                }
+#pragma unroll
+            for (int l = 0; l < BS; ++l)
+#pragma unroll
+                for (int k = 0; k < CH; ++k) acc[l] = on[l][k] ? acc[l] - v[l][k] * g[l][k] : acc[l];
+        }
+    }
+    const T *val = static_cast<const T *>(E.ival);
+    int smax = 0;
+#pragma unroll
+    for (int l = 0; l < BS; ++l) smax = max(smax, io[l + 1] - io[l]);
+    for (int c0 = 0; c0 < smax; c0 += CH) {
+        int32_t col[BS][CH];
+        T v[BS][CH];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const int64_t e = (c0 + k < io[l + 1] - io[l] ? int64_t(io[l]) + c0 + k : E.ipad) * kLanes + jc;
+                col[l][k] = E.icol[e];
+                v[l][k] = val[e];
+            }
+        T g[BS][CH];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) g[l][k] = T(z[L.at(col[l][k] >= 0 ? col[l][k] : 0)]);
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc[l] = col[l][k] >= 0 ? acc[l] - v[l][k] * g[l][k] : acc[l];
+    }
+}
+
+// Couplings inside the level-1 block for all steps, at most MI per step,
+// into registers (padding: index -1, value 0).
+template <int BS, int MI, typename T>
+__device__ inline void int_load(T (&v)[BS][MI], int32_t (&lp)[BS][MI], const Tri E, int64_t gt, int jc) {
+    const T *val = static_cast<const T *>(E.int_val);
+    int32_t off[BS + 1];
+#pragma unroll
+    for (int l = 0; l <= BS; ++l) off[l] = E.int_off[gt + l];   // one batch of scalar loads
+#pragma unroll
+    for (int l = 0; l < BS; ++l) {
+#pragma unroll
+        for (int k = 0; k < MI; ++k) {
+            const int64_t e = (k < off[l + 1] - off[l] ? int64_t(off[l]) + k : E.int_pad) * kLanes + jc;
+            v[l][k] = val[e];
+            lp[l][k] = E.int_lp[e];
+        }
+    }
+}
+
+// Copies chain lane jc's couplings inside the level-1 blocks of steps
+// [l0, l1) of the tile into an LDS region laid out like the slot lists
+// (slot s of the tile at s * 64 + jc).  The NR lanes of a chain write the
+// same values to the same places; each lane reads back only its chain's.
+template <typename T>
+__device__ inline void stage_steps(const Tri &E, int64_t gt, int l0, int l1, int jc, T *sv, int32_t *sl) {
+    const int64_t ib = E.int_off[gt];
+    const int64_t s0 = E.int_off[gt + l0] - ib, s1 = E.int_off[gt + l1] - ib;
+    const T *val = static_cast<const T *>(E.int_val) + ib * kLanes;
+    const int32_t *lp = E.int_lp + ib * kLanes;
+#pragma unroll 4
+    for (int64_t s = s0; s < s1; ++s) {
+        sv[s * kLanes + jc] = val[s * kLanes + jc];
+        sl[s * kLanes + jc] = lp[s * kLanes + jc];
+    }
+}
+
+// The bs-step chains of one lane (eqs. "y2-2", "y2-3"): forward (y) and/or
+// backward (z) sweeps inside the level-1 block, with acc holding each step's
+// right-hand side after the couplings to other colors.  Stores y (forward
+// phases) or z, and with CG the (r, z) partial of the lane's right-hand side
+// at pslot.  MI == 0: couplings inside the block are staged into this
+// wavefront's LDS region sv/sl when lds, else read in place.
+template <int BS, typename T, int MODE, int MI, bool CG, int NR>
+__device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], const double (&rn)[BS],
+                              const T (&fv)[BS][MI > 0 ? MI : 1], const int32_t (&fl)[BS][MI > 0 ? MI : 1],
+                              const T (&bv)[BS][MI > 0 ? MI : 1], const int32_t (&bl)[BS][MI > 0 ? MI : 1],
+                              T *sv, int32_t *sl, bool lds, int64_t gt, int j, const Lane &L, int64_t rb,
+                              bool valid, bool qv, double *__restrict__ z, int64_t pslot,
+                              T *svb = nullptr, int32_t *slb = nullptr) {
+    constexpr int RM = MI > 0 ? MI : 1;
+    const int w = ph.w;
+    const int jc = L.jc;
+    // svb: couplings already staged by the caller (forward at sv/sl,
+    // backward at svb/slb); else staged here, one direction at a time
+    const bool staged = svb != nullptr;
+    auto stage = [&](const Tri &E) -> int64_t {
+        const int64_t ib = E.int_off[gt];
+        if (lds && !staged) stage_steps<T>(E, gt, 0, BS, jc, sv, sl);
+        return ib;
+    };
+    auto ival = [&](const Tri &E, int64_t s) -> T {
+        if (!lds) return static_cast<const T *>(E.int_val)[(s + E.int_off[gt]) * kLanes + jc];
+        return (staged && &E == &ph.b ? svb : sv)[s * kLanes + jc];
+    };
+    auto ilp = [&](const Tri &E, int64_t s) -> int32_t {
+        if (!lds) return E.int_lp[(s + E.int_off[gt]) * kLanes + jc];
+        return (staged && &E == &ph.b ? slb : sl)[s * kLanes + jc];
+    };
+
+    T y[BS];
+    if (MODE != kBackward) {
+        int64_t ib = 0;
+        if constexpr (MI == 0) ib = stage(ph.f);
+#pragma unroll
+        for (int l = 0; l < BS; ++l) {
+            T a = acc[l];
+            if constexpr (MI > 0) {
+#pragma unroll
+                for (int k = 0; k < RM; ++k) a -= fv[l][k] * pick<BS, T>(y, fl[l][k], 0, l);
+            } else {
+                const int64_t s0 = ph.f.int_off[gt + l] - ib, s1 = ph.f.int_off[gt + l + 1] - ib;
+                for (int64_t s = s0; s < s1; ++s) a -= ival(ph.f, s) * pick<BS, T>(y, ilp(ph.f, s), 0, l);
+            }
+            y[l] = a * dv[l];
+            if (MODE == kForward && valid) z[L.at(rb + int64_t(l) * w)] = double(y[l]);
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < BS; ++l) y[l] = acc[l];
+    }
+    if (MODE != kForward) {
+        int64_t ib = 0;
+        if constexpr (MI == 0) ib = stage(ph.b);
+        // y becomes z, from the last step down
+#pragma unroll
+        for (int l = BS - 1; l >= 0; --l) {
+            T a = y[l];
+            if constexpr (MI > 0) {
+#pragma unroll
+                for (int k = 0; k < RM; ++k) a -= bv[l][k] * pick<BS, T>(y, bl[l][k], l + 1, BS);
+            } else {
+                const int64_t s0 = ph.b.int_off[gt + l] - ib, s1 = ph.b.int_off[gt + l + 1] - ib;
+                for (int64_t s = s0; s < s1; ++s) a -= ival(ph.b, s) * pick<BS, T>(y, ilp(ph.b, s), l + 1, BS);
+            }
+            y[l] = a;
+            if (valid) z[L.at(rb + int64_t(l) * w)] = double(a);
+        }
+        if (CG) {
+            double rz = 0.0;
+#pragma unroll
+            for (int l = 0; l < BS; ++l) rz += valid ? rn[l] * double(y[l]) : 0.0;
+            rz = rhs_sum<NR>(rz);
+            if (j < NR && qv) ph.cg.part_rz[int64_t(L.q) * ph.ptiles + pslot] = rz;
+        }
+    }
+}
+
+// Loads the right-hand side of one row (r, or y for a backward phase); with
+// CG in a forward phase first applies x += alpha p, r -= alpha q to it.
+template <typename T, int MODE, bool CG>
+__device__ inline T row_rhs(const Phase &ph, const double *__restrict__ r, const double *__restrict__ z,
+                            int64_t e, bool valid, double alpha, double &rn, double &rr) {
+    if (CG && MODE != kBackward) {
+        const double pv = ph.cg.p[e];
+        const double xn = ph.cg.x[e] + alpha * pv;
+        rn = ph.cg.r[e] - alpha * ph.cg.q[e];
+        if (valid) { ph.cg.x[e] = xn; ph.cg.r[e] = rn; rr += rn * rn; }
+        return T(rn);
+    }
+    if (CG) rn = ph.cg.r[e];   // backward: r of these rows is final
+    return T(MODE == kBackward ? z[e] : r[e]);
+}
+
+// One color phase, one wavefront per (tile, sub-tile, right-hand-side
+// group): the wavefront loads the couplings of all bs steps itself, then
+// runs the chains.  Best when a color has many tiles.
+// MODE kForward: y of color c; kBackward: z of color c; kLast: y then z of
+// the last color.  z holds y of the colors whose forward sweep is done and
+// z of the colors whose backward sweep is done.
+// MI > 0: at most MI couplings per step inside a level-1 block, held in
+// registers.  MI == 0: any number, staged per wavefront in LDS when they fit.
+template <int BS, typename T, int MODE, int MI, int CH, int WAVES, bool CG, int NR>
+__global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double *__restrict__ r,
+                                                          double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    // the wavefront index is uniform: say so, so that everything indexed by
+    // the tile (slot offsets, strided bases and masks) uses scalar loads
+    const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
+    const int j = threadIdx.x % kLanes;
+    // NR == 1 runs one right-hand side only (K == 1 at compile time)
+    constexpr bool ONE = NR == 1;
+    const int K = ONE ? 1 : ph.K;
+    const int64_t W = int64_t(blockIdx.x) * WAVES + wave;
+    const int64_t ts = ONE ? W : W / ph.G;       // tile * NR + sub-tile
+    const int grp = int(W - ts * (ONE ? 1 : ph.G));   // right-hand-side group
+    const int64_t tile = ts / NR;
+    const int sub = int(ts % NR);
+    if (tile >= ph.ntile) return;
+    const int q0 = grp * NR + j % NR;
+    const bool qv = q0 < K;
+    const Lane L{sub * (kLanes / NR) + j / NR, qv ? q0 : K - 1, K};
+    const CgState *cs = CG ? &ph.cg.st[int64_t(ph.cg.tile_sys[ph.tile0 + tile]) * K + L.q] : nullptr;
+    const bool live = qv && !(CG && cs->done);
+    if (CG && !__any(live)) return;              // every right-hand side of this wave has stopped
+    const int64_t lam = tile * kLanes + L.jc;    // chain lane in the color
+    const bool valid = lam < ph.nlane && live;
+    const int w = ph.w;
+    // lanes past the color's last level-1 block (a partial last tile) work
+    // on the last lane's rows and store nothing
+    const int64_t lc = lam < ph.nlane ? lam : ph.nlane - 1;
+    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
+    const int64_t gt = (ph.tile0 + tile) * BS;   // (tile, step 0) slot list
+    const int64_t pslot = (ph.tile0 + tile) * NR + sub;
+
+    constexpr int RM = MI > 0 ? MI : 1;
+    T fv[BS][RM], bv[BS][RM];
+    int32_t fl[BS][RM], bl[BS][RM];
+    if constexpr (MI > 0) {
+        if (MODE != kBackward) int_load<BS, RM, T>(fv, fl, ph.f, gt, L.jc);
+        if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, L.jc);
+    }
+    T acc[BS], dv[BS];
+    double rn[BS];   // CG: the updated residual of the lane's rows
+    double rr = 0.0;
+    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
+#pragma unroll
+    for (int l = 0; l < BS; ++l) {
+        const int64_t row = rb + int64_t(l) * w;
+        if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
+        acc[l] = row_rhs<T, MODE, CG>(ph, r, z, L.at(row), valid, alpha, rn[l], rr);
+    }
+    if (CG && MODE != kBackward) {
+        rr = rhs_sum<NR>(rr);
+        if (j < NR && qv) ph.cg.part_rr[int64_t(L.q) * ph.ptiles + pslot] = rr;
+    }
+    ext_sweep<BS, CH, T>(acc, MODE == kBackward ? ph.b.ext : ph.f.ext, gt, j, L, z);
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    T *sv = reinterpret_cast<T *>(smem) + int64_t(wave) * ph.lds_slots * kLanes;
+    int32_t *sl = reinterpret_cast<int32_t *>(reinterpret_cast<T *>(smem) +
+                                              int64_t(WAVES) * ph.lds_slots * kLanes) +
+                  int64_t(wave) * ph.lds_slots * kLanes;
+    chains<BS, T, MODE, MI, CG, NR>(ph, acc, dv, rn, fv, fl, bv, bl, sv, sl, ph.lds_slots > 0, gt, j, L,
+                                    rb, valid, qv, z, pslot);
+}
+
+// One color phase, one workgroup per tile with one wavefront per step: each
+// wavefront folds in the couplings to other colors of its step for the 64
+// lanes, the partial right-hand sides meet in LDS, and wavefront 0 runs the
+// chains.  Eight times the wavefronts of k_sweep, each with one step's loads:
+// best when a color has few tiles or its steps have many couplings.  One
+// right-hand side only.
+template <int BS, typename T, int MODE, int MI, int CH, bool CG>
+__global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph, const double *__restrict__ r,
+                                                      double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    const int l = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);   // this wave's step
+    const int j = threadIdx.x % kLanes;
+    const int64_t tile = blockIdx.x;
+    const CgState *cs = CG ? &ph.cg.st[ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
+    if (CG && cs->done) return;                  // the whole workgroup: one tile
+    const Lane L{j, 0, 1};
+    const int64_t lam = tile * kLanes + j;
+    const bool valid = lam < ph.nlane;
+    const int w = ph.w;
+    const int64_t lc = valid ? lam : ph.nlane - 1;
+    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
+    const int64_t gt = (ph.tile0 + tile) * BS;
+
+    extern __shared__ __align__(16) unsigned char smem[];
+    double *srn = reinterpret_cast<double *>(smem);          // [BS][64] (CG)
+    double *srr = srn + BS * kLanes;                         // [BS]     (CG)
+    T *sq = reinterpret_cast<T *>(srr + BS);                 // [BS][64]
+    T *sd = sq + BS * kLanes;                                // [BS][64]
+    T *svf = sd + BS * kLanes;                               // [lds_slots][64] (MI == 0)
+    T *svb = svf + ph.lds_slots * kLanes;                    // [lds_slots][64]
+    int32_t *slf = reinterpret_cast<int32_t *>(svb + ph.lds_slots * kLanes);
+    int32_t *slb = slf + ph.lds_slots * kLanes;
+
+    constexpr int RM = MI > 0 ? MI : 1;
+    T fv[BS][RM], bv[BS][RM];
+    int32_t fl[BS][RM], bl[BS][RM];
+    if constexpr (MI > 0) {
+        if (l == 0) {
+            if (MODE != kBackward) int_load<BS, RM, T>(fv, fl, ph.f, gt, j);
+            if (MODE != kForward) int_load<BS, RM, T>(bv, bl, ph.b, gt, j);
+        }
+    }
+    const int64_t row = rb + int64_t(l) * w;
+    double rn1 = 0.0, rr = 0.0;
+    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
+    T acc1[1] = {row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn1, rr)};
+    if (MODE != kBackward) sd[l * kLanes + j] = static_cast<const T *>(ph.dinv)[row];
+    if (MI == 0 && ph.lds_slots > 0) {   // this step's couplings inside the block
+        if (MODE != kBackward) stage_steps<T>(ph.f, gt, l, l + 1, j, svf, slf);
+        if (MODE != kForward) stage_steps<T>(ph.b, gt, l, l + 1, j, svb, slb);
+    }
+    ext_sweep<1, CH, T>(acc1, MODE == kBackward ? ph.b.ext : ph.f.ext, gt + l, j, L, z);
+    sq[l * kLanes + j] = acc1[0];
+    if (CG) {
+        srn[l * kLanes + j] = rn1;
+        if (MODE != kBackward) {
+            rr = rhs_sum<1>(rr);
+            if (j == 0) srr[l] = rr;
+        }
+    }
+    __syncthreads();
+    if (l != 0) return;
+
+    T acc[BS], dv[BS];
+    double rn[BS];
+#pragma unroll
+    for (int k = 0; k < BS; ++k) {
+        acc[k] = sq[k * kLanes + j];
+        dv[k] = MODE != kBackward ? sd[k * kLanes + j] : T(1);
+        rn[k] = CG ? srn[k * kLanes + j] : 0.0;
+    }
+    if (CG && MODE != kBackward && j == 0) {
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < BS; ++k) t += srr[k];
+        ph.cg.part_rr[ph.tile0 + tile] = t;
+    }
+    chains<BS, T, MODE, MI, CG, 1>(ph, acc, dv, rn, fv, fl, bv, bl, svf, slf, ph.lds_slots > 0, gt, j, L, rb,
+                                   valid, true, z, ph.tile0 + tile, svb, slb);
+}
+
+// ---------------------------------------------------------------------------
+// host side
+// ---------------------------------------------------------------------------
+template <class P>
+const P *dev_at(const void *base, size_t off) {
+    return reinterpret_cast<const P *>(static_cast<const uint8_t *>(base) + off);
+}
+
+Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const Sell &i) {
+    const PackedOffsets &x = o.ext;
+    return Tri{Ext{dev_at<int32_t>(f->dev, x.soff), dev_at<int32_t>(f->dev, x.sbase),
+                   dev_at<uint64_t>(f->dev, x.smask), dev_at<void>(f->dev, x.sval),
+                   dev_at<int32_t>(f->dev, x.ioff), dev_at<int32_t>(f->dev, x.icol),
+                   dev_at<void>(f->dev, x.ival), e.strided(), e.indexed()},
+               dev_at<int32_t>(f->dev, o.int_off), dev_at<void>(f->dev, o.int_val),
+               dev_at<int32_t>(f->dev, o.int_lp), i.slots()};
+}
+
+// Which kernel runs the phases: one wavefront per tile (k_sweep) or one
+// workgroup of bs wavefronts per tile (k_rows, one right-hand side only).
+// Automatic choice: k_rows when the colors have few tiles on average (fewer
+// than 1024: a phase would not fill the chip with one wavefront per tile).
+bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
+    if (bs > 16 || K != 1 || nr != 1) return false;
+    if (f->kernel == HBMC_KERNEL_SWEEP) return false;
+    if (f->kernel == HBMC_KERNEL_ROWS) return true;
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc);
+}
+
+template <int BS, typename T, int MI, bool CG, int NR>
+int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
+                  const int32_t *done, const ApplyCg &cg, int K) {
+    constexpr int CH = BS <= 4 ? 4 : (BS <= 8 ? 2 : 1);   // measured best on 128^3, bs 8
+    constexpr int WAVES = MI > 0 ? 4 : 1;                 // k_sweep: wavefronts per workgroup
+    constexpr int CHR = 16;                               // k_rows: slots per chunk
+    if (NR == 1 && K != 1) return fail(HBMC_EINVAL, "right-hand-side tile 1 runs one right-hand side");
+    const bool rows = use_rows(f, BS, K, NR);
+    Phase ph{};
+    ph.w = f->w;
+    ph.lw = __builtin_ctz(unsigned(f->w));
+    ph.K = K;
+    ph.G = (K + NR - 1) / NR;
+    ph.ptiles = f->tile_base[f->nc] * NR;
+    ph.f = tri_of(f, f->fwd, f->fext, f->fint);
+    ph.b = tri_of(f, f->bwd, f->bext, f->bint);
+    ph.dinv = dev_at<void>(f->dev, f->off_dinv);
+    ph.done = done;
+    ph.cg = cg;
+    const size_t tw = sizeof(T) + sizeof(int32_t);
+    size_t lds = 0;
+    ph.lds_slots = 0;
+    if (MI == 0) {
+        ph.lds_slots = std::max(std::max(f->max_int_slots_f, f->max_int_slots_b), 1);
+        const size_t per = size_t(ph.lds_slots) * kLanes * tw;
+        if ((rows ? 2 * per + size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS : WAVES * per) > kMaxLds)
+            ph.lds_slots = 0;
+    }
+    if (rows)
+        lds = size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + 2 * size_t(ph.lds_slots) * kLanes * tw;
+    else
+        lds = size_t(WAVES) * ph.lds_slots * kLanes * tw;
+    auto run = [&](int c, auto sweep, auto rowk) -> int {
+        ph.row0 = f->color_start[c];
+        ph.row1 = f->color_start[c + 1];
+        ph.tile0 = f->tile_base[c];
+        ph.ntile = f->tile_base[c + 1] - f->tile_base[c];
+        ph.nlane = (ph.row1 - ph.row0) / BS;
+        if (ph.ntile == 0) return HBMC_OK;
+        if (rows) {
+            hipLaunchKernelGGL(rowk, dim3(unsigned(ph.ntile)), dim3(BS * kLanes), lds, s, ph, r, z);
+        } else {
+            const int64_t waves = ph.ntile * NR * ph.G;
+            if ((waves + WAVES - 1) / WAVES > int64_t(INT32_MAX))
+                return fail(HBMC_EINVAL, "too many wavefronts for one launch");
+            const unsigned grid = unsigned((waves + WAVES - 1) / WAVES);
+            hipLaunchKernelGGL(sweep, dim3(grid), dim3(WAVES * kLanes), lds, s, ph, r, z);
+        }
+        SWEEP_TRY(hipGetLastError());
+        return HBMC_OK;
+    };
+    const int nc = f->nc;
+    int st;
+    for (int c = 0; c + 1 < nc; ++c)
+        if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG, NR>,
+                      k_rows<BS, T, kForward, MI, CHR, CG>))) return st;
+    if ((st = run(nc - 1, k_sweep<BS, T, kLast, MI, CH, WAVES, CG, NR>,
+                  k_rows<BS, T, kLast, MI, CHR, CG>))) return st;
+    for (int c = nc - 2; c >= 0; --c)
+        if ((st = run(c, k_sweep<BS, T, kBackward, MI, CH, WAVES, CG, NR>,
+                      k_rows<BS, T, kBackward, MI, CHR, CG>))) return st;
+    return HBMC_OK;
+}
+
+// right-hand sides per wavefront: 1 (one right-hand side), 4, 8 or 16
+template <int BS, typename T, int MI, bool CG>
+int dispatch_nr(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+                const ApplyCg &cg, int K, int nr) {
+    switch (nr) {
+        case 1: return launch_phases<BS, T, MI, CG, 1>(f, r, z, s, done, cg, K);
+        case 4: return launch_phases<BS, T, MI, CG, 4>(f, r, z, s, done, cg, K);
+        case 8: return launch_phases<BS, T, MI, CG, 8>(f, r, z, s, done, cg, K);
+        case 16: return launch_phases<BS, T, MI, CG, 16>(f, r, z, s, done, cg, K);
+        default: return fail(HBMC_EINVAL, "right-hand-side tile %d (1, 4, 8, 16)", nr);
+    }
+}
+
+// couplings per step inside a level-1 block: <= 1, <= 2, or more (LDS path)
+template <int BS, typename T, bool CG>
+int dispatch_mi(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+                const ApplyCg &cg, int K, int nr) {
+    const int mi = std::max(f->max_int_step_f, f->max_int_step_b);
+    if (mi <= 1) return dispatch_nr<BS, T, 1, CG>(f, r, z, s, done, cg, K, nr);
+    if (BS <= 16 && mi <= 2) return dispatch_nr<BS, T, 2, CG>(f, r, z, s, done, cg, K, nr);
+    return dispatch_nr<BS, T, 0, CG>(f, r, z, s, done, cg, K, nr);
+}
+
+template <int BS>
+int launch_bs(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
+              const ApplyCg *cgp, int K, int nr) {
+    if (!cgp) {
+        const ApplyCg none{};
+        return f->precision == HBMC_F64 ? dispatch_mi<BS, double, false>(f, r, z, s, done, none, K, nr)
+                                        : dispatch_mi<BS, float, false>(f, r, z, s, done, none, K, nr);
+    }
+    return f->precision == HBMC_F64 ? dispatch_mi<BS, double, true>(f, cgp->r, z, s, done, *cgp, K, nr)
+                                    : dispatch_mi<BS, float, true>(f, cgp->r, z, s, done, *cgp, K, nr);
+}
+
+}  // namespace
+#endif  // HBMC_SWEEP_KERNELS

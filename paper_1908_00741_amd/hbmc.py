@@ -25,7 +25,8 @@ HBMC_KERNEL_AUTO, HBMC_KERNEL_SWEEP, HBMC_KERNEL_ROWS = 0, 1, 2
 SYMBOLS = (
     "hbmc_last_error", "hbmc_order", "hbmc_order_batch", "hbmc_order_info", "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
-    "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "ic0_apply", "hbmc_matrix_create",
+    "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "hbmc_factor_set_rhs_tile",
+    "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
 )
@@ -77,6 +78,7 @@ def lib():
         L.hbmc_factor_device_bytes.argtypes = [P, P]
         L.hbmc_factor_upload.argtypes = [P, P, sz, P]
         L.hbmc_factor_set_kernel.argtypes = [P, i32]
+        L.hbmc_factor_set_rhs_tile.argtypes = [P, i32]
         L.hbmc_factor_destroy.argtypes = [P]
         L.hbmc_factor_destroy.restype = None
         L.ic0_apply.argtypes = [P, P, P, i32, P]
@@ -200,6 +202,10 @@ class Factor:
 
     def set_kernel(self, kernel: int):
         _check("hbmc_factor_set_kernel", lib().hbmc_factor_set_kernel(self._h, int(kernel)))
+        return self
+
+    def set_rhs_tile(self, nr: int):
+        _check("hbmc_factor_set_rhs_tile", lib().hbmc_factor_set_rhs_tile(self._h, int(nr)))
         return self
 
     def upload(self, device="cuda", stream=None):

@@ -142,3 +142,14 @@ def test_breakdown():
     with pytest.raises(hbmc.HbmcError) as e:
         hbmc.ic0_factor(o, A)
     assert e.value.code == hbmc.HBMC_EBREAKDOWN
+
+
+def test_rhs_tile_errors():
+    A = inputs.grid2d_5pt(8)
+    f = hbmc.ic0_factor(hbmc.hbmc_order(A, 4, 8), A)
+    for ok in (0, 4, 8, 16):
+        f.set_rhs_tile(ok)
+    for bad in (1, 2, 3, 32, -1):
+        with pytest.raises(hbmc.HbmcError) as e:
+            f.set_rhs_tile(bad)
+        assert e.value.code == hbmc.HBMC_EINVAL
