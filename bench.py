@@ -73,6 +73,9 @@ def main() -> int:
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--ext", default="fp32,batch,rhs,graph",
+                    help="comma-separated extension comparisons to run after the headline "
+                         "(fp32, batch, rhs, graph); empty for none")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run dst = 2 * src on 256 MiB tensors, a kernel that reads "
@@ -160,6 +163,28 @@ def main() -> int:
     ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     log(f"[bench] ICCG {ms_per_step:.2f} ms per solve, {st.iters} iterations")
 
+    # ---- extensions: speedups over plain FP64 single-RHS ICCG ---------------
+    ext = {}
+    wanted = [e for e in args.ext.split(",") if e]
+    if wanted:
+        from paper_1908_00741_amd import experiments
+        for name in wanted:
+            try:
+                if name == "graph":
+                    ext[name] = experiments.graph(solver, b, tol=1e-7, log=log)
+                elif name == "fp32":
+                    ext[name] = experiments.fp32(dev, log=log)
+                elif name == "batch":
+                    ext[name] = experiments.batch(dev, log=log)
+                elif name == "rhs":
+                    ext[name] = experiments.rhs(dev, log=log)
+                else:
+                    ext[name] = {"error": "unknown extension"}
+            except Exception as e:   # reported in the JSON line, not fatal
+                ext[name] = {"error": f"{type(e).__name__}: {e}"}
+                log(f"[bench] extension {name} failed: {e}")
+            torch.cuda.empty_cache()
+
     # ---- oracle on the host ------------------------------------------------
     cpu = None
     if not args.no_cpu:
@@ -205,6 +230,7 @@ def main() -> int:
                  "true_rel_res": st.true_rel_res, "ms_per_iteration": round(ms_per_step / max(st.iters, 1), 4),
                  "setup_s": round(setup_s, 2)},
         "cpu_baseline": cpu,
+        "extensions": ext,
     }
     print(json.dumps(out), flush=True)
     return 0

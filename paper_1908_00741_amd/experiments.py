@@ -1,0 +1,153 @@
+"""Measured comparisons of the solver's forms against plain FP64 single-
+right-hand-side ICCG on the same GPU, at equal final true residual (every
+solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
+
+- fp32: FP32 factor and substitutions (FP64 CG) against FP64, on the
+  unstructured 13-NN Laplacian of 1M points;
+- batch: 128 Poisson systems of uneven size (16^3 .. 64^3) solved together
+  (one set of launches per iteration, per-system stopping tests, FP32
+  preconditioner) against solving them one by one in FP64;
+- rhs: 32 right-hand sides of the 128^3 lognormal diffusion problem solved
+  together (factor read once per apply for all of them, autotuned
+  right-hand-side tile, FP32 preconditioner) against 32 FP64 solves;
+- graph: the same solve with the iterations replayed as a hipGraph and
+  launched one by one.
+
+Setup (ordering, factorization, upload) is outside every timed region.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+
+from . import autotune, hbmc, inputs
+
+
+def _sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def _timed(fn, reps=3):
+    """Median wall time of reps calls (after one untimed call) and the last
+    result."""
+    out = fn()
+    ts = []
+    for _ in range(reps):
+        _sync()
+        t0 = time.perf_counter()
+        out = fn()
+        _sync()
+        ts.append(time.perf_counter() - t0)
+    return float(np.median(ts)), out
+
+
+def _stats(st):
+    sts = st if isinstance(st, list) else [st]
+    return {"iters_max": max(s.iters for s in sts), "iters_min": min(s.iters for s in sts),
+            "true_rel_res_max": max(s.true_rel_res for s in sts),
+            "all_converged": all(s.status == hbmc.HBMC_OK for s in sts)}
+
+
+def fp32(device, npts=1_000_000, bs=4, w=16, tol=1e-7, log=print):
+    """FP32 against FP64 preconditioner on the 13-NN Laplacian."""
+    import torch
+    log(f"[ext fp32] kNN Laplacian {npts} points, bs={bs} w={w}")
+    A = inputs.knn_laplacian(npts, 13, 4, 5, shift=1e-3)
+    b = torch.from_numpy(inputs.uniform_rhs(A.n, 3)).to(device)
+    res = {"workload": f"13-NN Laplacian of {npts} uniform points, 1/dist weights, shift 1e-3, "
+                       f"b~U[-1,1], HBMC bs={bs} w={w}, tol {tol:g}"}
+    o = hbmc.hbmc_order(A, bs, w)
+    m = hbmc.hbmc_matrix_create(o, A).upload(device)
+    xs = {}
+    for name, prec in (("f64", hbmc.HBMC_F64), ("f32", hbmc.HBMC_F32)):
+        sv = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).upload(device), m)
+        t, (x, st) = _timed(lambda: sv.solve(b, tol=tol))
+        xs[name] = x.cpu().numpy()
+        res[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
+        log(f"[ext fp32] {name}: {t * 1e3:.2f} ms, {st.iters} its, true res {st.true_rel_res:.2e}")
+    res["speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
+    res["rel_diff_x_f32_vs_f64"] = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
+    return res
+
+
+def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, log=print):
+    """Uneven batch in one set of launches against one-by-one FP64 solves."""
+    import torch
+    sizes = inputs.batch_sizes(count, seed, lo, hi)
+    log(f"[ext batch] {count} Poisson systems, N in [{sizes.min()}, {sizes.max()}]")
+    mats = [inputs.poisson3d(int(N)) for N in sizes]
+    A, sys_ptr = inputs.block_diag(mats)
+    rhs = [inputs.uniform_rhs(M.n, 1000 + s) for s, M in enumerate(mats)]
+    res = {"workload": f"{count} 7-point Poisson systems, N ~ U{{{lo}..{hi}}} (seed {seed}), "
+                       f"n total {A.n}, b~U[-1,1], HBMC bs={bs} w={w}, tol {tol:g}"}
+    t0 = time.perf_counter()
+    sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F32, device=device, sys_ptr=sys_ptr)
+    res["setup_s"] = round(time.perf_counter() - t0, 2)
+    bb = torch.from_numpy(np.concatenate(rhs)).to(device)
+    t, (x, st) = _timed(lambda: sv.solve(bb, tol=tol))
+    res["batched_f32"] = {"ms": round(t * 1e3, 3), **_stats(st)}
+    log(f"[ext batch] batched FP32: {t * 1e3:.2f} ms")
+    del sv
+    total, its, worst, conv = 0.0, [], 0.0, True
+    for s, M in enumerate(mats):
+        one = hbmc.Solver.setup(M, bs, w, hbmc.HBMC_F64, device=device)
+        b1 = torch.from_numpy(rhs[s]).to(device)
+        t1, (x1, st1) = _timed(lambda: one.solve(b1, tol=tol), reps=1)
+        total += t1
+        its.append(st1.iters)
+        worst = max(worst, st1.true_rel_res)
+        conv = conv and st1.status == hbmc.HBMC_OK
+    res["one_by_one_f64"] = {"ms": round(total * 1e3, 3), "iters_max": max(its), "iters_min": min(its),
+                             "true_rel_res_max": worst, "all_converged": conv}
+    res["speedup"] = round(total / t, 3)
+    log(f"[ext batch] one by one FP64: {total * 1e3:.2f} ms, speedup {total / t:.2f}")
+    return res
+
+
+def rhs(device, N=128, K=32, tol=1e-7, tune=True, log=print):
+    """K right-hand sides together against K single FP64 solves."""
+    import torch
+    log(f"[ext rhs] {N}^3 diffusion, K={K}")
+    A = inputs.diffusion3d(N, 1.0, 2)
+    B = np.stack([inputs.uniform_rhs(A.n, 500 + q) for q in range(K)], axis=1)
+    Bd = torch.from_numpy(np.ascontiguousarray(B).ravel()).to(device)
+    res = {"workload": f"diffusion3d {N}^3 lognormal sigma=1 seed 2, {K} right-hand sides "
+                       f"b_q~U[-1,1] (seeds 500..), tol {tol:g}"}
+    choice = None
+    if tune:
+        choice = autotune.tune(A, Bd, nrhs=K, precision=hbmc.HBMC_F32, tol=tol, bs_list=(4, 8, 16),
+                               w_list=(16, 32, 64), tiles=(4, 8, 16), reps=1, device=device, log=log)
+        res["autotune"] = {"bs": choice.bs, "w": choice.w, "rhs_tile": choice.rhs_tile,
+                           "trials": [[t.bs, t.w, t.rhs_tile, round(t.seconds * 1e3, 2), t.iters]
+                                      for t in choice.trials]}
+    bs, w, tile = (choice.bs, choice.w, choice.rhs_tile) if choice else (8, 64, 0)
+    sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F32, device=device)
+    sv.factor.set_rhs_tile(tile)
+    t, (x, st) = _timed(lambda: sv.solve(Bd, nrhs=K, tol=tol), reps=2)
+    res["multi_f32"] = {"ms": round(t * 1e3, 3), "bs": bs, "w": w, "rhs_tile": tile, **_stats(st)}
+    log(f"[ext rhs] {K} together (FP32 preconditioner, bs={bs} w={w} tile={tile}): {t * 1e3:.2f} ms")
+    del sv
+    one = hbmc.Solver.setup(A, 8, 64, hbmc.HBMC_F64, device=device)
+    cols = [torch.from_numpy(np.ascontiguousarray(B[:, q])).to(device) for q in range(K)]
+
+    def singles():
+        return [one.solve(c, tol=tol) for c in cols]
+    t1, outs = _timed(singles, reps=1)
+    res["singles_f64"] = {"ms": round(t1 * 1e3, 3), "bs": 8, "w": 64, **_stats([o[1] for o in outs])}
+    res["speedup"] = round(t1 / t, 3)
+    log(f"[ext rhs] {K} single FP64 solves: {t1 * 1e3:.2f} ms, speedup {t1 / t:.2f}")
+    return res
+
+
+def graph(solver, b, tol=1e-7, log=print):
+    """The same solve with the iterations as a replayed hipGraph and
+    launched one by one."""
+    out = {}
+    for name, ug in (("graph", True), ("eager", False)):
+        t, (x, st) = _timed(lambda: solver.solve(b, tol=tol, use_graph=ug, check_every=16))
+        out[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
+        log(f"[ext graph] {name}: {t * 1e3:.2f} ms")
+    out["speedup"] = round(out["eager"]["ms"] / out["graph"]["ms"], 3)
+    return out
