@@ -1,0 +1,558 @@
+// Kernels of the warm-start network x0 = s * MLP(theta) (12 -> 256 -> 256 ->
+// n, ReLU, mean squared error, Adam): dense products on the matrix cores in
+// BF16 with FP32 accumulation (or FP32 throughout, for checking), with the
+// bias, activation and loss folded into the products' epilogues.
+//
+// The products: a workgroup of four wavefronts computes a 64 x 64 tile of
+// C = A B, each wavefront a 32 x 32 quarter with 32x32 MFMA instructions
+// (K = 16 per instruction in BF16, 2 in FP32).  Tiles of A and B pass
+// through LDS in a k-contiguous layout, whatever their layout in memory, so
+// one kernel serves the three products of a linear layer: X W (forward),
+// X^T dY (weight gradient) and dY W^T (input gradient, split over K into
+// partial products that a second kernel adds in a fixed order).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdint>
+
+#include "hbmc_internal.h"
+#include "../../include/hbmc_mlp.h"
+
+using namespace hbmc;
+
+#define HIP_TRY(call)                                                                 \
+    do {                                                                              \
+        hipError_t e_ = (call);                                                       \
+        if (e_ != hipSuccess)                                                         \
+            return fail(HBMC_EHIP, "%s failed: %s", #call, hipGetErrorString(e_));    \
+    } while (0)
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// BF16 storage as 16-bit patterns; conversion from FP32 rounds to nearest
+// even (NaN stays NaN).
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+__device__ inline uint16_t f2bf(float f) {
+    const uint32_t u = __float_as_uint(f);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return uint16_t((u >> 16) | 0x40);   // quiet NaN
+    return uint16_t((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+template <typename T> __device__ inline float ld(const T *p, int64_t i);
+template <> __device__ inline float ld<uint16_t>(const uint16_t *p, int64_t i) { return bf2f(p[i]); }
+template <> __device__ inline float ld<float>(const float *p, int64_t i) { return p[i]; }
+template <typename T> __device__ inline T cvt(float v);
+template <> __device__ inline uint16_t cvt<uint16_t>(float v) { return f2bf(v); }
+template <> __device__ inline float cvt<float>(float v) { return v; }
+
+constexpr int BM = 64, BN = 64, KT = 32, LDK = KT + 8;   // LDS rows padded by 16 bytes
+constexpr int kThreads = 256;
+
+enum { EPI_STORE = 0, EPI_BIAS_ACT = 1, EPI_MSE = 2 };
+
+struct Epi {
+    // EPI_STORE: C[z * zstride + i * ldc + j] = acc (FP32)
+    float *C;
+    int64_t ldc, zstride;
+    // EPI_BIAS_ACT: Y[i * ldc + j] = act(acc + bias[j]) in the compute type,
+    // and Yf in FP32 when not null
+    const float *bias;
+    int relu;
+    void *Y;
+    float *Yf;
+    // EPI_MSE: y = acc + bias[j], d = y - T[i * ldc + j]; dY = scale * d in
+    // the compute type; loss_part[tile] = sum d^2; dbias_part[row tile][j] =
+    // sum over the tile's rows of scale * d
+    const void *T;
+    float scale;
+    float *loss_part, *dbias_part;
+};
+
+// The MFMA step for one K slice of KT held in LDS: acc += A[32 rows of the
+// wavefront][KT] * B[KT][32 columns of the wavefront].  A fragment is 8
+// consecutive k of one row (BF16) or 1 (FP32); the instruction pairs the
+// same k positions of A and B, so the order of k inside a slice is free.
+template <typename T>
+__device__ inline void mma_slice(f32x16 &acc, const T (*sA)[LDK], const T (*sB)[LDK], int ra, int cb, int l);
+template <>
+__device__ inline void mma_slice<uint16_t>(f32x16 &acc, const uint16_t (*sA)[LDK], const uint16_t (*sB)[LDK],
+                                           int ra, int cb, int l) {
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 16) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sA[ra][kk + 8 * (l >> 5)]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sB[cb][kk + 8 * (l >> 5)]);
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+}
+template <>
+__device__ inline void mma_slice<float>(f32x16 &acc, const float (*sA)[LDK], const float (*sB)[LDK], int ra,
+                                        int cb, int l) {
+#pragma unroll
+    for (int kk = 0; kk < KT; kk += 2) {
+        acc = __builtin_amdgcn_mfma_f32_32x32x2f32(sA[ra][kk + (l >> 5)], sB[cb][kk + (l >> 5)], acc, 0, 0, 0);
+    }
+}
+
+// C = A B for logical A [M][K] and B [K][N].  LAYOUT: MLP_NN (A stored
+// [M][K], B stored [K][N]), MLP_TN (A stored [K][M]), MLP_NT (B stored
+// [N][K]).  blockIdx.z: K split (k in [z * kchunk, (z + 1) * kchunk)).
+template <typename T, int LAYOUT, int EPI>
+__global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T *__restrict__ A, int64_t lda,
+                                                   const T *__restrict__ B, int64_t ldb, int kchunk, Epi ep) {
+    __shared__ __align__(16) T sA[BM][LDK];
+    __shared__ __align__(16) T sB[BN][LDK];
+    const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    f32x16 acc = {};
+    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+#pragma unroll
+        for (int e = 0; e < BM * KT / kThreads; ++e) {
+            const int idx = tid + kThreads * e;
+            int m, k;
+            if (LAYOUT == MLP_TN) { k = idx / BM; m = idx % BM; }   // A stored [K][M]: m contiguous
+            else { m = idx / KT; k = idx % KT; }                   // A stored [M][K]: k contiguous
+            const int gm = m0 + m, gk = k0 + k;
+            float v = 0.0f;
+            if (gm < M && gk < kend)
+                v = LAYOUT == MLP_TN ? ld(A, int64_t(gk) * lda + gm) : ld(A, int64_t(gm) * lda + gk);
+            sA[m][k] = cvt<T>(v);
+        }
+#pragma unroll
+        for (int e = 0; e < BN * KT / kThreads; ++e) {
+            const int idx = tid + kThreads * e;
+            int n, k;
+            if (LAYOUT == MLP_NT) { n = idx / KT; k = idx % KT; }   // B stored [N][K]: k contiguous
+            else { k = idx / BN; n = idx % BN; }                   // B stored [K][N]: n contiguous
+            const int gn = n0 + n, gk = k0 + k;
+            float v = 0.0f;
+            if (gn < N && gk < kend)
+                v = LAYOUT == MLP_NT ? ld(B, int64_t(gn) * ldb + gk) : ld(B, int64_t(gk) * ldb + gn);
+            sB[n][k] = cvt<T>(v);
+        }
+        __syncthreads();
+        mma_slice<T>(acc, sA, sB, wm * 32 + (l & 31), wn * 32 + (l & 31), l);
+        __syncthreads();
+    }
+    // element r of the accumulator: row 8 (r / 4) + 4 (l / 32) + r % 4 and
+    // column l % 32 of the wavefront's 32 x 32 quarter
+    const int j = n0 + wn * 32 + (l & 31);
+    if (EPI == EPI_STORE) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            if (i < M && j < N) ep.C[blockIdx.z * ep.zstride + int64_t(i) * ep.ldc + j] = acc[r];
+        }
+    } else if (EPI == EPI_BIAS_ACT) {
+        const float bj = ep.bias && j < N ? ep.bias[j] : 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            if (i < M && j < N) {
+                float y = acc[r] + bj;
+                if (ep.relu) y = fmaxf(y, 0.0f);
+                static_cast<T *>(ep.Y)[int64_t(i) * ep.ldc + j] = cvt<T>(y);
+                if (ep.Yf) ep.Yf[int64_t(i) * ep.ldc + j] = y;
+            }
+        }
+    } else {   // EPI_MSE
+        __shared__ float sCol[2][BN];
+        __shared__ float sLoss[kThreads / 64];
+        const float bj = ep.bias && j < N ? ep.bias[j] : 0.0f;
+        float col = 0.0f, loss = 0.0f;
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            if (i < M && j < N) {
+                const int64_t e = int64_t(i) * ep.ldc + j;
+                const float d = acc[r] + bj - ld(static_cast<const T *>(ep.T), e);
+                const float g = ep.scale * d;
+                static_cast<T *>(ep.Y)[e] = cvt<T>(g);
+                col += g;
+                loss += d * d;
+            }
+        }
+        col += __shfl_xor(col, 32, 64);              // the two lanes of one column
+        if (l < 32) sCol[wm][wn * 32 + l] = col;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+        if (l == 0) sLoss[wave] = loss;
+        __syncthreads();
+        if (tid < BN && n0 + tid < N) ep.dbias_part[int64_t(blockIdx.y) * N + n0 + tid] = sCol[0][tid] + sCol[1][tid];
+        if (tid == 0)
+            ep.loss_part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
+    }
+}
+
+// out[j] = sum over i < R of src[i * ld + j], i in order
+__global__ void k_sum_rows(int64_t R, int64_t N, const float *__restrict__ src, int64_t ld,
+                           float *__restrict__ out) {
+    const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= N) return;
+    float s = 0.0f;
+    for (int64_t i = 0; i < R; ++i) s += src[i * ld + j];
+    out[j] = s;
+}
+
+// dz = dh * (h > 0): dz in the compute type and, when dzf is set, FP32
+template <typename T>
+__global__ void k_relu_bwd(int64_t n, const float *__restrict__ dh, const T *__restrict__ h, T *__restrict__ dz,
+                           float *__restrict__ dzf) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float v = ld(h, i) > 0.0f ? dh[i] : 0.0f;
+    dz[i] = cvt<T>(v);
+    if (dzf) dzf[i] = v;
+}
+
+// Adam with bias corrections c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t);
+// the compute-type copy of the updated weights is written too
+template <typename T>
+__global__ void k_adam(int64_t n, float *__restrict__ w, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ g, T *__restrict__ wc, float lr, float b1, float b2, float eps,
+                       float c1, float c2) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[i] = wi;
+    if (wc) wc[i] = cvt<T>(wi);
+}
+
+template <typename T>
+__global__ void k_cast_f32(int64_t n, const float *__restrict__ src, T *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = cvt<T>(src[i]);
+}
+
+template <typename T>
+__global__ void k_cast_f64(int64_t n, const double *__restrict__ src, double scale, T *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = cvt<T>(float(src[i] * scale));
+}
+
+__global__ void k_to_f64(int64_t n, const float *__restrict__ src, double scale, double *__restrict__ dst) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = double(src[i]) * scale;
+}
+
+// b at the N^3 cell centres (index x + N y + N^2 z) for theta = (positions
+// s_q along the four body diagonals, widths, amplitudes)
+__global__ void k_gaussian_rhs(int N, double s0, double s1, double s2, double s3, double w0, double w1,
+                               double w2, double w3, double a0, double a1, double a2, double a3,
+                               double *__restrict__ b) {
+    const int64_t idx = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t n = int64_t(N) * N * N;
+    if (idx >= n) return;
+    const double h = 1.0 / N;
+    const double x = (double(idx % N) + 0.5) * h;
+    const double y = (double((idx / N) % N) + 0.5) * h;
+    const double z = (double(idx / (int64_t(N) * N)) + 0.5) * h;
+    // diagonal q starts at o_q and runs along d_q
+    const double ox[4] = {0, 1, 0, 0}, oy[4] = {0, 0, 1, 0}, oz[4] = {0, 0, 0, 1};
+    const double dx[4] = {1, -1, 1, 1}, dy[4] = {1, 1, -1, 1}, dz[4] = {1, 1, 1, -1};
+    const double s[4] = {s0, s1, s2, s3}, w[4] = {w0, w1, w2, w3}, a[4] = {a0, a1, a2, a3};
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double cx = ox[q] + s[q] * dx[q], cy = oy[q] + s[q] * dy[q], cz = oz[q] + s[q] * dz[q];
+        const double r2 = (x - cx) * (x - cx) + (y - cy) * (y - cy) + (z - cz) * (z - cz);
+        v += a[q] * exp(-r2 / (2.0 * w[q] * w[q]));
+    }
+    b[idx] = v;
+}
+
+// Y = act(X W + b) for a few rows (M <= MM): a matrix-vector product bound
+// by reading W once.  A workgroup covers 512 columns, each lane 8 adjacent
+// ones (one 16-byte load of W per k in BF16); its four wavefronts take a
+// quarter of k each and meet in LDS.
+template <typename T> struct Vec8;
+template <> struct Vec8<uint16_t> {
+    uint16_t v[8];
+    __device__ void load(const uint16_t *p) {
+        const uint4 u = *reinterpret_cast<const uint4 *>(p);
+        v[0] = u.x & 0xffff; v[1] = u.x >> 16; v[2] = u.y & 0xffff; v[3] = u.y >> 16;
+        v[4] = u.z & 0xffff; v[5] = u.z >> 16; v[6] = u.w & 0xffff; v[7] = u.w >> 16;
+    }
+    __device__ float at(int c) const { return bf2f(v[c]); }
+};
+template <> struct Vec8<float> {
+    float v[8];
+    __device__ void load(const float *p) {
+        const float4 a = *reinterpret_cast<const float4 *>(p), b = *reinterpret_cast<const float4 *>(p + 4);
+        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w; v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
+    }
+    __device__ float at(int c) const { return v[c]; }
+};
+
+constexpr int GV_COLS = 512;   // columns per workgroup
+template <typename T, int MM>
+__global__ void __launch_bounds__(kThreads) k_gemv(int M, int N, int K, const T *__restrict__ X,
+                                                   const T *__restrict__ W, const float *__restrict__ bias,
+                                                   int relu, T *__restrict__ Y, float *__restrict__ Yf) {
+    __shared__ float sred[kThreads / 64][MM][GV_COLS];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int j0 = blockIdx.x * GV_COLS + lane * 8;
+    const int kq = (K + 3) / 4, kb = wave * kq, ke = min(K, kb + kq);
+    const bool vec = (N % 8 == 0) && (j0 + 8 <= N);
+    float acc[MM][8];
+#pragma unroll
+    for (int m = 0; m < MM; ++m)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[m][c] = 0.0f;
+#pragma unroll 4
+    for (int k = kb; k < ke; ++k) {
+        Vec8<T> w;
+        if (vec) w.load(W + int64_t(k) * N + j0);
+        else
+#pragma unroll
+            for (int c = 0; c < 8; ++c) w.v[c] = j0 + c < N ? W[int64_t(k) * N + j0 + c] : T(0);
+#pragma unroll
+        for (int m = 0; m < MM; ++m) {
+            const float xm = m < M ? ld(X, int64_t(m) * K + k) : 0.0f;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) acc[m][c] += xm * w.at(c);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < MM; ++m)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) sred[wave][m][lane * 8 + c] = acc[m][c];
+    __syncthreads();
+    // thread t finishes columns t and t + 256 of the workgroup for every row
+    for (int cc = threadIdx.x; cc < GV_COLS; cc += kThreads) {
+        const int j = blockIdx.x * GV_COLS + cc;
+        if (j >= N) continue;
+        const float bj = bias ? bias[j] : 0.0f;
+        for (int m = 0; m < M; ++m) {
+            float y = (sred[0][m][cc] + sred[1][m][cc]) + (sred[2][m][cc] + sred[3][m][cc]) + bj;
+            if (relu) y = fmaxf(y, 0.0f);
+            Y[int64_t(m) * N + j] = cvt<T>(y);
+            if (Yf) Yf[int64_t(m) * N + j] = y;
+        }
+    }
+}
+
+// T[m][i] = scale * sum over q < 4 of amp[m][q] * G[idx[m][q]][i]
+template <typename T>
+__global__ void k_combine(int M, int64_t n, const T *__restrict__ G, const int32_t *__restrict__ idx,
+                          const float *__restrict__ amp, float scale, T *__restrict__ out) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int m = blockIdx.y;
+    if (i >= n || m >= M) return;
+    float v = 0.0f;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) v += amp[m * 4 + q] * ld(G, int64_t(idx[m * 4 + q]) * n + i);
+    out[int64_t(m) * n + i] = cvt<T>(scale * v);
+}
+
+inline unsigned blocks_for(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
+
+template <typename T, int EPI>
+int launch_gemm(int layout, int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb,
+                int nsplit, const Epi &ep, hipStream_t s) {
+    const int kchunk = ((K + nsplit - 1) / nsplit + KT - 1) / KT * KT;
+    const dim3 grid(unsigned((N + BN - 1) / BN), unsigned((M + BM - 1) / BM), unsigned(nsplit));
+    const T *a = static_cast<const T *>(A);
+    const T *b = static_cast<const T *>(B);
+    switch (layout) {
+        case MLP_NN: hipLaunchKernelGGL((k_gemm<T, MLP_NN, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        case MLP_TN: hipLaunchKernelGGL((k_gemm<T, MLP_TN, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        case MLP_NT: hipLaunchKernelGGL((k_gemm<T, MLP_NT, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        default: return fail(HBMC_EINVAL, "unknown layout %d", layout);
+    }
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+template <int EPI>
+int gemm_dtype(int dtype, int layout, int M, int N, int K, const void *A, int64_t lda, const void *B,
+               int64_t ldb, int nsplit, const Epi &ep, hipStream_t s) {
+    if (dtype == MLP_BF16) return launch_gemm<uint16_t, EPI>(layout, M, N, K, A, lda, B, ldb, nsplit, ep, s);
+    if (dtype == MLP_F32) return launch_gemm<float, EPI>(layout, M, N, K, A, lda, B, ldb, nsplit, ep, s);
+    return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+}
+
+int check_dims(int M, int N, int K, int nsplit) {
+    if (M < 1 || N < 1 || K < 1) return fail(HBMC_EINVAL, "bad sizes M=%d N=%d K=%d", M, N, K);
+    if (nsplit < 1 || nsplit > 65535) return fail(HBMC_EINVAL, "bad split %d", nsplit);
+    if ((N + BN - 1) / BN > INT32_MAX || (M + BM - 1) / BM > 65535) return fail(HBMC_EINVAL, "grid too large");
+    return HBMC_OK;
+}
+
+}  // namespace
+
+extern "C" int mlp_gemm(int32_t dtype, int32_t layout, int32_t M, int32_t N, int32_t K, const void *A,
+                        int64_t lda, const void *B, int64_t ldb, float *C, int64_t ldc, int32_t nsplit,
+                        void *stream) {
+    if (!A || !B || !C) return fail(HBMC_EINVAL, "null argument");
+    int st = check_dims(M, N, K, nsplit);
+    if (st) return st;
+    Epi ep{};
+    ep.C = C;
+    ep.ldc = ldc;
+    ep.zstride = int64_t(M) * ldc;
+    return gemm_dtype<EPI_STORE>(dtype, layout, M, N, K, A, lda, B, ldb, nsplit, ep, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int mlp_linear_fwd(int32_t dtype, int32_t M, int32_t N, int32_t K, const void *X, const void *W,
+                              const float *bias, int32_t relu, void *Y, float *Yf, void *stream) {
+    if (!X || !W || !Y) return fail(HBMC_EINVAL, "null argument");
+    int st = check_dims(M, N, K, 1);
+    if (st) return st;
+    auto s = static_cast<hipStream_t>(stream);
+    if (M <= 4) {   // a few rows: bound by reading W once
+        const dim3 grid(unsigned((N + GV_COLS - 1) / GV_COLS));
+        if (dtype == MLP_BF16)
+            hipLaunchKernelGGL((k_gemv<uint16_t, 4>), grid, dim3(kThreads), 0, s, M, N, K,
+                               static_cast<const uint16_t *>(X), static_cast<const uint16_t *>(W), bias, relu,
+                               static_cast<uint16_t *>(Y), Yf);
+        else if (dtype == MLP_F32)
+            hipLaunchKernelGGL((k_gemv<float, 4>), grid, dim3(kThreads), 0, s, M, N, K, static_cast<const float *>(X),
+                               static_cast<const float *>(W), bias, relu, static_cast<float *>(Y), Yf);
+        else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+        HIP_TRY(hipGetLastError());
+        return HBMC_OK;
+    }
+    Epi ep{};
+    ep.bias = bias;
+    ep.relu = relu;
+    ep.Y = Y;
+    ep.Yf = Yf;
+    ep.ldc = N;
+    return gemm_dtype<EPI_BIAS_ACT>(dtype, MLP_NN, M, N, K, X, K, W, N, 1, ep, s);
+}
+
+extern "C" int mlp_linear_fwd_mse(int32_t dtype, int32_t M, int32_t N, int32_t K, const void *X, const void *W,
+                                  const float *bias, const void *T, float scale, void *dY, float *loss_part,
+                                  float *dbias_part, void *stream) {
+    if (!X || !W || !T || !dY || !loss_part || !dbias_part) return fail(HBMC_EINVAL, "null argument");
+    int st = check_dims(M, N, K, 1);
+    if (st) return st;
+    Epi ep{};
+    ep.bias = bias;
+    ep.T = T;
+    ep.scale = scale;
+    ep.Y = dY;
+    ep.ldc = N;
+    ep.loss_part = loss_part;
+    ep.dbias_part = dbias_part;
+    return gemm_dtype<EPI_MSE>(dtype, MLP_NN, M, N, K, X, K, W, N, 1, ep, static_cast<hipStream_t>(stream));
+}
+
+extern "C" int mlp_mse_parts(int32_t M, int32_t N, int64_t *loss_parts, int64_t *dbias_rows) {
+    if (!loss_parts || !dbias_rows || M < 1 || N < 1) return fail(HBMC_EINVAL, "bad argument");
+    *loss_parts = int64_t((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+    *dbias_rows = (M + BM - 1) / BM;
+    return HBMC_OK;
+}
+
+extern "C" int mlp_sum_rows(int64_t R, int64_t N, const float *src, int64_t ld, float *out, void *stream) {
+    if (!src || !out || R < 1 || N < 1 || ld < N) return fail(HBMC_EINVAL, "bad argument");
+    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for(N)), dim3(256), 0, static_cast<hipStream_t>(stream), R, N, src,
+                       ld, out);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_relu_bwd(int32_t dtype, int64_t n, const float *dh, const void *h, void *dz, float *dzf,
+                            void *stream) {
+    if (!dh || !h || !dz || n < 1) return fail(HBMC_EINVAL, "bad argument");
+    auto s = static_cast<hipStream_t>(stream);
+    if (dtype == MLP_BF16)
+        hipLaunchKernelGGL(k_relu_bwd<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, dh,
+                           static_cast<const uint16_t *>(h), static_cast<uint16_t *>(dz), dzf);
+    else if (dtype == MLP_F32)
+        hipLaunchKernelGGL(k_relu_bwd<float>, dim3(blocks_for(n)), dim3(256), 0, s, n, dh,
+                           static_cast<const float *>(h), static_cast<float *>(dz), dzf);
+    else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_adam(int32_t dtype, int64_t n, float *w, float *m, float *v, const float *g, void *wc,
+                        float lr, float beta1, float beta2, float eps, int32_t step, void *stream) {
+    if (!w || !m || !v || !g || n < 1 || step < 1) return fail(HBMC_EINVAL, "bad argument");
+    const float c1 = float(1.0 / (1.0 - std::pow(double(beta1), step)));
+    const float c2 = float(1.0 / (1.0 - std::pow(double(beta2), step)));
+    auto s = static_cast<hipStream_t>(stream);
+    if (dtype == MLP_BF16)
+        hipLaunchKernelGGL(k_adam<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, w, m, v, g,
+                           static_cast<uint16_t *>(wc), lr, beta1, beta2, eps, c1, c2);
+    else if (dtype == MLP_F32)
+        hipLaunchKernelGGL(k_adam<float>, dim3(blocks_for(n)), dim3(256), 0, s, n, w, m, v, g,
+                           static_cast<float *>(wc), lr, beta1, beta2, eps, c1, c2);
+    else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_cast(int32_t dtype, int64_t n, const float *src, void *dst, void *stream) {
+    if (!src || !dst || n < 1) return fail(HBMC_EINVAL, "bad argument");
+    auto s = static_cast<hipStream_t>(stream);
+    if (dtype == MLP_BF16)
+        hipLaunchKernelGGL(k_cast_f32<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, src,
+                           static_cast<uint16_t *>(dst));
+    else if (dtype == MLP_F32)
+        hipLaunchKernelGGL(k_cast_f32<float>, dim3(blocks_for(n)), dim3(256), 0, s, n, src, static_cast<float *>(dst));
+    else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_cast_f64(int32_t dtype, int64_t n, const double *src, double scale, void *dst, void *stream) {
+    if (!src || !dst || n < 1) return fail(HBMC_EINVAL, "bad argument");
+    auto s = static_cast<hipStream_t>(stream);
+    if (dtype == MLP_BF16)
+        hipLaunchKernelGGL(k_cast_f64<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, src, scale,
+                           static_cast<uint16_t *>(dst));
+    else if (dtype == MLP_F32)
+        hipLaunchKernelGGL(k_cast_f64<float>, dim3(blocks_for(n)), dim3(256), 0, s, n, src, scale,
+                           static_cast<float *>(dst));
+    else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_to_f64(int64_t n, const float *src, double scale, double *dst, void *stream) {
+    if (!src || !dst || n < 1) return fail(HBMC_EINVAL, "bad argument");
+    hipLaunchKernelGGL(k_to_f64, dim3(blocks_for(n)), dim3(256), 0, static_cast<hipStream_t>(stream), n, src, scale,
+                       dst);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_gaussian_rhs(int32_t N, const double *theta, double *b, void *stream) {
+    if (!theta || !b || N < 1) return fail(HBMC_EINVAL, "bad argument");
+    const double *t = theta;
+    hipLaunchKernelGGL(k_gaussian_rhs, dim3(blocks_for(int64_t(N) * N * N)), dim3(256), 0,
+                       static_cast<hipStream_t>(stream), N, t[0], t[1], t[2], t[3], t[4], t[5], t[6], t[7], t[8],
+                       t[9], t[10], t[11], b);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+extern "C" int mlp_combine(int32_t dtype, int32_t M, int64_t n, const void *G, int64_t rows, const int32_t *idx,
+                           const float *amp, float scale, void *T, void *stream) {
+    if (!G || !idx || !amp || !T || M < 1 || M > 65535 || n < 1 || rows < 1) return fail(HBMC_EINVAL, "bad argument");
+    auto s = static_cast<hipStream_t>(stream);
+    const dim3 grid(blocks_for(n), unsigned(M));
+    if (dtype == MLP_BF16)
+        hipLaunchKernelGGL(k_combine<uint16_t>, grid, dim3(256), 0, s, M, n, static_cast<const uint16_t *>(G), idx, amp,
+                           scale, static_cast<uint16_t *>(T));
+    else if (dtype == MLP_F32)
+        hipLaunchKernelGGL(k_combine<float>, grid, dim3(256), 0, s, M, n, static_cast<const float *>(G), idx, amp, scale,
+                           static_cast<float *>(T));
+    else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}

@@ -1,0 +1,197 @@
+"""GPU checks of the warm-start network's kernels (include/hbmc_mlp.h).
+
+Bars:
+- products C = A B in all three layouts, with and without a split over K:
+  inputs that bfloat16 holds exactly, so BF16 products are exact and only
+  the FP32 accumulation rounds: |C - C_ref| <= 1e-5 * (|A| |B|)_ij; FP32
+  inputs: the same bound;
+- loss and gradients of the network against the FP64 oracle on the same
+  weights: FP32 mode 1e-5 relative (norm of each parameter's gradient);
+  BF16 mode 1e-2 against the oracle that rounds weights, inputs,
+  activations, targets and backward signals to bfloat16 where the kernels
+  store them, and 5e-2 against the all-FP64 oracle (bfloat16 storage of the
+  activations alone moves the first layer's gradient by about 2 % on this
+  case, ReLU gates near zero flipping);
+- one Adam step against the published update: 1e-6 relative;
+- the Gaussian-source right-hand side against the input generator: 1e-12.
+"""
+import numpy as np
+import pytest
+
+from paper_1908_00741_amd import inputs
+from paper_1908_00741_amd import mlp
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _bf16_exact(rng, shape):
+    """Values with at most 8 significant bits, held exactly in bfloat16."""
+    return (rng.integers(-128, 128, shape) / 64.0).astype(np.float32)
+
+
+def _to_dtype(torch, a, dtype):
+    t = torch.from_numpy(np.ascontiguousarray(a, np.float32)).cuda()
+    if dtype == mlp.MLP_F32:
+        return t
+    out = torch.empty(a.shape, dtype=torch.int16, device="cuda")
+    mlp.cast(dtype, t, out)
+    return out
+
+
+@pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
+@pytest.mark.parametrize("layout", [mlp.MLP_NN, mlp.MLP_TN, mlp.MLP_NT], ids=["NN", "TN", "NT"])
+@pytest.mark.parametrize("M,N,K,split", [(70, 130, 45, 1), (64, 64, 32, 1), (5, 300, 1000, 3), (128, 33, 12, 1)])
+def test_gemm(torch, dtype, layout, M, N, K, split):
+    print(f"gemm dtype {dtype} layout {layout} {M}x{N}x{K} split {split}", flush=True)
+    rng = np.random.default_rng(M + N + K)
+    A = _bf16_exact(rng, (M, K))
+    B = _bf16_exact(rng, (K, N))
+    As = A.T.copy() if layout == mlp.MLP_TN else A
+    Bs = B.T.copy() if layout == mlp.MLP_NT else B
+    lda = As.shape[1]
+    ldb = Bs.shape[1]
+    Cd = torch.zeros((split, M, N), dtype=torch.float32, device="cuda")
+    mlp.gemm(dtype, layout, M, N, K, _to_dtype(torch, As, dtype), lda, _to_dtype(torch, Bs, dtype), ldb, Cd, N, split)
+    Cg = Cd.cpu().numpy().astype(np.float64).sum(axis=0)
+    ref = A.astype(np.float64) @ B.astype(np.float64)
+    bound = np.abs(A).astype(np.float64) @ np.abs(B).astype(np.float64)
+    assert np.all(np.abs(Cg - ref) <= 1e-5 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
+@pytest.mark.parametrize("M,N,K", [(1, 1000, 256), (3, 1024, 256), (4, 4104, 12), (5, 1000, 256), (70, 333, 45)])
+def test_linear_fwd(torch, dtype, M, N, K):
+    """Bias and ReLU epilogue, on both product paths (few rows: the
+    matrix-vector kernel; more: the tiled MFMA kernel)."""
+    rng = np.random.default_rng(M * 7 + N)
+    X = _bf16_exact(rng, (M, K))
+    W = _bf16_exact(rng, (K, N))
+    b = (rng.integers(-64, 64, N) / 32.0).astype(np.float32)
+    for relu in (0, 1):
+        Y = torch.empty((M, N), dtype=torch.int16 if dtype == mlp.MLP_BF16 else torch.float32, device="cuda")
+        Yf = torch.empty((M, N), dtype=torch.float32, device="cuda")
+        Xd, Wd, bd = _to_dtype(torch, X, dtype), _to_dtype(torch, W, dtype), torch.from_numpy(b).cuda()
+        mlp._ck("mlp_linear_fwd", mlp.lib().mlp_linear_fwd(dtype, M, N, K, mlp._p(Xd), mlp._p(Wd), mlp._p(bd), relu,
+                                                           mlp._p(Y), mlp._p(Yf), mlp._s()))
+        torch.cuda.synchronize()
+        ref = X.astype(np.float64) @ W.astype(np.float64) + b
+        if relu:
+            ref = np.maximum(ref, 0.0)
+        bound = np.abs(X).astype(np.float64) @ np.abs(W).astype(np.float64) + np.abs(b)
+        assert np.all(np.abs(Yf.cpu().numpy() - ref) <= 1e-5 * bound + 1e-30)
+
+
+def _net(rng, dims):
+    ps = []
+    for k in range(3):
+        b = 1.0 / np.sqrt(dims[k])
+        ps += [rng.uniform(-b, b, (dims[k], dims[k + 1])).astype(np.float32),
+               rng.uniform(-b, b, dims[k + 1]).astype(np.float32)]
+    return ps
+
+
+@pytest.mark.parametrize("dtype,tol", [(mlp.MLP_F32, 1e-5), (mlp.MLP_BF16, 1e-2)], ids=["f32", "bf16"])
+def test_gradients_against_oracle(torch, dtype, tol):
+    from oracle import mlp as omlp
+    print(f"mlp gradient check dtype {dtype}", flush=True)
+    rng = np.random.default_rng(11)
+    M, n = 40, 777
+    ps = _net(rng, [12, 256, 256, n])
+    theta = rng.uniform(-1, 1, (M, 12)).astype(np.float32)
+    target = rng.uniform(-1, 1, (M, n)).astype(np.float32)
+    net = mlp.MLP(n, dtype=dtype)
+    net.set_weights(ps)
+    tgt = _to_dtype(torch, target, dtype)
+    loss_parts = net.loss_and_grads(torch.from_numpy(theta).cuda(), tgt)
+    torch.cuda.synchronize()
+    loss = float(loss_parts.cpu().numpy().astype(np.float64).sum()) / (M * n)
+    grads = [g.cpu().numpy().astype(np.float64) for g in net.grad]
+    checks = []
+    if dtype == mlp.MLP_BF16:
+        # weights as the kernels read them (bfloat16), biases FP32
+        ref_ps = [omlp.bf16_round(p) if p.ndim == 2 else p.astype(np.float64) for p in ps]
+        checks.append((omlp.loss_and_grads(theta, target, ref_ps, store=omlp.bf16_round), tol))
+        checks.append((omlp.loss_and_grads(omlp.bf16_round(theta), omlp.bf16_round(target), ref_ps), 5e-2))
+    else:
+        checks.append((omlp.loss_and_grads(theta, target, [p.astype(np.float64) for p in ps]), tol))
+    for (L, gs), bar in checks:
+        assert abs(loss - L) <= bar * abs(L)
+        for k, (g, gr) in enumerate(zip(grads, gs)):
+            assert np.linalg.norm(g - gr) <= bar * np.linalg.norm(gr), (k, bar)
+
+
+def test_adam_step(torch):
+    from oracle import mlp as omlp
+    rng = np.random.default_rng(5)
+    n = 10007
+    w, m, v, g = [rng.uniform(-1, 1, n).astype(np.float32) for _ in range(4)]
+    v = np.abs(v)
+    dev = [torch.from_numpy(a.copy()).cuda() for a in (w, m, v, g)]
+    wc = torch.empty(n, dtype=torch.int16, device="cuda")
+    for step in (1, 7):
+        lib = mlp.lib()
+        mlp._ck("mlp_adam", lib.mlp_adam(mlp.MLP_BF16, n, mlp._p(dev[0]), mlp._p(dev[1]), mlp._p(dev[2]),
+                                         mlp._p(dev[3]), mlp._p(wc), 1e-3, 0.9, 0.999, 1e-8, step, mlp._s()))
+        w, m, v = omlp.adam(w.astype(np.float64), m.astype(np.float64), v.astype(np.float64),
+                            g.astype(np.float64), step)
+        for t, r in zip(dev[:3], (w, m, v)):
+            assert np.allclose(t.cpu().numpy(), r, rtol=1e-6, atol=1e-7)
+        w, m, v = [t.cpu().numpy() for t in dev[:3]]
+    # the compute copy is the rounded master copy
+    wc32 = (wc.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(wc32.astype(np.float64), omlp.bf16_round(dev[0].cpu().numpy()))
+
+
+def test_gaussian_rhs(torch):
+    N = 20
+    theta = inputs.sample_sources(3, 12)
+    for th in theta:
+        b = torch.empty(N ** 3, dtype=torch.float64, device="cuda")
+        mlp.gaussian_rhs(N, th, b)
+        ref = inputs.gaussian_sources_rhs(N, th)
+        assert np.abs(b.cpu().numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+def test_combine(torch):
+    rng = np.random.default_rng(9)
+    G = rng.uniform(-1, 1, (10, 333)).astype(np.float32)
+    Gd = torch.from_numpy(G).cuda()
+    idx = rng.integers(0, 10, (7, 4))
+    amp = rng.uniform(-1, 1, (7, 4)).astype(np.float32)
+    out = torch.empty((7, 333), dtype=torch.float32, device="cuda")
+    mlp.combine(mlp.MLP_F32, Gd, idx, amp, 0.5, out)
+    ref = 0.5 * np.einsum("mq,mqi->mi", amp.astype(np.float64), G[idx].astype(np.float64))
+    assert np.abs(out.cpu().numpy() - ref).max() <= 1e-6
+    with pytest.raises(ValueError):
+        mlp.combine(mlp.MLP_F32, Gd, idx + 10, amp, 1.0, out)
+
+
+def test_warm_start_gain(torch):
+    """A network trained on combinations of 2000 single-source solutions of
+    a 16^3 problem family gives CG start vectors that save iterations on 24
+    unseen source configurations at the same stopping test, and makes none of
+    them take more than one extra iteration."""
+    from paper_1908_00741_amd import warmstart
+    print("warm start gain 16^3", flush=True)
+    ws = warmstart.WarmStart(N=16, sigma=0.5, seed=10, device="cuda", tol=1e-8)
+    G, S, W, gen = ws.generate_single(500)
+    tr = ws.train_combined(G, S, W, steps=3000, batch=128, lr=1e-3, log_every=1000)
+    assert tr["curve"][-1][1] < 0.5 * tr["curve"][0][1]
+    test = inputs.sample_sources(24, 12)
+    rows = []
+    for th in test:
+        _, s0 = ws.solve(th)
+        _, s1 = ws.solve(th, ws.predict(th))
+        rows.append((s0.iters, s1.iters, s0.true_rel_res, s1.true_rel_res))
+    r = np.array(rows)
+    print("iterations x0=0", r[:, 0].mean(), "warm", r[:, 1].mean(), flush=True)
+    assert r[:, 2].max() < 1e-7 and r[:, 3].max() < 1e-7
+    assert r[:, 1].mean() <= r[:, 0].mean() - 0.5
+    assert np.all(r[:, 1] <= r[:, 0] + 1)

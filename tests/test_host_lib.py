@@ -18,6 +18,17 @@ from paper_1908_00741_amd import hbmc, inputs
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 
+def test_exports_every_declared_mlp_symbol():
+    from paper_1908_00741_amd import mlp
+    header = open(os.path.join(ROOT, "include", "hbmc_mlp.h")).read()
+    header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
+    declared = set(re.findall(r"\b(mlp_[a-z0-9_]+)\s*\(", header))
+    assert declared == set(mlp.SYMBOLS)
+    L = mlp.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
 def test_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "hbmc.h")).read()
     header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
