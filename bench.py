@@ -10,7 +10,10 @@ and one ic0_apply per iteration, plus the permutations in and out).  The
 headline value is the ic0_apply rate in algorithmic GB/s: bytes the
 substitutions must move (factor values and indices read once, diaginv, r
 in, z out, y out and back) divided by the apply's measured time, with the
-256 MB last-level cache flushed before each timed apply.
+caches cold before each timed apply: 1 GiB is written (evicting the apply's
+data from L2 and the 256 MB MALL), then a different 1 GiB is read (so the
+MALL holds clean lines and the apply's misses do not pay for write-backs of
+the flush).  The write-only flush time is reported too.
 
 Prints one JSON line on stdout; everything else goes to stderr.
 """
@@ -41,7 +44,8 @@ def apply_bytes(n: int, nnz_lower: int, s_v: int = 8, s_d: int = 8, s_y: int = 8
 
 
 PROFILE = os.path.join(ROOT, "profiles", "ic0_apply_diffusion128.md")
-PROFILED_SOURCES = ["paper_1908_00741_amd/csrc/substitution.hip",
+PROFILED_SOURCES = ["paper_1908_00741_amd/csrc/sweep.h",
+                    "paper_1908_00741_amd/csrc/sweep_bs8.hip",
                     "paper_1908_00741_amd/csrc/factor.cpp",
                     "paper_1908_00741_amd/csrc/hbmc_internal.h"]
 
@@ -122,30 +126,45 @@ def main() -> int:
     r = torch.from_numpy(r_np).to(dev)
     z = torch.empty_like(r)
     flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+    flush2 = torch.zeros(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB, read
+    sink = torch.empty((), dtype=torch.float64, device=dev)
     for _ in range(5):
         hbmc.ic0_apply(f, r, z)
     torch.cuda.synchronize()
 
-    def timed(reps, cold):
+    def evict(i, clean):
+        flush.fill_(i & 255)
+        if clean:
+            torch.sum(flush2, dim=0, out=sink)
+
+    def timed(reps, mode, fn=lambda: hbmc.ic0_apply(f, r, z)):
         ts = []
         for i in range(reps):
-            if cold:
-                flush.fill_(i & 255)
+            if mode != "warm":
+                evict(i, mode == "cold")
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
-            hbmc.ic0_apply(f, r, z)
+            fn()
             e1.record(stream)
             e1.synchronize()
             ts.append(e0.elapsed_time(e1))
         return np.array(ts)
 
-    t_cold = timed(args.apply_reps, True)
-    t_warm = timed(args.apply_reps, False)
-    log(f"[bench] apply cold: median {np.median(t_cold) * 1e3:.1f} us, "
-        f"warm: median {np.median(t_warm) * 1e3:.1f} us")
+    t_cold = timed(args.apply_reps, "cold")
+    t_dirty = timed(args.apply_reps, "dirty")
+    t_warm = timed(args.apply_reps, "warm")
+    log(f"[bench] apply cold: median {np.median(t_cold) * 1e3:.1f} us, after a write-only flush: "
+        f"{np.median(t_dirty) * 1e3:.1f} us, warm: median {np.median(t_warm) * 1e3:.1f} us")
     gbs_cold = B / (np.median(t_cold) * 1e-3) / 1e9
     gbs_warm = B / (np.median(t_warm) * 1e-3) / 1e9
+    # a plain copy of 128 MB under the same cold state, for context
+    src = torch.zeros(1 << 24, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    t_copy = timed(20, "cold", lambda: dst.copy_(src))
+    copy_gbs = 2 * src.numel() * 8 / (np.median(t_copy) * 1e-3) / 1e9
+    del src, dst
+    log(f"[bench] cold 128 MB copy: {copy_gbs:.0f} GB/s")
 
     # ---- ICCG steps --------------------------------------------------------
     b = torch.from_numpy(b_np).to(dev)
@@ -222,8 +241,10 @@ def main() -> int:
                      "unit": "GB/s", "frac": round(gbs_cold / HBM_PEAK_GBS, 4),
                      "traffic": measured_traffic(),
                      "kernel": "ic0_apply (2*n_colors-1 phase launches)",
-                     "bytes_per_launch": B},
+                     "bytes_per_launch": B,
+                     "cold_copy_gbs": round(copy_gbs, 1)},
         "apply": {"median_us_cold": round(float(np.median(t_cold)) * 1e3, 2),
+                  "median_us_after_write_only_flush": round(float(np.median(t_dirty)) * 1e3, 2),
                   "median_us_warm": round(float(np.median(t_warm)) * 1e3, 2),
                   "gbs_warm": round(gbs_warm, 2), "reps": args.apply_reps},
         "iccg": {"ms_to_1e-7": round(ms_per_step, 3), "iterations": st.iters,

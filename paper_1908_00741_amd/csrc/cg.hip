@@ -335,6 +335,54 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
     store_part<NR>(part, np, K, pq);
 }
 
+// Several right-hand sides: p = z + beta p_old first (elementwise), so that
+// the product below gathers p alone at the columns a row couples to (with
+// [n][K] vectors the gathered rows are K times longer and miss the caches;
+// forming p on the fly would gather z and p_old both).
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, const double *__restrict__ z,
+                                                     const double *__restrict__ p_old, double *__restrict__ p_new,
+                                                     const CgState *st, const int32_t *alldone) {
+    if (*alldone) return;
+    const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
+    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    if (q0 >= K || c.done) return;
+    const double beta = c.beta;
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) {
+            const int64_t e = r.row * K + r.q;
+            p_new[e] = z[e] + beta * p_old[e];
+        }
+    }
+}
+
+// q = A p for p formed by k_update_p; part partials of (p, q)
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, const double *__restrict__ p,
+                                                     double *__restrict__ q, double *part, int64_t np,
+                                                     const CgState *st, const int32_t *alldone) {
+    if (*alldone) return;
+    const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
+    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    const bool live = q0 < K && !c.done;
+    auto pv = [=](int64_t i) { return p[i]; };
+    double pq = 0.0;
+#pragma unroll 1
+    for (int mm = 0; mm < NR; ++mm) {
+        const Elem r = elem<NR>(m.n, K, mm);
+        if (!r.wave_on || !__any(live)) continue;
+        const double qi = spmv_row_with(m, pv, r, K);
+        if (r.valid && live) {
+            const int64_t e = r.row * K + r.q;
+            q[e] = qi;
+            pq += p[e] * qi;
+        }
+    }
+    store_part<NR>(part, np, K, pq);
+}
+
 // sigma = (p, Ap); alpha = rho / sigma
 __global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t np, int K, Sys sys,
                                                     CgState *st, int32_t *ndone, int32_t *alldone) {
@@ -533,7 +581,7 @@ inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock -
 
 // One CG iteration (everything after the first preconditioning step); the
 // direction is read from p[parity] and written to p[1 - parity].
-//   q = A p, p = z + beta p_old  |  alpha = rho / (p, q)  |
+//   q = A p, p = z + beta p_old (two kernels for several right-hand sides)  |  alpha = rho / (p, q)  |
 //   x += alpha p, r -= alpha q, z = M^-1 r, partials of ||r||^2 and (r, z)  |
 //   stopping test, beta
 int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipStream_t s,
@@ -542,7 +590,12 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
     const int K = w.K;
     const unsigned nst = unsigned(f->nsys) * K;
     double *p_old = w.p[parity], *p_new = w.p[1 - parity];
-    VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+    if (K == 1) {
+        VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+    } else {
+        VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);
+        VEC_LAUNCH(k_spmv_dot, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+    }
     hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st, w.ndone,
                        w.alldone);
     HIP_TRY(hipGetLastError());
