@@ -123,14 +123,30 @@ __device__ inline double rhs_sum(double v) {
 }
 
 // Elements of the vector kernels.  Vectors are [n][K] (the K right-hand
-// sides of a row adjacent).  A workgroup covers one part of kPartRows rows
-// for NR right-hand sides (group blockIdx.y), in NR rounds m; in a round a
-// wavefront covers 64/NR consecutive rows of one 64-row group, lane j taking
-// row j / NR and right-hand side j % NR.  In the last part (n need not be a
-// multiple of it) a wavefront whose rows all lie past n does no work; in the
-// wavefront that holds row n - 1 all lanes stay active (the SpMV broadcasts
-// slot metadata from any lane), the lanes past n computing on row n - 1 and
-// storing nothing.  Every thread still reaches the workgroup's reduction.
+// sides of a row adjacent).  A wavefront covers 64/NR consecutive rows (of
+// one 64-row group) for NR right-hand sides (group blockIdx.y), lane j taking
+// row j / NR and right-hand side j % NR: with NR = K its loads and stores are
+// whole contiguous rows.  A part of kPartRows rows is split over SB(NR)
+// workgroups (blockIdx.x = part * SB + sub-block), each covering its share in
+// ROUNDS(NR) rounds.  In the last part (n need not be a multiple of it) a
+// wavefront whose rows all lie past n does no work; in the wavefront that
+// holds row n - 1 all lanes stay active (the SpMV broadcasts slot metadata
+// from any lane), the lanes past n computing on row n - 1 and storing
+// nothing.  Every thread still reaches the workgroup's reduction.
+__host__ __device__ constexpr int sub_blocks(int NR) { return NR <= 4 ? 1 : NR / 4; }
+
+// The workgroup's place in the row order.  Workgroups are dealt to the
+// chip's 8 XCDs (each with its own L2) in turn; renumbering them so that XCD
+// x gets a contiguous range of the row order keeps rows whose neighbours
+// overlap (the gathers of the SpMV) in the same L2.
+constexpr int kXcds = 8;
+__device__ inline int64_t logical_block() {
+    const int64_t nb = gridDim.x, b = blockIdx.x;
+    const int64_t x = b % kXcds, i = b / kXcds, q = nb / kXcds, r = nb % kXcds;
+    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+__host__ __device__ constexpr int rounds(int NR) { return NR / sub_blocks(NR); }
+
 struct Elem {
     int64_t row;     // this lane's row
     int64_t rc;      // the row it reads (row, or n - 1 past the end)
@@ -144,9 +160,12 @@ struct Elem {
 template <int NR>
 __device__ inline Elem elem(int64_t n, int K, int m) {
     if (NR == 1) K = 1;   // one right-hand side: compile-time stride
+    constexpr int SB = sub_blocks(NR);
     Elem r;
     const int wave = threadIdx.x >> 6, j = threadIdx.x & 63;
-    const int64_t base = int64_t(blockIdx.x) * kPartRows + m * (kPartRows / NR) + wave * (kLanes / NR);
+    const int64_t lb = logical_block();
+    const int64_t part = lb / SB, sb = lb % SB;
+    const int64_t base = part * kPartRows + sb * (kPartRows / SB) + m * (kPartRows / NR) + wave * (kLanes / NR);
     const int q0 = int(blockIdx.y) * NR + j % NR;
     r.row = base + j / NR;
     r.g = __builtin_amdgcn_readfirstlane(int(base >> 6));
@@ -158,6 +177,10 @@ __device__ inline Elem elem(int64_t n, int K, int m) {
     r.e = r.rc * K + r.q;
     return r;
 }
+
+// the part of the workgroup (for the system tables)
+template <int NR>
+__device__ inline int64_t part_of_block() { return logical_block() / sub_blocks(NR); }
 
 // One row of y = A x for one right-hand side, x(i) given by an accessor of
 // element indices; all 64 lanes of the wavefront must be active.  The
@@ -197,7 +220,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Mat m, int K, const double *__r
                                                  double *__restrict__ y) {
     if (NR == 1) K = 1;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on) continue;
         const double v = spmv_row_with(m, [=](int64_t i) { return x[i]; }, r, K);
@@ -219,7 +242,7 @@ __device__ inline void store_part(double *part, int64_t np, int K, double v) {
 #pragma unroll
         for (int k = 0; k < kBlock / kLanes; ++k) t += sh[k][threadIdx.x];
         const int q = int(blockIdx.y) * NR + threadIdx.x;
-        if (q < K) part[q * np + blockIdx.x] = t;
+        if (q < K) part[q * np + logical_block()] = t;
     }
     __syncthreads();
 }
@@ -232,7 +255,7 @@ __global__ void __launch_bounds__(kBlock) k_init_r(int64_t n, int K, const doubl
     if (NR == 1) K = 1;
     double sb = 0.0, sr = 0.0;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(n, K, mm);
         if (r.valid) {
             const int64_t e = r.row * K + r.q;
@@ -254,12 +277,12 @@ __device__ inline void count_done(int32_t *ndone, int32_t *alldone, int total) {
 
 // per (system s, right-hand side q) = blockIdx.x = s * K + q: ||b||^2,
 // ||r0||^2, the state, and whether it is already done
-__global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t np, int K, Sys sys,
+__global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t np, int pmul, int K, Sys sys,
                                                    CgState *st, double tol, int32_t maxit, double *hist,
                                                    int32_t *ndone, int32_t *alldone) {
     const int b = blockIdx.x, s = b / K, q = b % K;
-    const double bb = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
-    const double rr = sys_total(part + (K + q) * np, sys.parts, sys.nc, s, 1);
+    const double bb = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
+    const double rr = sys_total(part + (K + q) * np, sys.parts, sys.nc, s, pmul);
     if (threadIdx.x) return;
     CgState &c = st[b];
     c.bb = bb;
@@ -284,7 +307,7 @@ __global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, int K, const doubl
     if (NR == 1) K = 1;
     double s = 0.0;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(n, K, mm);
         if (r.valid) {
             const int64_t e = r.row * K + r.q;
@@ -295,10 +318,10 @@ __global__ void __launch_bounds__(kBlock) k_init_p(int64_t n, int K, const doubl
     store_part<NR>(part, np, K, s);
 }
 
-__global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, int64_t np, int K, Sys sys,
+__global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, int64_t np, int pmul, int K, Sys sys,
                                                   CgState *st) {
     const int b = blockIdx.x, s = b / K, q = b % K;
-    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
     if (threadIdx.x == 0) { st[b].rho = t; st[b].beta = 0.0; }
 }
 
@@ -313,14 +336,14 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
     if (*alldone) return;
     if (NR == 1) K = 1;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
     const bool live = q0 < K && !c.done;          // a part lies in one system
     if (NR == 1 && !live) return;                  // workgroup-uniform with one right-hand side
     const double beta = c.beta;
     auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
     double pq = 0.0;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on || !__any(live)) continue;
         const double pi = pv(r.e);
@@ -345,11 +368,11 @@ __global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, 
                                                      const CgState *st, const int32_t *alldone) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
     if (q0 >= K || c.done) return;
     const double beta = c.beta;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(n, K, mm);
         if (r.valid) {
             const int64_t e = r.row * K + r.q;
@@ -365,12 +388,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, cons
                                                      const CgState *st, const int32_t *alldone) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[blockIdx.x]) * K + (q0 < K ? q0 : K - 1)];
+    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
     const bool live = q0 < K && !c.done;
     auto pv = [=](int64_t i) { return p[i]; };
     double pq = 0.0;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on || !__any(live)) continue;
         const double qi = spmv_row_with(m, pv, r, K);
@@ -384,12 +407,12 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, cons
 }
 
 // sigma = (p, Ap); alpha = rho / sigma
-__global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t np, int K, Sys sys,
+__global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t np, int pmul, int K, Sys sys,
                                                     CgState *st, int32_t *ndone, int32_t *alldone) {
     const int b = blockIdx.x, s = b / K, q = b % K;
     CgState &c = st[b];
     if (c.done) return;
-    const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
     if (threadIdx.x) return;
     c.sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
@@ -436,17 +459,17 @@ __global__ void __launch_bounds__(kBlock) k_resid(int64_t n, int K, const double
     if (NR == 1) K = 1;
     double s = 0.0;
 #pragma unroll 1
-    for (int mm = 0; mm < NR; ++mm) {
+    for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(n, K, mm);
         if (r.valid) { const int64_t e = r.row * K + r.q; const double d = b[e] - q[e]; s += d * d; }
     }
     store_part<NR>(part, np, K, s);
 }
 
-__global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, int64_t np, int K, Sys sys,
+__global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, int64_t np, int pmul, int K, Sys sys,
                                                     double *out) {
     const int b = blockIdx.x, s = b / K, q = b % K;
-    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, 1);
+    const double t = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
     if (threadIdx.x == 0) out[b] = t;
 }
 
@@ -508,6 +531,15 @@ Sys sys_of(const hbmc_factor_s *f) {
 
 std::atomic<uint64_t> g_uid{1};
 
+// Right-hand sides per wavefront of the vector kernels for K right-hand
+// sides: K rounded up to a power of two, at most 64 (1 for one).
+inline int vec_nr(int K) {
+    if (K == 1) return 1;
+    int nr = 4;
+    while (nr < K && nr < 64) nr *= 2;
+    return nr;
+}
+
 // Workspace, for K right-hand sides: b, x, r, z, p (two, used in turn), q
 // in HBMC order ([n_pad][K]); partial sums per part (two slots) and per
 // (tile, sub-tile) (two); the CG state of each (system, right-hand side);
@@ -517,7 +549,8 @@ struct Work {
     double *bb, *xb, *r, *z, *p[2], *q, *part_g, *part_rr, *part_rz, *resid, *hist;
     CgState *st;
     int32_t *ndone, *alldone;
-    int64_t np;        // parts
+    int64_t np;        // part partial slots per right-hand side (parts * pmul)
+    int32_t pmul;      // sub-blocks per part of the vector kernels
     int64_t ptiles;    // tile partial slots per right-hand side
     int32_t K, nr;     // right-hand sides; right-hand sides per wavefront
     int32_t hist_len;
@@ -534,7 +567,7 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
     const int64_t tmul = K == 1 ? 1 : kMaxTile;
     const int64_t ptiles = f->tile_base[f->nc] * tmul;
     const size_t vec = up(size_t(f->n_pad) * K * sizeof(double));
-    const size_t pg = up(size_t(2) * K * np * sizeof(double));
+    const size_t pg = up(size_t(2) * K * np * sub_blocks(64) * sizeof(double));
     const size_t tp = up(size_t(ptiles) * K * sizeof(double));
     const size_t sts = up(size_t(f->nsys) * K * sizeof(CgState));
     const size_t res = up(size_t(f->nsys) * K * sizeof(double));
@@ -555,7 +588,8 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
         w->alldone = w->ndone + 1; a += 256;
         w->resid = reinterpret_cast<double *>(b + a);
         w->hist_len = kHistLen;
-        w->np = np;
+        w->pmul = sub_blocks(vec_nr(K));
+        w->np = np * w->pmul;
         w->K = K;
         w->nr = rhs_tile(f, K);
         w->ptiles = f->tile_base[f->nc] * w->nr;
@@ -563,20 +597,23 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
     return total;
 }
 
-// Launches a vector kernel template on the workgroups (parts of n_pad
-// rows, groups of NR right-hand sides): NR = 1 for one right-hand side, 4
-// for up to four, else 8.
-#define VEC_LAUNCH(kernel, n_pad, K, s, ...)                                                  \
-    do {                                                                                      \
-        const unsigned np_ = unsigned(((n_pad) + kPartRows - 1) / kPartRows);                 \
-        if ((K) == 1)                                                                         \
-            hipLaunchKernelGGL(kernel<1>, dim3(np_), dim3(kBlock), 0, s, __VA_ARGS__);        \
-        else if ((K) <= 4)                                                                    \
-            hipLaunchKernelGGL(kernel<4>, dim3(np_), dim3(kBlock), 0, s, __VA_ARGS__);        \
-        else                                                                                  \
-            hipLaunchKernelGGL(kernel<8>, dim3(np_, unsigned(((K) + 7) / 8)), dim3(kBlock), 0, \
-                               s, __VA_ARGS__);                                               \
+// Launches a vector kernel template on the workgroups (parts of n_pad rows
+// times sub-blocks, groups of NR right-hand sides).
+#define VEC_LAUNCH(kernel, n_pad, K, s, ...)                                                      \
+    do {                                                                                          \
+        const int nr_ = vec_nr(K);                                                                \
+        const unsigned px_ = unsigned(((n_pad) + kPartRows - 1) / kPartRows * sub_blocks(nr_));   \
+        const dim3 g_(px_, unsigned(((K) + nr_ - 1) / nr_));                                      \
+        switch (nr_) {                                                                            \
+            case 1: hipLaunchKernelGGL(kernel<1>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;    \
+            case 4: hipLaunchKernelGGL(kernel<4>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;    \
+            case 8: hipLaunchKernelGGL(kernel<8>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;    \
+            case 16: hipLaunchKernelGGL(kernel<16>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+            case 32: hipLaunchKernelGGL(kernel<32>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+            default: hipLaunchKernelGGL(kernel<64>, g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+        }                                                                                         \
     } while (0)
+
 inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock - 1) / kBlock)); }
 
 // One CG iteration (everything after the first preconditioning step); the
@@ -596,7 +633,7 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
         VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);
         VEC_LAUNCH(k_spmv_dot, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     }
-    hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st, w.ndone,
+    hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, w.ndone,
                        w.alldone);
     HIP_TRY(hipGetLastError());
     const ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz};
@@ -757,7 +794,7 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     else hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, x, w.xb);
     VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
     VEC_LAUNCH(k_init_r, n, K, s, n, K, w.bb, w.q, w.r, w.part_g, w.np);
-    hipLaunchKernelGGL(k_fin_init, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st, tol, maxit,
+    hipLaunchKernelGGL(k_fin_init, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, tol, maxit,
                        history ? w.hist : nullptr, w.ndone, w.alldone);
     HIP_TRY(hipGetLastError());
     int32_t hd[2] = {0, 0};
@@ -768,7 +805,7 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
         int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr, K);
         if (st) return st;
         VEC_LAUNCH(k_init_p, n, K, s, n, K, w.r, w.z, w.p[0], w.part_g, w.np);
-        hipLaunchKernelGGL(k_fin_rho, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.st);
+        hipLaunchKernelGGL(k_fin_rho, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st);
         HIP_TRY(hipGetLastError());
         hipGraphExec_t exec = nullptr;
         if (use_graph && (st = get_graph(f, A, m, w, work, check, history, &exec))) return st;
@@ -789,7 +826,7 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
                        perm, w.xb, x);
     VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
     VEC_LAUNCH(k_resid, n, K, s, n, K, w.bb, w.q, w.part_g, w.np);
-    hipLaunchKernelGGL(k_fin_resid, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, K, sys, w.resid);
+    hipLaunchKernelGGL(k_fin_resid, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.resid);
     HIP_TRY(hipGetLastError());
     std::vector<CgState> hs(nst);
     std::vector<double> rt(nst);

@@ -138,3 +138,21 @@ def test_batch_with_multi_rhs(torch):
             assert st.iters == st1.iters, (s, q)
             assert np.linalg.norm(X[sys_ptr[s]: sys_ptr[s + 1], q] - x1) <= 1e-12 * np.linalg.norm(x1)
 
+
+
+@pytest.mark.parametrize("K", [16, 32, 40, 64])
+def test_solve_many_rhs_vector_tiles(torch, K):
+    """K from 16 to 64 right-hand sides: the vector kernels cover whole rows
+    per wavefront (16, 32, 64 per wavefront; 40 leaves lanes idle); every
+    column equals its single-vector solve."""
+    print(f"many-rhs solve K {K}", flush=True)
+    A = inputs.diffusion3d(10, 1.0, 8)
+    B = np.stack([inputs.uniform_rhs(A.n, 900 + q) for q in range(K)], axis=1)
+    sv = hbmc.Solver.setup(A, 4, 16)
+    X, sts = _solve_cols(torch, sv, B, tol=1e-9)
+    for q in range(0, K, 7):
+        x1, st1 = sv.solve(_dev(torch, B[:, q]), tol=1e-9)
+        x1 = x1.cpu().numpy()
+        assert sts[q].iters == st1.iters, q
+        assert np.linalg.norm(X[:, q] - x1) <= 1e-12 * np.linalg.norm(x1), q
+    assert all(st.status == hbmc.HBMC_OK and st.true_rel_res < 1e-8 for st in sts)
