@@ -86,6 +86,33 @@ int mlp_to_f64(int64_t n, const float *src, double scale, double *dst, void *str
 int mlp_combine(int32_t dtype, int32_t M, int64_t n, const void *G, int64_t rows, const int32_t *idx,
                 const float *amp, float scale, void *T, void *stream);
 
+/* ---- the whole network ------------------------------------------------------
+ * W[3]: the layers' weights in the compute type, W[k] [in_k][out_k] with
+ * (in, out) = (n_in, hidden), (hidden, hidden), (hidden, n_out); b[3]: FP32
+ * biases (entries may be NULL).  W and b are HOST arrays of device pointers.
+ * work: device scratch of mlp_workspace_bytes(dtype, M, ...) bytes, valid
+ * for batches of up to M rows of that network. */
+int mlp_workspace_bytes(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, size_t *bytes);
+
+/* Y (compute type) and/or Yf (FP32) [M][n_out] = the network at X [M][n_in]
+ * (compute type); ReLU after the two hidden layers. */
+int mlp_forward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                const void *const *W, const float *const *b, void *Y, float *Yf, void *work, size_t work_bytes,
+                void *stream);
+
+/* Gradients of L = mean over [M][n_out] of (MLP(X) - T)^2 into grad[6] (FP32
+ * device arrays shaped like W1, b1, W2, b2, W3, b3; grad is a HOST array of
+ * device pointers); *loss (device FP32, optional) = M n_out L. */
+int mlp_backward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                 const void *T, const void *const *W, const float *const *b, float *const *grad, float *loss,
+                 void *work, size_t work_bytes, void *stream);
+
+/* mlp_adam on count parameter arrays (host arrays of device pointers; wc
+ * may be NULL or hold NULL entries). */
+int mlp_adam_step(int32_t dtype, int32_t count, const int64_t *sizes, float *const *w, float *const *m,
+                  float *const *v, const float *const *g, void *const *wc, float lr, float beta1, float beta2,
+                  float eps, int32_t step, void *stream);
+
 /* Right-hand side of the warm-start workload: b (FP64 [N^3], index
  * x + N y + N^2 z) = sum over q < 4 of a_q exp(-|p - c_q|^2 / (2 w_q^2)) at
  * the cell centres p, c_q = o_q + s_q d_q on the four body diagonals of the

@@ -199,6 +199,22 @@ __global__ void k_sum_rows(int64_t R, int64_t N, const float *__restrict__ src, 
     out[j] = s;
 }
 
+// *out = sum of src[0 .. n) by one workgroup, in a fixed order
+__global__ void __launch_bounds__(1024) k_total(int64_t n, const float *__restrict__ src, float *__restrict__ out) {
+    __shared__ double sh[16];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += src[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int k = 0; k < 16; ++k) t += sh[k];
+        *out = float(t);
+    }
+}
+
 // dz = dh * (h > 0): dz in the compute type and, when dzf is set, FP32
 template <typename T>
 __global__ void k_relu_bwd(int64_t n, const float *__restrict__ dh, const T *__restrict__ h, T *__restrict__ dz,
@@ -554,5 +570,129 @@ extern "C" int mlp_combine(int32_t dtype, int32_t M, int64_t n, const void *G, i
                            static_cast<float *>(T));
     else return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
     HIP_TRY(hipGetLastError());
+    return HBMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// The whole network: forward, backward (with the loss) and the Adam step,
+// composed from the kernels above.
+// ---------------------------------------------------------------------------
+namespace {
+
+struct NetWork {   // workspace carve-up for a batch of M rows
+    void *h1, *h2, *dY, *dz;
+    float *loss, *dbias, *part, *dh, *dzf;
+    int64_t nloss, nrows;
+    int split;
+};
+
+size_t elem_size(int dtype) { return dtype == MLP_BF16 ? 2 : 4; }
+
+size_t net_layout(int dtype, int M, int n_in, int hid, int n_out, NetWork *w, void *base) {
+    (void)n_in;
+    auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
+    const int64_t nloss = int64_t((M + BM - 1) / BM) * ((n_out + BN - 1) / BN);
+    const int64_t nrows = (M + BM - 1) / BM;
+    const int split = std::max(1, std::min(1024, n_out / 1024));
+    const size_t es = elem_size(dtype);
+    const size_t sz[9] = {up(size_t(M) * hid * es), up(size_t(M) * hid * es), up(size_t(M) * n_out * es),
+                          up(size_t(M) * hid * es), up(size_t(nloss) * 4), up(size_t(nrows) * n_out * 4),
+                          up(size_t(split) * M * hid * 4), up(size_t(M) * hid * 4), up(size_t(M) * hid * 4)};
+    size_t total = 0;
+    for (size_t v : sz) total += v;
+    if (w && base) {
+        auto *b = static_cast<uint8_t *>(base);
+        void **ptrs[9] = {&w->h1, &w->h2, &w->dY, &w->dz, reinterpret_cast<void **>(&w->loss),
+                          reinterpret_cast<void **>(&w->dbias), reinterpret_cast<void **>(&w->part),
+                          reinterpret_cast<void **>(&w->dh), reinterpret_cast<void **>(&w->dzf)};
+        size_t a = 0;
+        for (int i = 0; i < 9; ++i) { *ptrs[i] = b + a; a += sz[i]; }
+        w->nloss = nloss;
+        w->nrows = nrows;
+        w->split = split;
+    }
+    return total;
+}
+
+int check_net(int dtype, int M, int n_in, int hid, int n_out, const void *const *W, const float *const *b) {
+    if (dtype != MLP_BF16 && dtype != MLP_F32) return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
+    if (M < 1 || n_in < 1 || hid < 1 || n_out < 1 || M > 65535 * BM) return fail(HBMC_EINVAL, "bad sizes");
+    if (!W || !b || !W[0] || !W[1] || !W[2]) return fail(HBMC_EINVAL, "null weights");
+    return HBMC_OK;
+}
+
+#define MLP_TRY(call)           \
+    do {                        \
+        int st_ = (call);       \
+        if (st_) return st_;    \
+    } while (0)
+
+}  // namespace
+
+extern "C" int mlp_workspace_bytes(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out,
+                                   size_t *bytes) {
+    if (!bytes || M < 1 || n_in < 1 || hidden < 1 || n_out < 1) return fail(HBMC_EINVAL, "bad argument");
+    *bytes = net_layout(dtype, M, n_in, hidden, n_out, nullptr, nullptr);
+    return HBMC_OK;
+}
+
+extern "C" int mlp_forward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                           const void *const *W, const float *const *b, void *Y, float *Yf, void *work,
+                           size_t work_bytes, void *stream) {
+    MLP_TRY(check_net(dtype, M, n_in, hidden, n_out, W, b));
+    if (!X || (!Y && !Yf) || !work) return fail(HBMC_EINVAL, "null argument");
+    if (work_bytes < net_layout(dtype, M, n_in, hidden, n_out, nullptr, nullptr))
+        return fail(HBMC_EINVAL, "workspace too small");
+    NetWork w{};
+    net_layout(dtype, M, n_in, hidden, n_out, &w, work);
+    // the output in the compute type goes to Y, or to the dY slot when only FP32 is wanted
+    MLP_TRY(mlp_linear_fwd(dtype, M, hidden, n_in, X, W[0], b[0], 1, w.h1, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd(dtype, M, hidden, hidden, w.h1, W[1], b[1], 1, w.h2, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd(dtype, M, n_out, hidden, w.h2, W[2], b[2], 0, Y ? Y : w.dY, Yf, stream));
+    return HBMC_OK;
+}
+
+extern "C" int mlp_backward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                            const void *T, const void *const *W, const float *const *b, float *const *grad,
+                            float *loss, void *work, size_t work_bytes, void *stream) {
+    MLP_TRY(check_net(dtype, M, n_in, hidden, n_out, W, b));
+    if (!X || !T || !grad || !work) return fail(HBMC_EINVAL, "null argument");
+    for (int i = 0; i < 6; ++i)
+        if (!grad[i]) return fail(HBMC_EINVAL, "null gradient %d", i);
+    if (work_bytes < net_layout(dtype, M, n_in, hidden, n_out, nullptr, nullptr))
+        return fail(HBMC_EINVAL, "workspace too small");
+    NetWork w{};
+    net_layout(dtype, M, n_in, hidden, n_out, &w, work);
+    auto s = static_cast<hipStream_t>(stream);
+    const int h = hidden, n = n_out;
+    MLP_TRY(mlp_linear_fwd(dtype, M, h, n_in, X, W[0], b[0], 1, w.h1, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd(dtype, M, h, h, w.h1, W[1], b[1], 1, w.h2, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd_mse(dtype, M, n, h, w.h2, W[2], b[2], T, 2.0f / (float(M) * float(n)), w.dY, w.loss,
+                               w.dbias, stream));
+    if (loss) {
+        hipLaunchKernelGGL(k_total, dim3(1), dim3(1024), 0, s, w.nloss, w.loss, loss);
+        HIP_TRY(hipGetLastError());
+    }
+    MLP_TRY(mlp_sum_rows(w.nrows, n, w.dbias, n, grad[5], stream));                          // db3
+    MLP_TRY(mlp_gemm(dtype, MLP_TN, h, n, M, w.h2, h, w.dY, n, grad[4], n, 1, stream));        // h2^T dY
+    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, n, w.dY, n, W[2], n, w.part, h, w.split, stream));   // dY W3^T
+    MLP_TRY(mlp_sum_rows(w.split, int64_t(M) * h, w.part, int64_t(M) * h, w.dh, stream));
+    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h2, w.dz, w.dzf, stream));
+    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[3], stream));                                    // db2
+    MLP_TRY(mlp_gemm(dtype, MLP_TN, h, h, M, w.h1, h, w.dz, h, grad[2], h, 1, stream));        // h1^T dz2
+    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, h, w.dz, h, W[1], h, w.dh, h, 1, stream));           // dz2 W2^T
+    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h1, w.dz, w.dzf, stream));
+    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[1], stream));                                    // db1
+    MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, grad[0], h, 1, stream));     // x^T dz1
+    return HBMC_OK;
+}
+
+extern "C" int mlp_adam_step(int32_t dtype, int32_t count, const int64_t *sizes, float *const *w, float *const *m,
+                             float *const *v, const float *const *g, void *const *wc, float lr, float beta1,
+                             float beta2, float eps, int32_t step, void *stream) {
+    if (count < 1 || !sizes || !w || !m || !v || !g) return fail(HBMC_EINVAL, "null argument");
+    for (int i = 0; i < count; ++i)
+        MLP_TRY(mlp_adam(dtype, sizes[i], w[i], m[i], v[i], g[i], wc ? wc[i] : nullptr, lr, beta1, beta2, eps,
+                         step, stream));
     return HBMC_OK;
 }

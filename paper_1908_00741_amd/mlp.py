@@ -21,7 +21,7 @@ MLP_NN, MLP_TN, MLP_NT = 0, 1, 2
 
 SYMBOLS = ("mlp_gemm", "mlp_linear_fwd", "mlp_linear_fwd_mse", "mlp_mse_parts", "mlp_sum_rows",
            "mlp_relu_bwd", "mlp_adam", "mlp_cast", "mlp_cast_f64", "mlp_to_f64", "mlp_gaussian_rhs",
-           "mlp_combine")
+           "mlp_combine", "mlp_workspace_bytes", "mlp_forward", "mlp_backward", "mlp_adam_step")
 
 _ready = False
 
@@ -43,6 +43,10 @@ def lib():
         L.mlp_to_f64.argtypes = [i64, P, f64, P, P]
         L.mlp_gaussian_rhs.argtypes = [i32, P, P, P]
         L.mlp_combine.argtypes = [i32, i32, i64, P, i64, P, P, f32, P, P]
+        L.mlp_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, P]
+        L.mlp_forward.argtypes = [i32, i32, i32, i32, i32, P, P, P, P, P, P, C.c_size_t, P]
+        L.mlp_backward.argtypes = [i32, i32, i32, i32, i32, P, P, P, P, P, P, P, C.c_size_t, P]
+        L.mlp_adam_step.argtypes = [i32, i32, P, P, P, P, P, P, f32, f32, f32, f32, i32, P]
         _ready = True
     return L
 
@@ -158,21 +162,19 @@ class MLP:
     def _buffers(self, M):
         import torch
         if M not in self._bufs:
-            d, td = self.device, _torch_dtype(self.dtype)
             n_in, h, _, n = self.dims
-            nlp, nrows = C.c_int64(), C.c_int64()
-            _ck("mlp_mse_parts", lib().mlp_mse_parts(M, n, C.byref(nlp), C.byref(nrows)))
-            split = max(1, min(1024, n // 1024))
+            nb = C.c_size_t(0)
+            _ck("mlp_workspace_bytes", lib().mlp_workspace_bytes(self.dtype, M, n_in, h, n, C.byref(nb)))
             self._bufs[M] = dict(
-                x=torch.empty((M, n_in), dtype=td, device=d),
-                h1=torch.empty((M, h), dtype=td, device=d), h2=torch.empty((M, h), dtype=td, device=d),
-                dY=torch.empty((M, n), dtype=td, device=d),
-                loss=torch.empty(nlp.value, dtype=torch.float32, device=d),
-                dbias=torch.empty((nrows.value, n), dtype=torch.float32, device=d),
-                split=split, part=torch.empty((split, M, h), dtype=torch.float32, device=d),
-                dh=torch.empty((M, h), dtype=torch.float32, device=d),
-                dz=torch.empty((M, h), dtype=td, device=d), dzf=torch.empty((M, h), dtype=torch.float32, device=d))
+                x=torch.empty((M, n_in), dtype=_torch_dtype(self.dtype), device=self.device),
+                work=torch.empty(max(nb.value, 256), dtype=torch.uint8, device=self.device),
+                loss=torch.empty(1, dtype=torch.float32, device=self.device))
         return self._bufs[M]
+
+    def _ptrs(self):
+        W = (C.c_void_p * 3)(*[t.data_ptr() for t in self.comp[0::2]])
+        b = (C.c_void_p * 3)(*[t.data_ptr() for t in self.master[1::2]])
+        return W, b
 
     def load_input(self, theta, stream=None):
         """theta: FP32 device tensor [M][12] -> the compute-type input."""
@@ -188,50 +190,32 @@ class MLP:
         n_in, h, _, n = self.dims
         if "yf" not in B:
             B["yf"] = torch.empty((M, n), dtype=torch.float32, device=self.device)
-            B["y"] = torch.empty((M, n), dtype=_torch_dtype(self.dtype), device=self.device)
-        W1, b1, W2, b2, W3, b3 = self.comp[0], self.master[1], self.comp[2], self.master[3], self.comp[4], self.master[5]
-        L, s = lib(), _s(stream)
-        _ck("mlp_linear_fwd", L.mlp_linear_fwd(self.dtype, M, h, n_in, _p(B["x"]), _p(W1), _p(b1), 1, _p(B["h1"]), None, s))
-        _ck("mlp_linear_fwd", L.mlp_linear_fwd(self.dtype, M, h, h, _p(B["h1"]), _p(W2), _p(b2), 1, _p(B["h2"]), None, s))
-        _ck("mlp_linear_fwd", L.mlp_linear_fwd(self.dtype, M, n, h, _p(B["h2"]), _p(W3), _p(b3), 0, _p(B["y"]),
-                                               _p(B["yf"]), s))
+        W, b = self._ptrs()
+        _ck("mlp_forward", lib().mlp_forward(self.dtype, M, n_in, h, n, _p(B["x"]), W, b, None, _p(B["yf"]),
+                                             _p(B["work"]), B["work"].numel(), _s(stream)))
         return B["yf"]
 
     def loss_and_grads(self, theta, target, stream=None):
         """Mean squared error against target (compute type [M][n]) and the
-        gradients of every parameter into self.grad.  Returns the loss
-        partials (device); loss = their sum / (M n)."""
+        gradients of every parameter into self.grad.  Returns a device
+        tensor holding M n times the loss."""
         M = theta.shape[0]
         B = self.load_input(theta, stream)
         n_in, h, _, n = self.dims
-        dt, L, s = self.dtype, lib(), _s(stream)
-        W1, W2, W3 = self.comp[0], self.comp[2], self.comp[4]
-        b1, b2, b3 = self.master[1], self.master[3], self.master[5]
-        gW1, gb1, gW2, gb2, gW3, gb3 = self.grad
-        _ck("mlp_linear_fwd", L.mlp_linear_fwd(dt, M, h, n_in, _p(B["x"]), _p(W1), _p(b1), 1, _p(B["h1"]), None, s))
-        _ck("mlp_linear_fwd", L.mlp_linear_fwd(dt, M, h, h, _p(B["h1"]), _p(W2), _p(b2), 1, _p(B["h2"]), None, s))
-        _ck("mlp_linear_fwd_mse", L.mlp_linear_fwd_mse(dt, M, n, h, _p(B["h2"]), _p(W3), _p(b3), _p(target),
-                                                       2.0 / (M * n), _p(B["dY"]), _p(B["loss"]), _p(B["dbias"]), s))
-        sum_rows(B["dbias"].shape[0], n, B["dbias"], n, gb3, stream)
-        gemm(dt, MLP_TN, h, n, M, B["h2"], h, B["dY"], n, gW3, n, 1, stream)            # h2^T dY
-        S = B["split"]
-        gemm(dt, MLP_NT, M, h, n, B["dY"], n, W3, n, B["part"], h, S, stream)            # dY W3^T
-        sum_rows(S, M * h, B["part"], M * h, B["dh"], stream)
-        _ck("mlp_relu_bwd", L.mlp_relu_bwd(dt, M * h, _p(B["dh"]), _p(B["h2"]), _p(B["dz"]), _p(B["dzf"]), s))
-        sum_rows(M, h, B["dzf"], h, gb2, stream)
-        gemm(dt, MLP_TN, h, h, M, B["h1"], h, B["dz"], h, gW2, h, 1, stream)             # h1^T dz2
-        gemm(dt, MLP_NT, M, h, h, B["dz"], h, W2, h, B["dh"], h, 1, stream)              # dz2 W2^T
-        _ck("mlp_relu_bwd", L.mlp_relu_bwd(dt, M * h, _p(B["dh"]), _p(B["h1"]), _p(B["dz"]), _p(B["dzf"]), s))
-        sum_rows(M, h, B["dzf"], h, gb1, stream)
-        gemm(dt, MLP_TN, n_in, h, M, B["x"], n_in, B["dz"], h, gW1, h, 1, stream)        # x^T dz1
+        W, b = self._ptrs()
+        g = (C.c_void_p * 6)(*[t.data_ptr() for t in self.grad])
+        _ck("mlp_backward", lib().mlp_backward(self.dtype, M, n_in, h, n, _p(B["x"]), _p(target), W, b, g,
+                                               _p(B["loss"]), _p(B["work"]), B["work"].numel(), _s(stream)))
         return B["loss"]
 
     def adam_step(self, opt: Adam, stream=None):
         self.step_no += 1
-        L, s = lib(), _s(stream)
-        for w, c, m, v, g in zip(self.master, self.comp, self.m, self.v, self.grad):
-            _ck("mlp_adam", L.mlp_adam(self.dtype, w.numel(), _p(w), _p(m), _p(v), _p(g), _p(c), opt.lr,
-                                       opt.beta1, opt.beta2, opt.eps, self.step_no, s))
+        k = len(self.master)
+        arr = lambda ts: (C.c_void_p * k)(*[t.data_ptr() for t in ts])
+        sizes = (C.c_int64 * k)(*[t.numel() for t in self.master])
+        _ck("mlp_adam_step", lib().mlp_adam_step(self.dtype, k, sizes, arr(self.master), arr(self.m), arr(self.v),
+                                                 arr(self.grad), arr(self.comp), opt.lr, opt.beta1, opt.beta2,
+                                                 opt.eps, self.step_no, _s(stream)))
 
     def state(self):
         """Host copies of the master weights, moments and step (checkpoint)."""
