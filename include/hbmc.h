@@ -138,6 +138,19 @@ void hbmc_order_destroy(hbmc_order_t *h);
 int ic0_factor(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
                const double *val, int32_t precision, double shift, hbmc_factor_t **out);
 
+/* ssor_factor: the SSOR splitting of Abar in the same layout (Section 2: the
+ * Gauss-Seidel and SOR iterations are substitutions of the same kind):
+ * L = the strictly lower part of Abar itself (no update, no fill) and
+ * d_i = abar_ii / omega, 0 < omega < 2.  Then (D + L) D^-1 (D + L^T) is
+ * (2 - omega) times the inverse of the SSOR matrix; omega = 1 gives
+ * symmetric Gauss-Seidel.  The handle is used as an IC(0) factor is:
+ * ic0_apply applies ((D + L) D^-1 (D + L^T))^-1, iccg_solve runs
+ * SSOR-preconditioned CG, and hbmc_smooth runs SOR / SSOR sweeps.
+ * precision, errors and ownership as for ic0_factor (HBMC_EINVAL also for
+ * omega outside (0, 2)). */
+int ssor_factor(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
+                const double *val, int32_t precision, double omega, hbmc_factor_t **out);
+
 /* Host copy of the factor, for checking: d[n_pad] and the strictly lower
  * part of L in CSR over HBMC indices (lower_rowptr[n_pad+1], lower_col and
  * lower_val sized by *lower_nnz).  Call with lower_col == NULL to get
@@ -146,6 +159,20 @@ int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lower_rowptr,
                        int32_t *lower_col, double *lower_val, int64_t *lower_nnz);
 
 int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes);
+
+/* Host copies of the device images (hbmc_factor_device_bytes /
+ * hbmc_matrix_device_bytes bytes), for checking; HBMC_EINVAL if bytes is
+ * smaller. */
+int hbmc_factor_image(const hbmc_factor_t *f, void *host, size_t bytes);
+int hbmc_matrix_image(const hbmc_matrix_t *m, void *host, size_t bytes);
+
+/* Host threads used by the setup (hbmc_order*, ic0_factor, ssor_factor,
+ * hbmc_matrix_create): permutation, factorization (the colors in turn, the
+ * level-1 blocks of a color in parallel, Section 4.2) and layout packing
+ * (tiles in parallel chunks joined in order).  0 (the default) = all
+ * hardware threads.  Results are the same bits for every setting.  A
+ * process-wide setting; HBMC_EINVAL for threads < 0. */
+int hbmc_set_num_threads(int32_t threads);
 
 /* Kernel that runs the substitution phases (same results, different speed):
  * HBMC_KERNEL_SWEEP -- one wavefront per 64 lanes walks all bs steps of its
@@ -244,6 +271,34 @@ int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);
 int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
                int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
                hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
+
+/* ---- smoother ----------------------------------------------------------------
+ * hbmc_smooth: sweeps steps of  x <- x + c M^-1 (b - Abar x)  (Section 2: the
+ * GS and SOR steps are substitutions; Section 3: under an equivalent
+ * reordering they give the same iterates, permuted).
+ *   mode HBMC_SMOOTH_SYMMETRIC: M^-1 = both substitutions (as ic0_apply);
+ *     with an ssor_factor handle one step is one forward and one backward
+ *     SOR sweep over the HBMC order (c = 2 - omega; symmetric Gauss-Seidel
+ *     for omega = 1); with an ic0_factor handle it is the IC(0) smoother
+ *     (c = 1).
+ *   mode HBMC_SMOOTH_FORWARD: M^-1 = the forward substitution only,
+ *     (D + L)^-1 (c = 1); with an ssor_factor handle one step is one forward
+ *     SOR sweep (Gauss-Seidel for omega = 1).
+ * b, x: device FP64 in HBMC order [n_pad][nrhs] (hbmc_to_hbmc maps from the
+ * caller's numbering); dummy entries of b and x must be 0 and stay 0.  x is
+ * updated in place and must not alias b or work.  sweeps >= 0 (0 leaves x
+ * as it is).  work: device scratch of hbmc_smooth_workspace_bytes(f, nrhs),
+ * 256-byte aligned.  A is the matrix the factor was made from (same
+ * ordering).  Asynchronous on stream.
+ * Errors: HBMC_EINVAL, HBMC_ENOTREADY, HBMC_EHIP. */
+#define HBMC_SMOOTH_SYMMETRIC 0
+#define HBMC_SMOOTH_FORWARD 1
+
+int hbmc_smooth_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);
+
+int hbmc_smooth(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
+                int32_t nrhs, int32_t sweeps, int32_t mode, void *work, size_t work_bytes,
+                void *stream);
 
 /* Residual history (of system 0 in a batch) of the last iccg_solve that ran
  * with record_history on this workspace: hist[k] = ||r_k|| / ||b|| for k = 0..count-1 (k = 0 is the

@@ -58,6 +58,9 @@ def lib():
         L.orc_spmv.argtypes = [i64, P, P, P, P, P]
         L.orc_spmv.restype = None
         L.orc_pcg.argtypes = [i64, P, P, P, P, P, i32, P, P, f64, i32, P, P]
+        L.orc_sor_sweep.argtypes = [i64, P, P, P, P, P, f64, i32]
+        L.orc_sor_sweep.restype = None
+        L.orc_ssor_split.argtypes = [i64, P, P, P, f64, P, P]
         _lib = L
     return _lib
 
@@ -232,6 +235,31 @@ def spmv(Ab, x) -> np.ndarray:
     y = np.empty(Ab.n, np.float64)
     lib().orc_spmv(Ab.n, _p(rp), _p(ci), _p(v), _p(x), _p(y))
     return y
+
+
+def sor_sweeps(Ab, b, x0, omega: float = 1.0, sweeps: int = 1, symmetric: bool = True) -> np.ndarray:
+    """sweeps SOR steps in Ab's numbering: each a forward sweep, followed by
+    a backward sweep when symmetric (SSOR; symmetric Gauss-Seidel at
+    omega = 1)."""
+    rp, ci, v = _csr(Ab)
+    b = np.ascontiguousarray(b, np.float64)
+    x = np.array(x0, np.float64, copy=True)
+    for _ in range(sweeps):
+        lib().orc_sor_sweep(Ab.n, _p(rp), _p(ci), _p(v), _p(b), _p(x), float(omega), 0)
+        if symmetric:
+            lib().orc_sor_sweep(Ab.n, _p(rp), _p(ci), _p(v), _p(b), _p(x), float(omega), 1)
+    return x
+
+
+def ssor_split(Ab, omega: float = 1.0):
+    """(d, fac) of the SSOR splitting, usable with apply and pcg."""
+    rp, ci, v = _csr(Ab)
+    d = np.empty(Ab.n, np.float64)
+    fac = np.empty_like(v)
+    st = lib().orc_ssor_split(Ab.n, _p(rp), _p(ci), _p(v), float(omega), _p(d), _p(fac))
+    if st:
+        raise OracleError("orc_ssor_split", st)
+    return d, fac
 
 
 @dataclass

@@ -400,6 +400,47 @@ void orc_apply_f32(int64_t n, const int64_t *rp, const int32_t *ci, const double
     free(zf);
 }
 
+/* ------------------------------------------------------------------------
+ * SOR sweep (Section 2: the GS and SOR iterations, textbook form), in place,
+ * one unknown at a time in the given numbering:
+ *     x_i <- (1 - omega) x_i + omega (b_i - sum_{j != i} a_ij x_j) / a_ii ,
+ * with i ascending (backward == 0) or descending (backward != 0); every x_j
+ * read is the current value (already updated for the unknowns visited
+ * earlier in the sweep).  Sums run over the row's entries in ascending
+ * column order.  omega = 1 is Gauss-Seidel; a forward sweep followed by a
+ * backward sweep is one SSOR (symmetric GS) step.
+ * ---------------------------------------------------------------------- */
+void orc_sor_sweep(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                   const double *b, double *x, double omega, int32_t backward)
+{
+    for (int64_t t = 0; t < n; t++) {
+        int64_t i = backward ? n - 1 - t : t;
+        double s = b[i], aii = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) {
+            if (ci[p] == i) aii = v[p];
+            else s = s - v[p] * x[ci[p]];
+        }
+        x[i] = (1.0 - omega) * x[i] + omega * (s / aii);
+    }
+}
+
+/* The SSOR splitting as a "factor" for orc_apply / orc_pcg: d_i = a_ii /
+ * omega and the strictly lower entries of A unchanged, so that
+ * (D + L) D^-1 (D + L^T) = (2 - omega) M_SSOR with
+ * M_SSOR = (D_A + omega L)(omega (2 - omega))^-1 D_A^-1 (D_A + omega L^T). */
+int orc_ssor_split(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
+                   double omega, double *d, double *fac)
+{
+    if (!(omega > 0.0 && omega < 2.0)) return ORC_EINVAL;
+    memcpy(fac, v, (size_t)rp[n] * sizeof(double));
+    for (int64_t i = 0; i < n; i++) {
+        int64_t pd = csr_find(rp, ci, (int32_t)i, (int32_t)i);
+        if (pd < 0) return ORC_EDIAG;
+        d[i] = v[pd] / omega;
+    }
+    return ORC_OK;
+}
+
 /* y = A x, rows in order, entries in ascending column order. */
 void orc_spmv(int64_t n, const int64_t *rp, const int32_t *ci, const double *v,
               const double *x, double *y)

@@ -473,7 +473,27 @@ __global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, int64_t 
     if (threadIdx.x == 0) out[b] = t;
 }
 
+// r = b - A x (the residual of a smoothing step)
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_smooth_r(Mat m, int K, const double *__restrict__ b,
+                                                     const double *__restrict__ x, double *__restrict__ r) {
+    if (NR == 1) K = 1;
+#pragma unroll 1
+    for (int mm = 0; mm < rounds(NR); ++mm) {
+        const Elem e = elem<NR>(m.n, K, mm);
+        if (!e.wave_on) continue;
+        const double ax = spmv_row_with(m, [=](int64_t i) { return x[i]; }, e, K);
+        if (e.valid) r[e.row * K + e.q] = b[e.row * K + e.q] - ax;
+    }
+}
+
 // element-wise kernels over [rows][K]
+__global__ void __launch_bounds__(kBlock) k_axpy(int64_t n, double c, const double *__restrict__ z,
+                                                 double *__restrict__ x) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e < n) x[e] += c * z[e];
+}
+
 __global__ void __launch_bounds__(kBlock) k_to_hbmc(int64_t n_pad, int K, const int32_t *__restrict__ iperm,
                                                     const double *__restrict__ v,
                                                     double *__restrict__ vb) {
@@ -863,5 +883,59 @@ extern "C" int iccg_history(const void *work, size_t work_bytes, const hbmc_fact
     auto s = static_cast<hipStream_t>(stream);
     HIP_TRY(hipMemcpyAsync(hist, work, size_t(count) * sizeof(double), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
+    return HBMC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Smoothing (Section 2: the GS and SOR iterations are substitutions with the
+// triangles of A).  One step is  x <- x + c M^-1 (b - A x):  with the SSOR
+// splitting (ssor_factor) and both substitutions it is one forward and one
+// backward SOR sweep (c = 2 - omega; symmetric Gauss-Seidel at omega = 1),
+// with the forward substitution alone one forward SOR sweep (c = 1); with an
+// IC(0) factor it is the IC smoother (c = 1).
+// ---------------------------------------------------------------------------
+namespace {
+size_t smooth_vec_bytes(const hbmc_factor_s *f, int K) {
+    return (size_t(f->n_pad) * K * sizeof(double) + 255) & ~size_t(255);
+}
+}  // namespace
+
+extern "C" int hbmc_smooth_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes) {
+    if (!f || !bytes) return fail(HBMC_EINVAL, "null argument");
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
+    *bytes = 2 * smooth_vec_bytes(f, nrhs);
+    return HBMC_OK;
+}
+
+extern "C" int hbmc_smooth(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
+                           int32_t nrhs, int32_t sweeps, int32_t mode, void *work, size_t work_bytes,
+                           void *stream) {
+    clear_error();
+    int st = check_ready(f, nrhs);
+    if (st) return st;
+    if (!A || !b || !x || !work) return fail(HBMC_EINVAL, "null argument");
+    if (!A->dev) return fail(HBMC_ENOTREADY, "matrix not uploaded");
+    if (A->n_pad != f->n_pad || A->n != f->n) return fail(HBMC_EINVAL, "matrix and factor sizes differ");
+    if (sweeps < 0) return fail(HBMC_EINVAL, "sweeps = %d", sweeps);
+    if (mode != HBMC_SMOOTH_SYMMETRIC && mode != HBMC_SMOOTH_FORWARD)
+        return fail(HBMC_EINVAL, "unknown smoothing mode %d", mode);
+    if (static_cast<const void *>(b) == static_cast<const void *>(x)) return fail(HBMC_EINVAL, "x must not alias b");
+    const int K = nrhs;
+    const size_t vb = smooth_vec_bytes(f, K);
+    if (work_bytes < 2 * vb) return fail(HBMC_EINVAL, "workspace too small (%zu < %zu)", work_bytes, 2 * vb);
+    if (reinterpret_cast<uintptr_t>(work) % 256) return fail(HBMC_EINVAL, "workspace not 256-byte aligned");
+    auto s = static_cast<hipStream_t>(stream);
+    double *r = at<double>(work, 0), *z = at<double>(work, vb);
+    const Mat m = mat_of(A);
+    const bool fwd = mode == HBMC_SMOOTH_FORWARD;
+    const double c = fwd ? 1.0 : f->smooth_scale;
+    const int64_t ne = f->n_pad * K;
+    for (int32_t k = 0; k < sweeps; ++k) {
+        VEC_LAUNCH(k_smooth_r, f->n_pad, K, s, m, K, b, x, r);
+        HIP_TRY(hipGetLastError());
+        if ((st = apply_launch(f, r, z, s, nullptr, nullptr, K, fwd))) return st;
+        hipLaunchKernelGGL(k_axpy, dim3(grid_elems(ne)), dim3(kBlock), 0, s, ne, c, z, x);
+        HIP_TRY(hipGetLastError());
+    }
     return HBMC_OK;
 }

@@ -6,18 +6,22 @@
 // Compiled without floating-point contraction (-ffp-contract=off).
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <new>
 
 #include "hbmc_internal.h"
+#include "parallel.h"
 
 using namespace hbmc;
 
 namespace {
 
+constexpr int64_t kGrain = 16384;   // rows per chunk of the parallel setup, at least
+
 struct Csr {
-    std::vector<int64_t> rp;
-    std::vector<int32_t> ci;
-    std::vector<double> v;
+    RawVec<int64_t> rp;
+    RawVec<int32_t> ci;
+    RawVec<double> v;
 };
 
 // Abar in HBMC numbering, rows sorted by column, dummy rows = identity.
@@ -30,22 +34,63 @@ Csr permute(const hbmc_order_s &o, const int64_t *rp, const int32_t *ci, const d
     }
     a.ci.resize(a.rp.back());
     a.v.resize(a.rp.back());
-    std::vector<std::pair<int32_t, double>> row;
-    for (int64_t r = 0; r < o.n_pad; ++r) {
-        const int32_t i = o.iperm[r];
-        int64_t at = a.rp[r];
-        if (i < 0) {
-            a.ci[at] = int32_t(r);
-            a.v[at] = 1.0;
-            continue;
+    parallel_chunks(o.n_pad, chunks_for(o.n_pad, kGrain), [&](int64_t lo, int64_t hi, int) {
+        std::vector<std::pair<int32_t, double>> row;
+        for (int64_t r = lo; r < hi; ++r) {
+            const int32_t i = o.iperm[r];
+            int64_t at = a.rp[r];
+            if (i < 0) {
+                a.ci[at] = int32_t(r);
+                a.v[at] = 1.0;
+                continue;
+            }
+            row.clear();
+            for (int64_t p = rp[i]; p < rp[i + 1]; ++p) row.emplace_back(o.perm[ci[p]], v ? v[p] : 0.0);
+            std::sort(row.begin(), row.end(),
+                      [](const auto &x, const auto &y) { return x.first < y.first; });
+            for (const auto &e : row) { a.ci[at] = e.first; a.v[at] = e.second; ++at; }
         }
-        row.clear();
-        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) row.emplace_back(o.perm[ci[p]], v ? v[p] : 0.0);
-        std::sort(row.begin(), row.end(),
-                  [](const auto &x, const auto &y) { return x.first < y.first; });
-        for (const auto &e : row) { a.ci[at] = e.first; a.v[at] = e.second; ++at; }
-    }
+    });
     return a;
+}
+
+// Where the rows of Abar sit in the HBMC layout: color starts and the
+// level-1 block size bs * w (a color's rows are whole level-1 blocks).
+struct Levels {
+    const std::vector<int64_t> &color_start;
+    int64_t l1;
+    int w;
+};
+
+// The strictly lower pattern of Abar (row pointers); checks that no
+// coupling joins two level-1 blocks of one color or two lanes of one
+// level-1 block (Section 4.2: the blocks of a color are independent), which
+// the parallel factorization relies on.
+int lower_pattern(const Csr &a, int64_t n, const Levels &lv, std::vector<int64_t> &lrp) {
+    lrp.assign(n + 1, 0);
+    for (size_t c = 0; c + 1 < lv.color_start.size(); ++c) {
+        const int64_t r0 = lv.color_start[c], r1 = lv.color_start[c + 1];
+        const int chunks = chunks_for(r1 - r0, kGrain);
+        std::vector<int64_t> bad(chunks, -1);
+        parallel_chunks(r1 - r0, chunks, [&](int64_t lo, int64_t hi, int ch) {
+            for (int64_t t = lo; t < hi; ++t) {
+                const int64_t i = r0 + t;
+                int64_t cnt = 0;
+                for (int64_t p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) {
+                    const int64_t k = a.ci[p];
+                    if (k >= r0 && ((k - r0) / lv.l1 != t / lv.l1 || (i - k) % lv.w != 0) && bad[ch] < 0)
+                        bad[ch] = i;
+                    ++cnt;
+                }
+                lrp[i + 1] = cnt;
+            }
+        });
+        for (int64_t x : bad)
+            if (x >= 0)
+                return fail(HBMC_EINVAL, "internal: a coupling of row %lld crosses level-1 blocks", (long long)x);
+    }
+    for (int64_t i = 0; i < n; ++i) lrp[i + 1] += lrp[i];
+    return HBMC_OK;
 }
 
 // IC(0), row by row: for each row i and each lower entry (i, k) in
@@ -53,19 +98,18 @@ Csr permute(const hbmc_order_s &o, const int64_t *rp, const int32_t *ci, const d
 // lower pattern of rows i and k; then d_i = a_ii - sum_{m<i} L_im^2 / d_m.
 // This is the same arithmetic, term for term and in the same order, as the
 // right-looking elimination with overwriting, organised by rows so that
-// each row is finished before the next starts.
-int ic0_rows(const Csr &a, int64_t n, double shift, std::vector<int64_t> &lrp,
+// each row is finished before the next starts.  A row needs only rows of
+// earlier colors and earlier rows of its own level-1 block, so the colors
+// run in turn and the level-1 blocks of a color in parallel (each block's
+// rows in order): the same arithmetic as one row after another.
+int ic0_rows(const Csr &a, int64_t n, double shift, const Levels &lv, std::vector<int64_t> &lrp,
              std::vector<int32_t> &lcol, std::vector<double> &lval, std::vector<double> &d) {
-    lrp.assign(n + 1, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        int64_t cnt = 0;
-        for (int64_t p = a.rp[i]; p < a.rp[i + 1] && a.ci[p] < i; ++p) ++cnt;
-        lrp[i + 1] = lrp[i] + cnt;
-    }
+    int st = lower_pattern(a, n, lv, lrp);
+    if (st) return st;
     lcol.resize(lrp[n]);
     lval.resize(lrp[n]);
     d.assign(n, 0.0);
-    for (int64_t i = 0; i < n; ++i) {
+    auto row = [&](int64_t i) -> bool {
         double aii = 0.0;
         int64_t q = lrp[i];
         for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
@@ -86,10 +130,47 @@ int ic0_rows(const Csr &a, int64_t n, double shift, std::vector<int64_t> &lrp,
         }
         double s = aii * (1.0 + shift);
         for (int64_t p = lrp[i]; p < lrp[i + 1]; ++p) s = s - lval[p] * lval[p] / d[lcol[p]];
-        if (!(s > 0.0) || !std::isfinite(s))
-            return fail(HBMC_EBREAKDOWN, "IC(0) pivot %lld is not > 0 (%g)", (long long)i, s);
         d[i] = s;
+        return s > 0.0 && std::isfinite(s);
+    };
+    for (size_t c = 0; c + 1 < lv.color_start.size(); ++c) {
+        const int64_t r0 = lv.color_start[c], r1 = lv.color_start[c + 1];
+        const int64_t blocks = (r1 - r0) / lv.l1;
+        const int chunks = chunks_for(blocks, std::max<int64_t>(1, kGrain / lv.l1));
+        std::vector<int64_t> first_bad(chunks, -1);
+        parallel_chunks(blocks, chunks, [&](int64_t lo, int64_t hi, int ch) {
+            for (int64_t b = lo; b < hi; ++b)
+                for (int64_t i = r0 + b * lv.l1; i < r0 + (b + 1) * lv.l1; ++i)
+                    if (!row(i) && (first_bad[ch] < 0 || i < first_bad[ch])) first_bad[ch] = i;
+        });
+        int64_t bad = -1;
+        for (int64_t x : first_bad)
+            if (x >= 0 && (bad < 0 || x < bad)) bad = x;
+        if (bad >= 0)
+            return fail(HBMC_EBREAKDOWN, "IC(0) pivot %lld is not > 0 (%g)", (long long)bad, d[bad]);
     }
+    return HBMC_OK;
+}
+
+// The SSOR splitting (Section 2: the GS and SOR steps are substitutions
+// with the triangles of A itself): L = strict lower triangle of Abar, copied
+// without any update, and d_i = a_ii / omega.  With these, the
+// preconditioner (D + L) D^-1 (D + L^T) is (2 - omega) times the inverse of
+// the SSOR matrix, and omega = 1 gives symmetric Gauss-Seidel.
+int ssor_rows(const Csr &a, int64_t n, double omega, const Levels &lv, std::vector<int64_t> &lrp,
+              std::vector<int32_t> &lcol, std::vector<double> &lval, std::vector<double> &d) {
+    int st = lower_pattern(a, n, lv, lrp);
+    if (st) return st;
+    lcol.resize(lrp[n]);
+    lval.resize(lrp[n]);
+    d.assign(n, 0.0);
+    parallel_for(n, kGrain, [&](int64_t i) {
+        int64_t q = lrp[i];
+        for (int64_t p = a.rp[i]; p < a.rp[i + 1]; ++p) {
+            if (a.ci[p] < i) { lcol[q] = a.ci[p]; lval[q] = a.v[p]; ++q; }
+            else if (a.ci[p] == i) d[i] = a.v[p] / omega;
+        }
+    });
     return HBMC_OK;
 }
 
@@ -112,22 +193,27 @@ size_t add_packed(ImageBuilder &im, const Packed &p, bool f32, PackedOffsets &o)
 
 }  // namespace
 
-int Packed::add_group(const std::vector<const Couplings *> &lanes, int64_t limit, int budget) {
+int Packed::add_group(const std::vector<CouplingSpan> &lanes, int64_t limit, int budget) {
     const int nl = int(lanes.size());
     // every coupling (lane j, column c) proposes the strided base c - j
     struct Entry { int64_t key; int lane; int idx; };
-    std::vector<Entry> all;
-    for (int j = 0; j < nl; ++j)
-        if (lanes[j])
-            for (int t = 0; t < int(lanes[j]->size()); ++t)
-                all.push_back({int64_t((*lanes[j])[t].first) - j, j, t});
+    thread_local std::vector<Entry> all;
+    thread_local std::vector<int32_t> first;   // first entry of each lane in `used`
+    thread_local std::vector<uint8_t> used;
+    all.clear();
+    first.assign(nl + 1, 0);
+    for (int j = 0; j < nl; ++j) {
+        for (int t = 0; t < int(lanes[j].size()); ++t) all.push_back({int64_t(lanes[j][t].first) - j, j, t});
+        first[j + 1] = first[j] + int32_t(lanes[j].size());
+    }
     entries += int64_t(all.size());
     std::sort(all.begin(), all.end(), [](const Entry &a, const Entry &b) {
         return a.key != b.key ? a.key < b.key : a.lane < b.lane;
     });
     // bases shared by enough lanes become strided slots, most shared first
     struct Cand { int64_t key; size_t first, count; };
-    std::vector<Cand> cands;
+    thread_local std::vector<Cand> cands;
+    cands.clear();
     for (size_t i = 0; i < all.size();) {
         size_t k = i;
         while (k < all.size() && all[k].key == all[i].key) ++k;
@@ -139,9 +225,7 @@ int Packed::add_group(const std::vector<const Couplings *> &lanes, int64_t limit
     std::stable_sort(cands.begin(), cands.end(),
                      [](const Cand &a, const Cand &b) { return a.count > b.count; });
     if (int(cands.size()) > std::max(budget, 0)) cands.resize(std::max(budget, 0));
-    std::vector<std::vector<uint8_t>> used(nl);
-    for (int j = 0; j < nl; ++j)
-        if (lanes[j]) used[j].assign(lanes[j]->size(), 0);
+    used.assign(first[nl], 0);
     for (const Cand &c : cands) {
         const int64_t slot = int64_t(sbase.size());
         sbase.push_back(int32_t(c.key));
@@ -150,37 +234,59 @@ int Packed::add_group(const std::vector<const Couplings *> &lanes, int64_t limit
         for (size_t i = c.first; i < c.first + c.count; ++i) {
             const Entry &e = all[i];
             mask |= uint64_t(1) << e.lane;
-            sval[slot * kTileLanes + e.lane] = (*lanes[e.lane])[e.idx].second;
-            used[e.lane][e.idx] = 1;
+            sval[slot * kTileLanes + e.lane] = lanes[e.lane][e.idx].second;
+            used[first[e.lane] + e.idx] = 1;
         }
         smask.push_back(mask);
     }
     soff.push_back(int32_t(sbase.size()));
     max_strided = std::max(max_strided, int32_t(cands.size()));
     // the rest, per lane in column order, as indexed slots
-    size_t len = 0;
-    for (int j = 0; j < nl; ++j)
-        if (lanes[j]) {
-            size_t left = 0;
-            for (uint8_t u : used[j]) left += !u;
-            len = std::max(len, left);
-        }
+    int32_t len = 0;
+    for (int j = 0; j < nl; ++j) {
+        int32_t left = 0;
+        for (int32_t i = first[j]; i < first[j + 1]; ++i) left += !used[i];
+        len = std::max(len, left);
+    }
     const int64_t base = ioff.back();
     ioff.push_back(int32_t(base + len));
     icol.resize((base + len) * kTileLanes, -1);
     ival.resize((base + len) * kTileLanes, 0.0);
     for (int j = 0; j < nl; ++j) {
-        if (!lanes[j]) continue;
         int64_t t = 0;
-        for (size_t i = 0; i < lanes[j]->size(); ++i)
-            if (!used[j][i]) {
-                icol[(base + t) * kTileLanes + j] = (*lanes[j])[i].first;
-                ival[(base + t) * kTileLanes + j] = (*lanes[j])[i].second;
+        for (size_t i = 0; i < lanes[j].size(); ++i)
+            if (!used[first[j] + i]) {
+                icol[(base + t) * kTileLanes + j] = lanes[j][i].first;
+                ival[(base + t) * kTileLanes + j] = lanes[j][i].second;
                 ++t;
             }
     }
-    max_indexed = std::max(max_indexed, int32_t(len));
+    max_indexed = std::max(max_indexed, len);
     return int(cands.size());
+}
+
+void Packed::reserve_for(const std::vector<const Packed *> &parts) {
+    size_t so = soff.size(), sb = sbase.size(), sv = sval.size(), io = ioff.size(), iv = icol.size();
+    for (const Packed *p : parts) {
+        so += p->soff.size(); sb += p->sbase.size(); sv += p->sval.size();
+        io += p->ioff.size(); iv += p->icol.size();
+    }
+    soff.reserve(so); sbase.reserve(sb + 1); smask.reserve(sb + 1); sval.reserve(sv + kTileLanes);
+    ioff.reserve(io); icol.reserve(iv + kTileLanes); ival.reserve(iv + kTileLanes);
+}
+
+void Packed::append(const Packed &o) {
+    const int32_t sb = soff.back(), ib = ioff.back();
+    for (size_t i = 1; i < o.soff.size(); ++i) soff.push_back(sb + o.soff[i]);
+    for (size_t i = 1; i < o.ioff.size(); ++i) ioff.push_back(ib + o.ioff[i]);
+    sbase.insert(sbase.end(), o.sbase.begin(), o.sbase.end());
+    smask.insert(smask.end(), o.smask.begin(), o.smask.end());
+    sval.insert(sval.end(), o.sval.begin(), o.sval.end());
+    icol.insert(icol.end(), o.icol.begin(), o.icol.end());
+    ival.insert(ival.end(), o.ival.begin(), o.ival.end());
+    max_strided = std::max(max_strided, o.max_strided);
+    max_indexed = std::max(max_indexed, o.max_indexed);
+    entries += o.entries;
 }
 
 void Packed::finish() {
@@ -191,15 +297,22 @@ void Packed::finish() {
     ival.resize(ival.size() + kTileLanes, 0.0);
 }
 
-extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
-                          const double *val, int32_t precision, double shift, hbmc_factor_t **out) {
+namespace {
+
+enum class Split { kIc0, kSsor };
+
+// Factor of either splitting, its substitution layout and its device image.
+int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col, const double *val,
+                int32_t precision, Split kind, double param, hbmc_factor_t **out) {
     clear_error();
     if (!out) return fail(HBMC_EINVAL, "out is NULL");
     *out = nullptr;
     if (!o || !val) return fail(HBMC_EINVAL, "null argument");
     if (precision != HBMC_F64 && precision != HBMC_F32)
         return fail(HBMC_EINVAL, "precision must be HBMC_F64 or HBMC_F32");
-    if (!(shift >= 0.0)) return fail(HBMC_EINVAL, "shift must be >= 0");
+    if (kind == Split::kIc0 && !(param >= 0.0)) return fail(HBMC_EINVAL, "shift must be >= 0");
+    if (kind == Split::kSsor && !(param > 0.0 && param < 2.0))
+        return fail(HBMC_EINVAL, "omega must lie in (0, 2) (got %g)", param);
     int st = check_csr(o->n, rowptr, col, val);
     if (st) return st;
     try {
@@ -212,47 +325,68 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         f->nsys = o->nsys;
         f->sys_ptr = o->sys_ptr;
         const Csr a = permute(*o, rowptr, col, val);
-        st = ic0_rows(a, f->n_pad, shift, f->lrp, f->lcol, f->lval, f->d);
-        if (st) { delete f; return st; }
-
         const int64_t n = f->n_pad;
         const int bs = f->bs, w = f->w;
         const int64_t l1 = int64_t(bs) * w;
+        const Levels lv{f->color_start, l1, w};
+        st = kind == Split::kIc0 ? ic0_rows(a, n, param, lv, f->lrp, f->lcol, f->lval, f->d)
+                                 : ssor_rows(a, n, param, lv, f->lrp, f->lcol, f->lval, f->d);
+        if (st) { delete f; return st; }
+        f->smooth_scale = kind == Split::kSsor ? 2.0 - param : 1.0;
+
         std::vector<double> dinv(n);
-        for (int64_t i = 0; i < n; ++i) dinv[i] = 1.0 / f->d[i];
         // color of each HBMC row
         std::vector<int32_t> color(n);
         for (int c = 0; c < f->nc; ++c)
-            for (int64_t r = f->color_start[c]; r < f->color_start[c + 1]; ++r) color[r] = c;
-        // the step of row r inside its level-1 block, and its chain lane
+            std::fill(color.begin() + f->color_start[c], color.begin() + f->color_start[c + 1], c);
+        parallel_for(n, kGrain, [&](int64_t i) { dinv[i] = 1.0 / f->d[i]; });
+        // the step of row r inside its level-1 block
         auto step_of = [&](int64_t r) { return int(((r - f->color_start[color[r]]) % l1) / w); };
 
         // couplings of each row: forward (lower) and backward (upper, scaled
         // by diaginv of the row: U = I + D^-1 L^T), split into couplings to
-        // other colors (ext) and inside the level-1 block (int)
-        std::vector<Couplings> fe(n), fi(n), be(n), bi(n);
-        for (int64_t r = 0; r < n; ++r) {
-            const int64_t lb = (r - f->color_start[color[r]]) / l1;
+        // other colors (ext) and inside the level-1 block (int, column = the
+        // source step).  The upper couplings of row k are the columns r > k
+        // of Abar's row k (the pattern is symmetric), each with L_rk found in
+        // row r; they come out in ascending r.
+        CouplingRows fe, fi, be, bi;
+        for (CouplingRows *cr : {&fe, &fi, &be, &bi}) cr->ptr.assign(n + 1, 0);
+        auto lower_at = [&](int64_t r, int32_t k) {
+            const int32_t *b = f->lcol.data() + f->lrp[r], *e = f->lcol.data() + f->lrp[r + 1];
+            return f->lval[f->lrp[r] + (std::lower_bound(b, e, k) - b)];
+        };
+        parallel_for(n, kGrain, [&](int64_t r) {
+            int64_t ne = 0, ni = 0;
+            for (int64_t p = f->lrp[r]; p < f->lrp[r + 1]; ++p) (color[f->lcol[p]] != color[r] ? ne : ni) += 1;
+            fe.ptr[r + 1] = ne;
+            fi.ptr[r + 1] = ni;
+            ne = ni = 0;
+            for (int64_t p = a.rp[r]; p < a.rp[r + 1]; ++p)
+                if (a.ci[p] > r) (color[a.ci[p]] != color[r] ? ne : ni) += 1;
+            be.ptr[r + 1] = ne;
+            bi.ptr[r + 1] = ni;
+        });
+        for (CouplingRows *cr : {&fe, &fi, &be, &bi}) {
+            for (int64_t r = 0; r < n; ++r) cr->ptr[r + 1] += cr->ptr[r];
+            cr->data.resize(cr->ptr[n]);
+        }
+        parallel_for(n, kGrain, [&](int64_t r) {
+            int64_t xe = fe.ptr[r], xi = fi.ptr[r];
             for (int64_t p = f->lrp[r]; p < f->lrp[r + 1]; ++p) {
                 const int32_t k = f->lcol[p];
-                const double lv = f->lval[p];
-                // (r, k) lower: forward coupling of r; (k, r) upper: backward of k
-                if (color[k] != color[r]) {
-                    fe[r].emplace_back(k, lv);
-                    be[k].emplace_back(int32_t(r), dinv[k] * lv);
-                } else {
-                    const int64_t lbk = (k - f->color_start[color[k]]) / l1;
-                    if (lbk != lb || (r - k) % w != 0) {
-                        delete f;
-                        return fail(HBMC_EINVAL, "internal: coupling (%lld,%d) crosses level-1 blocks",
-                                    (long long)r, k);
-                    }
-                    fi[r].emplace_back(step_of(k), lv);
-                    bi[k].emplace_back(step_of(r), dinv[k] * lv);
-                }
+                if (color[k] != color[r]) fe.data[xe++] = {k, f->lval[p]};
+                else fi.data[xi++] = {step_of(k), f->lval[p]};
             }
-        }
-        // be and bi were filled in ascending r, so they are already sorted
+            xe = be.ptr[r];
+            xi = bi.ptr[r];
+            for (int64_t p = a.rp[r]; p < a.rp[r + 1]; ++p) {
+                const int32_t q = a.ci[p];
+                if (q <= r) continue;
+                const double u = dinv[r] * lower_at(q, int32_t(r));
+                if (color[q] != color[r]) be.data[xe++] = {q, u};
+                else bi.data[xi++] = {step_of(q), u};
+            }
+        });
 
         // Layout of the substitutions: per color, the chain lanes (one per BMC
         // block, lam = level-1 block * w + m) are cut into tiles of 64 lanes;
@@ -260,76 +394,108 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         // one entry per lane: the couplings of row  S_c + (lam / w) bs w +
         // l w + lam % w.  Missing entries have column -1 and value 0.  Each
         // array ends with one extra all-padding slot that loads may target
-        // instead of branching.
+        // instead of branching.  Tiles are packed in parallel chunks, which
+        // are then joined in tile order.
         f->tile_base.assign(f->nc + 1, 0);
         for (int c = 0; c < f->nc; ++c) {
             const int64_t lanes = (f->color_start[c + 1] - f->color_start[c]) / bs;
             f->tile_base[c + 1] = f->tile_base[c] + (lanes + kTileLanes - 1) / kTileLanes;
         }
-        // couplings to other colors: one Packed group per (tile, step)
-        std::vector<const Couplings *> lanes_f, lanes_b;
-        for (int c = 0; c < f->nc; ++c) {
-            const int64_t r0 = f->color_start[c];
-            const int64_t lanes = (f->color_start[c + 1] - r0) / bs;
-            for (int64_t t0 = 0; t0 < lanes; t0 += kTileLanes) {
-                // the kernel fetches a tile's strided-slot metadata one slot per lane
-                int budget_f = kTileLanes, budget_b = kTileLanes;
-                for (int l = 0; l < bs; ++l) {
-                    lanes_f.assign(kTileLanes, nullptr);
-                    lanes_b.assign(kTileLanes, nullptr);
-                    for (int64_t lam = t0; lam < std::min(lanes, t0 + kTileLanes); ++lam) {
-                        const int64_t row = r0 + (lam / w) * l1 + int64_t(l) * w + lam % w;
-                        lanes_f[lam - t0] = &fe[row];
-                        lanes_b[lam - t0] = &be[row];
+        const int64_t ntiles = f->tile_base[f->nc];
+        struct Chunk {
+            Packed fext, bext;                 // couplings to other colors, one group per (tile, step)
+            Sell fint, bint;                   // couplings inside level-1 blocks, one slice per (tile, step)
+            int32_t slots_f = 0, slots_b = 0;  // most in-block slots of a tile
+            int32_t step_f = 0, step_b = 0;    // most in-block slots of a (tile, step)
+        };
+        const int nchunks = chunks_for(ntiles, std::max<int64_t>(1, kGrain / (int64_t(kTileLanes) * bs)));
+        std::vector<Chunk> chunks(nchunks);
+        parallel_chunks(ntiles, nchunks, [&](int64_t t_lo, int64_t t_hi, int ch) {
+            Chunk &k = chunks[ch];
+            k.fint.off.assign(1, 0);
+            k.bint.off.assign(1, 0);
+            std::vector<CouplingSpan> lanes_f(kTileLanes), lanes_b(kTileLanes), lanes_fi(kTileLanes),
+                lanes_bi(kTileLanes);
+            // in-block couplings of one (tile, step): slots of (source step, value)
+            auto pack_int = [](const std::vector<CouplingSpan> &ls, Sell &s, int32_t &tile_slots,
+                               int32_t &max_step) {
+                size_t len = 0;
+                for (const auto &e : ls) len = std::max(len, e.size());
+                const int64_t base = s.off.back();
+                s.off.push_back(int32_t(base + len));
+                s.val.resize((base + len) * kTileLanes, 0.0);
+                s.col.resize((base + len) * kTileLanes, -1);
+                for (int j = 0; j < kTileLanes; ++j)
+                    for (size_t t = 0; t < ls[j].size(); ++t) {
+                        s.col[(base + t) * kTileLanes + j] = ls[j][t].first;
+                        s.val[(base + t) * kTileLanes + j] = ls[j][t].second;
                     }
-                    budget_f -= f->fext.add_group(lanes_f, n, budget_f);
-                    budget_b -= f->bext.add_group(lanes_b, n, budget_b);
-                }
-            }
-        }
-        f->fext.finish();
-        f->bext.finish();
-        // couplings inside the level-1 blocks: per (tile, step) a list of
-        // slots, one entry per lane (column = source step, -1 = none)
-        auto pack_lanes = [&](const std::vector<Couplings> &rows, Sell &s, int32_t &max_slots,
-                              int32_t &max_step) {
-            s.off.assign(1, 0);
-            max_slots = 0;
-            max_step = 0;
-            for (int c = 0; c < f->nc; ++c) {
+                tile_slots += int32_t(len);
+                max_step = std::max(max_step, int32_t(len));
+            };
+            for (int64_t t = t_lo; t < t_hi; ++t) {
+                const int c = int(std::upper_bound(f->tile_base.begin(), f->tile_base.end(), t) -
+                                  f->tile_base.begin()) - 1;
                 const int64_t r0 = f->color_start[c];
                 const int64_t lanes = (f->color_start[c + 1] - r0) / bs;
-                for (int64_t t0 = 0; t0 < lanes; t0 += kTileLanes) {
-                    const int64_t t1 = std::min(lanes, t0 + kTileLanes);
-                    int32_t tile_slots = 0;
-                    for (int l = 0; l < bs; ++l) {
-                        auto row_of = [&](int64_t lam) {
-                            return r0 + (lam / w) * l1 + int64_t(l) * w + lam % w;
-                        };
-                        size_t len = 0;
-                        for (int64_t lam = t0; lam < t1; ++lam) len = std::max(len, rows[row_of(lam)].size());
-                        const int64_t base = s.off.back();
-                        s.off.push_back(int32_t(base + len));
-                        s.val.resize((base + len) * kTileLanes, 0.0);
-                        s.col.resize((base + len) * kTileLanes, -1);
-                        for (int64_t lam = t0; lam < t1; ++lam) {
-                            const auto &e = rows[row_of(lam)];
-                            for (size_t t = 0; t < e.size(); ++t) {
-                                s.col[(base + t) * kTileLanes + (lam - t0)] = e[t].first;
-                                s.val[(base + t) * kTileLanes + (lam - t0)] = e[t].second;
-                            }
+                const int64_t t0 = (t - f->tile_base[c]) * kTileLanes;
+                // the kernel fetches a tile's strided-slot metadata one slot per lane
+                int budget_f = kTileLanes, budget_b = kTileLanes;
+                int32_t tile_f = 0, tile_b = 0;
+                for (int l = 0; l < bs; ++l) {
+                    for (int j = 0; j < kTileLanes; ++j) {
+                        const int64_t lam = t0 + j;
+                        if (lam < lanes) {
+                            const int64_t row = r0 + (lam / w) * l1 + int64_t(l) * w + lam % w;
+                            lanes_f[j] = fe.row(row);
+                            lanes_b[j] = be.row(row);
+                            lanes_fi[j] = fi.row(row);
+                            lanes_bi[j] = bi.row(row);
+                        } else {
+                            lanes_f[j] = lanes_b[j] = lanes_fi[j] = lanes_bi[j] = CouplingSpan{};
                         }
-                        tile_slots += int32_t(len);
-                        max_step = std::max(max_step, int32_t(len));
                     }
-                    max_slots = std::max(max_slots, tile_slots);
+                    budget_f -= k.fext.add_group(lanes_f, n, budget_f);
+                    budget_b -= k.bext.add_group(lanes_b, n, budget_b);
+                    pack_int(lanes_fi, k.fint, tile_f, k.step_f);
+                    pack_int(lanes_bi, k.bint, tile_b, k.step_b);
                 }
+                k.slots_f = std::max(k.slots_f, tile_f);
+                k.slots_b = std::max(k.slots_b, tile_b);
             }
-            s.val.resize(s.val.size() + kTileLanes, 0.0);   // the padding slot
-            s.col.resize(s.col.size() + kTileLanes, -1);
-        };
-        pack_lanes(fi, f->fint, f->max_int_slots_f, f->max_int_step_f);
-        pack_lanes(bi, f->bint, f->max_int_slots_b, f->max_int_step_b);
+        });
+        f->fint.off.assign(1, 0);
+        f->bint.off.assign(1, 0);
+        f->max_int_slots_f = f->max_int_slots_b = f->max_int_step_f = f->max_int_step_b = 0;
+        {
+            std::vector<const Packed *> pf, pb;
+            std::vector<const Sell *> sf, sb;
+            for (const Chunk &k : chunks) {
+                pf.push_back(&k.fext); pb.push_back(&k.bext);
+                sf.push_back(&k.fint); sb.push_back(&k.bint);
+            }
+            f->fext.reserve_for(pf);
+            f->bext.reserve_for(pb);
+            f->fint.reserve_for(sf);
+            f->bint.reserve_for(sb);
+        }
+        for (const Chunk &k : chunks) {
+            f->fext.append(k.fext);
+            f->bext.append(k.bext);
+            f->fint.append(k.fint);
+            f->bint.append(k.bint);
+            f->max_int_slots_f = std::max(f->max_int_slots_f, k.slots_f);
+            f->max_int_slots_b = std::max(f->max_int_slots_b, k.slots_b);
+            f->max_int_step_f = std::max(f->max_int_step_f, k.step_f);
+            f->max_int_step_b = std::max(f->max_int_step_b, k.step_b);
+        }
+        chunks.clear();
+        f->fext.finish();
+        f->bext.finish();
+        for (Sell *sl : {&f->fint, &f->bint}) {   // the padding slot
+            sl->val.resize(sl->val.size() + kTileLanes, 0.0);
+            sl->col.resize(sl->col.size() + kTileLanes, -1);
+        }
 
         // systems: each tile and each kPartRows-row part lies in one system
         // (a single system trivially; batches pad every system's share of a
@@ -372,6 +538,16 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
 
         // device image
         auto &im = f->image;
+        {
+            auto vb = [](const auto &v) { return v.size() * sizeof(v[0]) + 256; };
+            size_t est = 256 + vb(dinv) + vb(f->perm) + vb(f->iperm) + vb(f->tile_sys) + vb(f->part_sys) +
+                         vb(f->sys_tiles) + vb(f->sys_parts);
+            for (const Packed *e : {&f->fext, &f->bext})
+                est += vb(e->soff) + vb(e->sbase) + vb(e->smask) + vb(e->sval) + vb(e->ioff) + vb(e->icol) +
+                       vb(e->ival);
+            for (const Sell *i : {&f->fint, &f->bint}) est += vb(i->off) + vb(i->col) + vb(i->val);
+            im.bytes.reserve(est);
+        }
         auto add_tri = [&](const Packed &e, const Sell &i, TriOffsets &t) {
             add_packed<double>(im, e, precision == HBMC_F32, t.ext);
             t.int_off = im.add(i.off);
@@ -391,8 +567,20 @@ extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const in
         *out = f;
         return HBMC_OK;
     } catch (const std::bad_alloc &) {
-        return fail(HBMC_ENOMEM, "out of host memory in ic0_factor");
+        return fail(HBMC_ENOMEM, "out of host memory in %s", kind == Split::kIc0 ? "ic0_factor" : "ssor_factor");
     }
+}
+
+}  // namespace
+
+extern "C" int ic0_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
+                          const double *val, int32_t precision, double shift, hbmc_factor_t **out) {
+    return make_factor(o, rowptr, col, val, precision, Split::kIc0, shift, out);
+}
+
+extern "C" int ssor_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
+                           const double *val, int32_t precision, double omega, hbmc_factor_t **out) {
+    return make_factor(o, rowptr, col, val, precision, Split::kSsor, omega, out);
 }
 
 extern "C" int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lower_rowptr,
@@ -403,6 +591,22 @@ extern "C" int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lo
     if (lower_rowptr) std::copy(f->lrp.begin(), f->lrp.end(), lower_rowptr);
     if (lower_col) std::copy(f->lcol.begin(), f->lcol.end(), lower_col);
     if (lower_val) std::copy(f->lval.begin(), f->lval.end(), lower_val);
+    return HBMC_OK;
+}
+
+extern "C" int hbmc_factor_image(const hbmc_factor_t *f, void *host, size_t bytes) {
+    if (!f || !host) return fail(HBMC_EINVAL, "null argument");
+    if (bytes < f->image.bytes.size())
+        return fail(HBMC_EINVAL, "buffer too small (%zu < %zu)", bytes, f->image.bytes.size());
+    std::memcpy(host, f->image.bytes.data(), f->image.bytes.size());
+    return HBMC_OK;
+}
+
+extern "C" int hbmc_matrix_image(const hbmc_matrix_t *m, void *host, size_t bytes) {
+    if (!m || !host) return fail(HBMC_EINVAL, "null argument");
+    if (bytes < m->image.bytes.size())
+        return fail(HBMC_EINVAL, "buffer too small (%zu < %zu)", bytes, m->image.bytes.size());
+    std::memcpy(host, m->image.bytes.data(), m->image.bytes.size());
     return HBMC_OK;
 }
 
@@ -431,21 +635,49 @@ extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, 
         m->n = o->n;
         m->n_pad = o->n_pad;
         const Csr a = permute(*o, rowptr, col, val);
-        m->diag.assign(m->n_pad, 0.0);
-        std::vector<Couplings> rows(m->n_pad);
-        for (int64_t r = 0; r < m->n_pad; ++r)
+        const int64_t n = m->n_pad;
+        m->diag.assign(n, 0.0);
+        CouplingRows rows;
+        rows.ptr.assign(n + 1, 0);
+        parallel_for(n, kGrain, [&](int64_t r) { rows.ptr[r + 1] = a.rp[r + 1] - a.rp[r] - 1; });
+        for (int64_t r = 0; r < n; ++r) rows.ptr[r + 1] += rows.ptr[r];
+        rows.data.resize(rows.ptr[n]);
+        parallel_for(n, kGrain, [&](int64_t r) {
+            int64_t x = rows.ptr[r];
             for (int64_t p = a.rp[r]; p < a.rp[r + 1]; ++p) {
                 if (a.ci[p] == r) m->diag[r] = a.v[p];
-                else rows[r].emplace_back(a.ci[p], a.v[p]);
+                else rows.data[x++] = {a.ci[p], a.v[p]};
             }
-        // one Packed group per 64-row slice
-        std::vector<const Couplings *> lanes;
-        for (int64_t r0 = 0; r0 < m->n_pad; r0 += kTileLanes) {
-            lanes.assign(kTileLanes, nullptr);
-            for (int64_t r = r0; r < std::min(m->n_pad, r0 + kTileLanes); ++r) lanes[r - r0] = &rows[r];
-            m->off.add_group(lanes, m->n_pad, kTileLanes);
+        });
+        // one Packed group per 64-row slice, slices packed in parallel chunks
+        // and joined in slice order
+        const int64_t slices = (n + kTileLanes - 1) / kTileLanes;
+        const int nchunks = chunks_for(slices, kGrain / kTileLanes);
+        std::vector<Packed> part(nchunks);
+        parallel_chunks(slices, nchunks, [&](int64_t lo, int64_t hi, int ch) {
+            std::vector<CouplingSpan> lanes(kTileLanes);
+            for (int64_t sl = lo; sl < hi; ++sl) {
+                for (int j = 0; j < kTileLanes; ++j) {
+                    const int64_t r = sl * kTileLanes + j;
+                    lanes[j] = r < n ? rows.row(r) : CouplingSpan{};
+                }
+                part[ch].add_group(lanes, n, kTileLanes);
+            }
+        });
+        {
+            std::vector<const Packed *> pp;
+            for (const Packed &pk : part) pp.push_back(&pk);
+            m->off.reserve_for(pp);
         }
+        for (const Packed &pk : part) m->off.append(pk);
+        part.clear();
         m->off.finish();
+        {
+            const Packed &e = m->off;
+            auto vb = [](const auto &v) { return v.size() * sizeof(v[0]) + 256; };
+            m->image.bytes.reserve(256 + vb(m->diag) + vb(e.soff) + vb(e.sbase) + vb(e.smask) + vb(e.sval) +
+                                   vb(e.ioff) + vb(e.icol) + vb(e.ival));
+        }
         m->off_diag = m->image.add(m->diag);
         add_packed<double>(m->image, m->off, false, m->offs);
         m->image.bytes.resize((m->image.bytes.size() + 255) & ~size_t(255));

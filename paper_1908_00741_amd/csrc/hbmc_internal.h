@@ -4,7 +4,9 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <memory>
 #include <string>
+#include <utility>
 #include <vector>
 
 #include "../../include/hbmc.h"
@@ -37,6 +39,19 @@ struct Sell {
     std::vector<double> val;    // [slots * kTileLanes]
     std::vector<int32_t> col;   // [slots * kTileLanes]
     int64_t slots() const { return off.empty() ? 0 : off.back(); }
+    // room for the slices of parts (before appending them)
+    void reserve_for(const std::vector<const Sell *> &parts) {
+        size_t o = off.size(), v = val.size();
+        for (const Sell *p : parts) { o += p->off.size(); v += p->val.size(); }
+        off.reserve(o); val.reserve(v); col.reserve(v);
+    }
+    // o's slices after this one's (both started with off = {0}, no padding slot yet)
+    void append(const Sell &o) {
+        const int32_t base = off.back();
+        for (size_t i = 1; i < o.off.size(); ++i) off.push_back(base + o.off[i]);
+        val.insert(val.end(), o.val.begin(), o.val.end());
+        col.insert(col.end(), o.col.begin(), o.col.end());
+    }
 };
 
 // CG state of one system, kept on the device between kernels.
@@ -64,9 +79,10 @@ struct ApplyCg {
 // Enqueues z = M^-1 r for K right-hand sides ([n_pad][K]) on stream (a
 // hipStream_t).  When done is not null the kernels return at once while
 // *done != 0 (used inside captured CG loops).  With cg, r is taken from
-// cg->r after the update.
+// cg->r after the update.  With fwd_only (and no cg), only the forward
+// substitution runs: z = (D + L)^-1 r.
 int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *stream,
-                 const int32_t *done, const ApplyCg *cg, int K);
+                 const int32_t *done, const ApplyCg *cg, int K, bool fwd_only = false);
 // Right-hand sides per wavefront (NR) used for K right-hand sides.
 int rhs_tile(const ::hbmc_factor_s *f, int K);
 // Destroys the hipGraph executables cached by iccg_solve for this factor.
@@ -83,7 +99,37 @@ uint64_t next_uid();
 // does not line up goes to indexed slots (one column per lane, -1 = none).
 // Each array ends with one all-padding slot that loads may target instead
 // of branching.
-using Couplings = std::vector<std::pair<int32_t, double>>;
+// Allocator whose resize() leaves new elements of trivial types
+// uninitialized: large setup arrays are first written by the threads that
+// fill them, not zeroed by one thread beforehand.
+template <class T>
+struct NoInit : std::allocator<T> {
+    template <class U> struct rebind { using other = NoInit<U>; };
+    NoInit() = default;
+    template <class U> NoInit(const NoInit<U> &) noexcept {}
+    template <class U> void construct(U *p) noexcept { ::new (static_cast<void *>(p)) U; }
+    template <class U, class... A> void construct(U *p, A &&...a) { ::new (static_cast<void *>(p)) U(std::forward<A>(a)...); }
+};
+template <class T> using RawVec = std::vector<T, NoInit<T>>;
+
+// One coupling: column (or source step) and value.
+struct Coupling {
+    int32_t first;
+    double second;
+};
+// Couplings of one row, sorted by column; empty for a lane without a row.
+struct CouplingSpan {
+    const Coupling *p = nullptr;
+    size_t n = 0;
+    size_t size() const { return n; }
+    const Coupling &operator[](size_t i) const { return p[i]; }
+};
+// Couplings of all rows in one array: row r is data[ptr[r] .. ptr[r + 1]).
+struct CouplingRows {
+    std::vector<int64_t> ptr;
+    RawVec<Coupling> data;
+    CouplingSpan row(int64_t r) const { return {data.data() + ptr[r], size_t(ptr[r + 1] - ptr[r])}; }
+};
 struct Packed {
     std::vector<int32_t> soff{0};   // [groups + 1] strided slots per group
     std::vector<int32_t> sbase;     // [strided + 1]
@@ -98,7 +144,9 @@ struct Packed {
     // Columns base + j of strided slots stay below limit; at most budget
     // strided slots are made (the rest of the couplings go to indexed slots).
     // Returns the number of strided slots made.
-    int add_group(const std::vector<const Couplings *> &lanes, int64_t limit, int budget);
+    int add_group(const std::vector<CouplingSpan> &lanes, int64_t limit, int budget);
+    void append(const Packed &o);   // o's groups after this one's (neither finished)
+    void reserve_for(const std::vector<const Packed *> &parts);   // room for appending parts
     void finish();   // appends the padding slots
     int64_t strided() const { return soff.back(); }
     int64_t indexed() const { return ioff.back(); }
@@ -140,6 +188,7 @@ struct hbmc_factor_s {
     int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;
     int64_t n_pad = 0;
+    double smooth_scale = 1.0;         // c of the smoothing step x += c M^-1 r: 1 (IC(0)), 2 - omega (SSOR)
     std::vector<int64_t> color_start;
     std::vector<int64_t> sys_ptr;      // [nsys + 1] original rows of each system
     // systems: tile and 64-row group -> system; per system and color the

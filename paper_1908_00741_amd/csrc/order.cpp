@@ -7,8 +7,11 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <thread>
+#include <atomic>
 
 #include "hbmc_internal.h"
+#include "parallel.h"
 
 namespace hbmc {
 
@@ -26,10 +29,23 @@ int fail(int code, const char *fmt, ...) {
 
 void clear_error() { g_last_error.clear(); }
 
+namespace {
+std::atomic<int> g_threads{0};
+}  // namespace
+
+int setup_threads() {
+    const int t = g_threads.load();
+    if (t > 0) return t;
+    return int(std::max(1u, std::thread::hardware_concurrency()));
+}
+
 size_t ImageBuilder::add(const void *src, size_t n) {
     size_t at = (bytes.size() + 255) & ~size_t(255);
     bytes.resize(at + n);
-    if (n) std::memcpy(bytes.data() + at, src, n);
+    constexpr int64_t kPiece = int64_t(1) << 22;   // bytes per thread of a large copy, at least
+    parallel_chunks(int64_t(n), chunks_for(int64_t(n), kPiece), [&](int64_t lo, int64_t hi, int) {
+        if (hi > lo) std::memcpy(bytes.data() + at + lo, static_cast<const uint8_t *>(src) + lo, size_t(hi - lo));
+    });
     return at;
 }
 
@@ -37,47 +53,51 @@ int check_csr(int32_t n, const int64_t *rp, const int32_t *ci, const double *v) 
     if (n < 1) return fail(HBMC_EINVAL, "n must be >= 1 (got %d)", n);
     if (!rp || !ci) return fail(HBMC_EINVAL, "null CSR pointer");
     if (rp[0] != 0) return fail(HBMC_EINVAL, "rowptr[0] must be 0");
-    for (int32_t i = 0; i < n; ++i) {
+    for (int32_t i = 0; i < n; ++i)
         if (rp[i + 1] < rp[i]) return fail(HBMC_EINVAL, "rowptr decreases at row %d", i);
+    // Rows are checked in parallel chunks; the error reported is the one of
+    // the first offending row (as a row-by-row check would find it).
+    struct Bad { int32_t row = -1, code = 0, other = 0; const char *what = nullptr; };
+    constexpr int64_t kRows = 16384;
+    auto first_bad = [&](auto &&check_row) -> Bad {
+        const int chunks = chunks_for(n, kRows);
+        std::vector<Bad> bad(chunks);
+        parallel_chunks(n, chunks, [&](int64_t lo, int64_t hi, int c) {
+            for (int64_t i = lo; i < hi && bad[c].row < 0; ++i) check_row(int32_t(i), bad[c]);
+        });
+        for (const Bad &x : bad)
+            if (x.row >= 0) return x;
+        return Bad{};
+    };
+    Bad e = first_bad([&](int32_t i, Bad &b) {
         bool diag = false;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-            if (ci[p] < 0 || ci[p] >= n) return fail(HBMC_EINVAL, "column out of range in row %d", i);
-            if (p > rp[i] && ci[p] <= ci[p - 1])
-                return fail(HBMC_EINVAL, "columns of row %d not strictly ascending", i);
+            if (ci[p] < 0 || ci[p] >= n) { b = {i, HBMC_EINVAL, 0, "column out of range in row %d"}; return; }
+            if (p > rp[i] && ci[p] <= ci[p - 1]) {
+                b = {i, HBMC_EINVAL, 0, "columns of row %d not strictly ascending"};
+                return;
+            }
             if (ci[p] == i) {
                 diag = true;
-                if (v && !(v[p] > 0.0)) return fail(HBMC_EDIAG, "diagonal of row %d is not > 0", i);
+                if (v && !(v[p] > 0.0)) { b = {i, HBMC_EDIAG, 0, "diagonal of row %d is not > 0"}; return; }
             }
         }
-        if (!diag) return fail(HBMC_EDIAG, "row %d has no diagonal entry", i);
-    }
-    // symmetry: walk each row's upper part against the matching column of
-    // the lower parts, using a per-row cursor (rows are sorted)
-    std::vector<int64_t> cursor(rp, rp + n);
-    for (int32_t i = 0; i < n; ++i) {
+        if (!diag) b = {i, HBMC_EDIAG, 0, "row %d has no diagonal entry"};
+    });
+    if (e.row >= 0) return fail(e.code, e.what, e.row);
+    // symmetry: every off-diagonal entry (i, j) has a mirror (j, i) with the
+    // same value (rows are sorted: binary search in row j)
+    e = first_bad([&](int32_t i, Bad &b) {
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
-            int32_t j = ci[p];
-            if (j <= i) continue;
-            // entry (j, i) must be the next unvisited lower entry of row j
-            int64_t &c = cursor[j];
-            while (c < rp[j + 1] && ci[c] < i) {
-                // a lower entry (j, ci[c]) with ci[c] < i whose mirror (ci[c], j)
-                // would have been met in row ci[c] < i: missing mirror
-                return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", j, ci[c]);
-            }
-            if (c >= rp[j + 1] || ci[c] != i)
-                return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", i, j);
-            if (v && v[c] != v[p])
-                return fail(HBMC_ENOTSYM, "values not symmetric at (%d,%d)", i, j);
-            ++c;
+            const int32_t j = ci[p];
+            if (j == i) continue;
+            const int32_t *lo = ci + rp[j], *hi = ci + rp[j + 1];
+            const int32_t *q = std::lower_bound(lo, hi, i);
+            if (q == hi || *q != i) { b = {i, HBMC_ENOTSYM, j, "pattern not symmetric: (%d,%d) has no mirror"}; return; }
+            if (v && v[q - ci] != v[p]) { b = {i, HBMC_ENOTSYM, j, "values not symmetric at (%d,%d)"}; return; }
         }
-    }
-    // every lower entry must have been matched by an upper one
-    for (int32_t j = 0; j < n; ++j) {
-        int64_t c = cursor[j];
-        if (c < rp[j + 1] && ci[c] < j)
-            return fail(HBMC_ENOTSYM, "pattern not symmetric: (%d,%d) has no mirror", j, ci[c]);
-    }
+    });
+    if (e.row >= 0) return fail(e.code, e.what, e.row, e.other);
     return HBMC_OK;
 }
 
@@ -307,3 +327,9 @@ extern "C" int hbmc_order_perm(const hbmc_order_t *h, int32_t *perm, int64_t *co
 extern "C" void hbmc_order_destroy(hbmc_order_t *h) { delete h; }
 
 extern "C" const char *hbmc_last_error(void) { return hbmc::g_last_error.c_str(); }
+
+extern "C" int hbmc_set_num_threads(int32_t threads) {
+    if (threads < 0) return fail(HBMC_EINVAL, "threads = %d", threads);
+    hbmc::g_threads.store(threads);
+    return HBMC_OK;
+}

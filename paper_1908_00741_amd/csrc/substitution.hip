@@ -29,16 +29,16 @@ int hbmc::rhs_tile(const hbmc_factor_s *f, int K) {
 }
 
 int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void *stream,
-                       const int32_t *done, const ApplyCg *cg, int K) {
+                       const int32_t *done, const ApplyCg *cg, int K, bool fo) {
     auto s = static_cast<hipStream_t>(stream);
     const int nr = rhs_tile(f, K);
     switch (f->bs) {
-        case 1: return launch_bs1(f, r, z, s, done, cg, K, nr);
-        case 2: return launch_bs2(f, r, z, s, done, cg, K, nr);
-        case 4: return launch_bs4(f, r, z, s, done, cg, K, nr);
-        case 8: return launch_bs8(f, r, z, s, done, cg, K, nr);
-        case 16: return launch_bs16(f, r, z, s, done, cg, K, nr);
-        case 32: return launch_bs32(f, r, z, s, done, cg, K, nr);
+        case 1: return launch_bs1(f, r, z, s, done, cg, K, nr, fo);
+        case 2: return launch_bs2(f, r, z, s, done, cg, K, nr, fo);
+        case 4: return launch_bs4(f, r, z, s, done, cg, K, nr, fo);
+        case 8: return launch_bs8(f, r, z, s, done, cg, K, nr, fo);
+        case 16: return launch_bs16(f, r, z, s, done, cg, K, nr, fo);
+        case 32: return launch_bs32(f, r, z, s, done, cg, K, nr, fo);
         default: return fail(HBMC_EINVAL, "bs = %d has no device kernel (1, 2, 4, 8, 16, 32)", f->bs);
     }
 }

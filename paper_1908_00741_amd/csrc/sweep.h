@@ -38,19 +38,21 @@
 namespace hbmc {
 
 // Launches the phases of one apply for factors of block size BS (defined in
-// sweep_bs<BS>.hip).  K right-hand sides, nr of them per wavefront.
+// sweep_bs<BS>.hip).  K right-hand sides, nr of them per wavefront.  With
+// fwd_only, only the forward substitution runs (z = (D + L)^-1 r, every
+// color in the forward form).
 int launch_bs1(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr);
+               const ApplyCg *cg, int K, int nr, bool fwd_only);
 int launch_bs2(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr);
+               const ApplyCg *cg, int K, int nr, bool fwd_only);
 int launch_bs4(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr);
+               const ApplyCg *cg, int K, int nr, bool fwd_only);
 int launch_bs8(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr);
+               const ApplyCg *cg, int K, int nr, bool fwd_only);
 int launch_bs16(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg *cg, int K, int nr);
+                const ApplyCg *cg, int K, int nr, bool fwd_only);
 int launch_bs32(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg *cg, int K, int nr);
+                const ApplyCg *cg, int K, int nr, bool fwd_only);
 
 }  // namespace hbmc
 
@@ -539,7 +541,7 @@ bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
 
 template <int BS, typename T, int MI, bool CG, int NR>
 int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
-                  const int32_t *done, const ApplyCg &cg, int K) {
+                  const int32_t *done, const ApplyCg &cg, int K, bool fwd_only) {
     constexpr int CH = BS <= 4 ? 4 : (BS <= 8 ? 2 : 1);   // measured best on 128^3, bs 8
     constexpr int WAVES = MI > 0 ? 4 : 1;                 // k_sweep: wavefronts per workgroup
     constexpr int CHR = 16;                               // k_rows: slots per chunk
@@ -590,6 +592,13 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     };
     const int nc = f->nc;
     int st;
+    if (fwd_only) {
+        if (CG) return fail(HBMC_EINVAL, "internal: forward-only substitution inside CG");
+        for (int c = 0; c < nc; ++c)
+            if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG, NR>,
+                          k_rows<BS, T, kForward, MI, CHR, CG>))) return st;
+        return HBMC_OK;
+    }
     for (int c = 0; c + 1 < nc; ++c)
         if ((st = run(c, k_sweep<BS, T, kForward, MI, CH, WAVES, CG, NR>,
                       k_rows<BS, T, kForward, MI, CHR, CG>))) return st;
@@ -604,12 +613,12 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
 // right-hand sides per wavefront: 1 (one right-hand side), 4, 8 or 16
 template <int BS, typename T, int MI, bool CG>
 int dispatch_nr(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg &cg, int K, int nr) {
+                const ApplyCg &cg, int K, int nr, bool fo) {
     switch (nr) {
-        case 1: return launch_phases<BS, T, MI, CG, 1>(f, r, z, s, done, cg, K);
-        case 4: return launch_phases<BS, T, MI, CG, 4>(f, r, z, s, done, cg, K);
-        case 8: return launch_phases<BS, T, MI, CG, 8>(f, r, z, s, done, cg, K);
-        case 16: return launch_phases<BS, T, MI, CG, 16>(f, r, z, s, done, cg, K);
+        case 1: return launch_phases<BS, T, MI, CG, 1>(f, r, z, s, done, cg, K, fo);
+        case 4: return launch_phases<BS, T, MI, CG, 4>(f, r, z, s, done, cg, K, fo);
+        case 8: return launch_phases<BS, T, MI, CG, 8>(f, r, z, s, done, cg, K, fo);
+        case 16: return launch_phases<BS, T, MI, CG, 16>(f, r, z, s, done, cg, K, fo);
         default: return fail(HBMC_EINVAL, "right-hand-side tile %d (1, 4, 8, 16)", nr);
     }
 }
@@ -617,23 +626,23 @@ int dispatch_nr(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_
 // couplings per step inside a level-1 block: <= 1, <= 2, or more (LDS path)
 template <int BS, typename T, bool CG>
 int dispatch_mi(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg &cg, int K, int nr) {
+                const ApplyCg &cg, int K, int nr, bool fo) {
     const int mi = std::max(f->max_int_step_f, f->max_int_step_b);
-    if (mi <= 1) return dispatch_nr<BS, T, 1, CG>(f, r, z, s, done, cg, K, nr);
-    if (BS <= 16 && mi <= 2) return dispatch_nr<BS, T, 2, CG>(f, r, z, s, done, cg, K, nr);
-    return dispatch_nr<BS, T, 0, CG>(f, r, z, s, done, cg, K, nr);
+    if (mi <= 1) return dispatch_nr<BS, T, 1, CG>(f, r, z, s, done, cg, K, nr, fo);
+    if (BS <= 16 && mi <= 2) return dispatch_nr<BS, T, 2, CG>(f, r, z, s, done, cg, K, nr, fo);
+    return dispatch_nr<BS, T, 0, CG>(f, r, z, s, done, cg, K, nr, fo);
 }
 
 template <int BS>
 int launch_bs(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-              const ApplyCg *cgp, int K, int nr) {
+              const ApplyCg *cgp, int K, int nr, bool fo) {
     if (!cgp) {
         const ApplyCg none{};
-        return f->precision == HBMC_F64 ? dispatch_mi<BS, double, false>(f, r, z, s, done, none, K, nr)
-                                        : dispatch_mi<BS, float, false>(f, r, z, s, done, none, K, nr);
+        return f->precision == HBMC_F64 ? dispatch_mi<BS, double, false>(f, r, z, s, done, none, K, nr, fo)
+                                        : dispatch_mi<BS, float, false>(f, r, z, s, done, none, K, nr, fo);
     }
-    return f->precision == HBMC_F64 ? dispatch_mi<BS, double, true>(f, cgp->r, z, s, done, *cgp, K, nr)
-                                    : dispatch_mi<BS, float, true>(f, cgp->r, z, s, done, *cgp, K, nr);
+    return f->precision == HBMC_F64 ? dispatch_mi<BS, double, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo)
+                                    : dispatch_mi<BS, float, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo);
 }
 
 }  // namespace

@@ -3,7 +3,8 @@ right-hand-side ICCG on the same GPU, at equal final true residual (every
 solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
 
 - fp32: FP32 factor and substitutions (FP64 CG) against FP64, on the
-  unstructured 13-NN Laplacian of 1M points;
+  unstructured 13-NN Laplacian of 1M points (many small color phases: bound
+  by latency) and on the 128^3 diffusion problem (bound by bandwidth);
 - batch: 128 Poisson systems of uneven size (16^3 .. 64^3) solved together
   (one set of launches per iteration, per-system stopping tests, FP32
   preconditioner) against solving them one by one in FP64;
@@ -11,7 +12,14 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
   together (factor read once per apply for all of them, autotuned
   right-hand-side tile, FP32 preconditioner) against 32 FP64 solves;
 - graph: the same solve with the iterations replayed as a hipGraph and
-  launched one by one.
+  launched one by one;
+- smoother: symmetric Gauss-Seidel / SSOR and forward Gauss-Seidel steps
+  on the HBMC substitution kernels (time per step, bytes per step), and
+  SSOR-preconditioned CG against IC(0)-preconditioned CG;
+- orderings: multi-color (bs = 1), block multi-color (w = 1: one block per
+  lane, rows of a lane 1 apart) and hierarchical block multi-color ordering
+  of the same problem, FP64: iterations, time and time per iteration (the
+  comparison of Section 5's tables, on one GPU).
 
 Setup (ordering, factorization, upload) is outside every timed region.
 """
@@ -67,6 +75,28 @@ def fp32(device, npts=1_000_000, bs=4, w=16, tol=1e-7, log=print):
         xs[name] = x.cpu().numpy()
         res[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
         log(f"[ext fp32] {name}: {t * 1e3:.2f} ms, {st.iters} its, true res {st.true_rel_res:.2e}")
+    res["speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
+    res["rel_diff_x_f32_vs_f64"] = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
+    return res
+
+
+def fp32_grid(device, N=128, bs=8, w=64, tol=1e-7, log=print):
+    """FP32 against FP64 preconditioner on the 128^3 diffusion problem, where
+    an iteration is bound by HBM bandwidth (the factor is half the bytes)."""
+    import torch
+    A = inputs.diffusion3d(N, 1.0, 2)
+    b = torch.from_numpy(inputs.uniform_rhs(A.n, 3)).to(device)
+    res = {"workload": f"diffusion3d {N}^3 lognormal sigma=1 seed 2, b~U[-1,1] seed 3, HBMC bs={bs} w={w}, "
+                       f"tol {tol:g}"}
+    o = hbmc.hbmc_order(A, bs, w)
+    m = hbmc.hbmc_matrix_create(o, A).upload(device)
+    xs = {}
+    for name, prec in (("f64", hbmc.HBMC_F64), ("f32", hbmc.HBMC_F32)):
+        sv = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).upload(device), m)
+        t, (x, st) = _timed(lambda: sv.solve(b, tol=tol))
+        xs[name] = x.cpu().numpy()
+        res[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
+        log(f"[ext fp32 grid] {name}: {t * 1e3:.2f} ms, {st.iters} its, true res {st.true_rel_res:.2e}")
     res["speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
     res["rel_diff_x_f32_vs_f64"] = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
     return res
@@ -151,3 +181,85 @@ def graph(solver, b, tol=1e-7, log=print):
         log(f"[ext graph] {name}: {t * 1e3:.2f} ms")
     out["speedup"] = round(out["eager"]["ms"] / out["graph"]["ms"], 3)
     return out
+
+
+def orderings(device, N=128, bs=8, w=64, tol=1e-7, log=print):
+    """MC, BMC and HBMC ICCG on the 128^3 diffusion problem.  MC is the
+    ordering with blocks of one unknown (more colors, more iterations); BMC
+    keeps the blocks but each lane walks its own block, so a warp touches
+    rows bs apart; HBMC has BMC's iterations with unit-stride lanes."""
+    import torch
+    A = inputs.diffusion3d(N, 1.0, 2)
+    b = torch.from_numpy(inputs.uniform_rhs(A.n, 3)).to(device)
+    res = {"workload": f"diffusion3d {N}^3 lognormal sigma=1 seed 2, b~U[-1,1] seed 3, FP64, tol {tol:g}"}
+    for name, obs, ow in (("mc", 1, w), ("bmc", bs, 1), ("hbmc", bs, w)):
+        t0 = time.perf_counter()
+        sv = hbmc.Solver.setup(A, obs, ow, hbmc.HBMC_F64, device=device)
+        setup = time.perf_counter() - t0
+        t, (x, st) = _timed(lambda: sv.solve(b, tol=tol))
+        res[name] = {"bs": obs, "w": ow, "colors": sv.order.n_colors, "ms": round(t * 1e3, 3),
+                     "ms_per_iter": round(t * 1e3 / max(1, st.iters), 4), "setup_s": round(setup, 2),
+                     **_stats(st)}
+        log(f"[ext orderings] {name} bs={obs} w={ow}: {sv.order.n_colors} colors, "
+            f"{st.iters} its, {t * 1e3:.2f} ms ({t * 1e3 / max(1, st.iters):.3f} ms/it)")
+        del sv
+    res["hbmc_vs_mc"] = round(res["mc"]["ms"] / res["hbmc"]["ms"], 3)
+    res["hbmc_vs_bmc"] = round(res["bmc"]["ms"] / res["hbmc"]["ms"], 3)
+    return res
+
+
+def smooth_bytes(n_pad: int, nnz_a: int, nnz_l: int, forward_only: bool = False) -> int:
+    """Algorithmic bytes of one FP64 smoothing step x += c M^-1 (b - A x):
+    the residual reads A (value and int32 index per entry), x and b and
+    writes r; the substitutions read L (value and index per entry, once per
+    direction), diaginv per direction, r, and write z (with the intermediate
+    y written and read back between the directions); the update reads x, z
+    and writes x."""
+    resid = nnz_a * 12 + 3 * n_pad * 8
+    if forward_only:
+        subst = nnz_l * 12 + 3 * n_pad * 8
+    else:
+        subst = 2 * nnz_l * 12 + 2 * n_pad * 8 + 2 * n_pad * 8 + 2 * n_pad * 8
+    return resid + subst + 3 * n_pad * 8
+
+
+def smoother(device, N=128, bs=8, w=64, steps=20, tol=1e-7, log=print):
+    """Smoothing steps and SSOR-PCG on the 128^3 diffusion problem (FP64)."""
+    import torch
+    A = inputs.diffusion3d(N, 1.0, 2)
+    b = inputs.uniform_rhs(A.n, 3)
+    res = {"workload": f"diffusion3d {N}^3 lognormal sigma=1 seed 2, b~U[-1,1] seed 3, HBMC bs={bs} w={w}, "
+                       f"FP64, {steps} steps timed"}
+    o = hbmc.hbmc_order(A, bs, w)
+    m = hbmc.hbmc_matrix_create(o, A).upload(device)
+    f = hbmc.ssor_factor(o, A, hbmc.HBMC_F64, 1.0).upload(device)
+    nnz_l = int(f.export()[1][-1])
+    nnz_a = int(A.rowptr[-1])
+    bb = hbmc.hbmc_to_hbmc(f, torch.from_numpy(b).to(device))
+    work = hbmc.smooth_workspace(f, 1, device)
+    stream = torch.cuda.current_stream()
+    for name, mode, fo in (("symmetric_gs", hbmc.HBMC_SMOOTH_SYMMETRIC, False),
+                           ("forward_gs", hbmc.HBMC_SMOOTH_FORWARD, True)):
+        x = torch.zeros_like(bb)
+        hbmc.hbmc_smooth(f, m, bb, x, sweeps=2, mode=mode, work=work)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        hbmc.hbmc_smooth(f, m, bb, x, sweeps=steps, mode=mode, work=work)
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        nbytes = smooth_bytes(f.n_pad, nnz_a, nnz_l, fo)
+        r = bb - hbmc.hbmc_spmv(m, x)
+        res[name] = {"ms_per_step": round(ms, 4), "bytes_per_step": nbytes,
+                     "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1),
+                     "rel_res_after": float(torch.linalg.norm(r) / torch.linalg.norm(bb))}
+        log(f"[ext smoother] {name}: {ms * 1e3:.1f} us/step, {nbytes / 1e6:.1f} MB -> "
+            f"{nbytes / (ms * 1e-3) / 1e9:.0f} GB/s")
+    bd = torch.from_numpy(b).to(device)
+    for name, omega in (("ic0_pcg", None), ("ssor_pcg", 1.0), ("ssor_pcg_1.5", 1.5)):
+        sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F64, device=device, omega=omega)
+        t, (x, st) = _timed(lambda: sv.solve(bd, tol=tol))
+        res[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
+        log(f"[ext smoother] {name}: {st.iters} its, {t * 1e3:.2f} ms")
+        del sv
+    return res

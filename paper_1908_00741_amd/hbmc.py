@@ -20,6 +20,7 @@ HBMC_OK, HBMC_EINVAL, HBMC_ENOTSYM, HBMC_EDIAG, HBMC_EBREAKDOWN = 0, -1, -2, -3,
 HBMC_EHIP, HBMC_ENOMEM, HBMC_ENOTREADY, HBMC_ENOCONV = -5, -6, -7, 1
 HBMC_F64, HBMC_F32 = 0, 1
 HBMC_KERNEL_AUTO, HBMC_KERNEL_SWEEP, HBMC_KERNEL_ROWS = 0, 1, 2
+HBMC_SMOOTH_SYMMETRIC, HBMC_SMOOTH_FORWARD = 0, 1
 
 # every symbol include/hbmc.h declares
 SYMBOLS = (
@@ -29,6 +30,8 @@ SYMBOLS = (
     "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
+    "ssor_factor", "hbmc_smooth_workspace_bytes", "hbmc_smooth",
+    "hbmc_factor_image", "hbmc_matrix_image", "hbmc_set_num_threads",
 )
 
 
@@ -93,6 +96,12 @@ def lib():
         L.iccg_workspace_bytes.argtypes = [P, i32, P]
         L.iccg_solve.argtypes = [P, P, P, P, i32, f64, i32, P, P, P, sz, P]
         L.iccg_history.argtypes = [P, sz, P, P, i32, P]
+        L.ssor_factor.argtypes = [P, P, P, P, i32, f64, P]
+        L.hbmc_smooth_workspace_bytes.argtypes = [P, i32, P]
+        L.hbmc_smooth.argtypes = [P, P, P, P, i32, i32, i32, P, sz, P]
+        L.hbmc_factor_image.argtypes = [P, P, sz]
+        L.hbmc_matrix_image.argtypes = [P, P, sz]
+        L.hbmc_set_num_threads.argtypes = [i32]
         _lib = L
     return _lib
 
@@ -182,6 +191,12 @@ class Factor:
     def handle(self):
         return self._h
 
+    def image(self) -> np.ndarray:
+        """Host copy of the device image (bytes)."""
+        out = np.empty(self.device_bytes(), np.uint8)
+        _check("hbmc_factor_image", lib().hbmc_factor_image(self._h, _ptr(out), out.size))
+        return out
+
     def export(self):
         """(d, lower_rowptr, lower_col, lower_val) of the FP64 factor."""
         nnz = C.c_int64(0)
@@ -230,6 +245,22 @@ def ic0_factor(order: Order, A, precision: int = HBMC_F64, shift: float = 0.0) -
     return Factor(h, order, precision)
 
 
+def set_num_threads(threads: int = 0) -> None:
+    """Host threads of the setup (0 = all hardware threads)."""
+    _check("hbmc_set_num_threads", lib().hbmc_set_num_threads(int(threads)))
+
+
+def ssor_factor(order: Order, A, precision: int = HBMC_F64, omega: float = 1.0) -> Factor:
+    """SSOR splitting of Abar (d = a_ii / omega, L = strict lower part of
+    Abar) in the factor's layout: a preconditioner for iccg_solve and the
+    operator of hbmc_smooth."""
+    rp, ci, v = _csr_arrays(A)
+    h = C.c_void_p()
+    _check("ssor_factor", lib().ssor_factor(order.handle, _ptr(rp), _ptr(ci), _ptr(v), precision,
+                                            float(omega), C.byref(h)))
+    return Factor(h, order, precision)
+
+
 class Matrix:
     """Handle of hbmc_matrix_create: Abar in sliced ELL."""
 
@@ -246,6 +277,12 @@ class Matrix:
         b = C.c_size_t(0)
         _check("hbmc_matrix_device_bytes", lib().hbmc_matrix_device_bytes(self._h, C.byref(b)))
         return b.value
+
+    def image(self) -> np.ndarray:
+        """Host copy of the device image (bytes)."""
+        out = np.empty(self.device_bytes(), np.uint8)
+        _check("hbmc_matrix_image", lib().hbmc_matrix_image(self._h, _ptr(out), out.size))
+        return out
 
     def upload(self, device="cuda", stream=None):
         import torch
@@ -286,6 +323,26 @@ def ic0_apply(f: Factor, r, z=None, nrhs: int = 1, stream=None):
     _vec_check(z, f.n_pad, nrhs, "z")
     _check("ic0_apply", lib().ic0_apply(f.handle, _dptr(r), _dptr(z), nrhs, _stream(stream)))
     return z
+
+
+def smooth_workspace(f: Factor, nrhs: int = 1, device="cuda"):
+    import torch
+    b = C.c_size_t(0)
+    _check("hbmc_smooth_workspace_bytes", lib().hbmc_smooth_workspace_bytes(f.handle, nrhs, C.byref(b)))
+    return torch.empty(max(b.value, 256), dtype=torch.uint8, device=device)
+
+
+def hbmc_smooth(f: Factor, m: Matrix, b, x, sweeps: int = 1, mode: int = HBMC_SMOOTH_SYMMETRIC,
+                nrhs: int = 1, work=None, stream=None):
+    """sweeps steps x <- x + c M^-1 (b - Abar x) in place on device vectors in
+    HBMC order ([n_pad][nrhs]); returns x."""
+    _vec_check(b, f.n_pad, nrhs, "b")
+    _vec_check(x, f.n_pad, nrhs, "x")
+    if work is None:
+        work = smooth_workspace(f, nrhs, x.device)
+    _check("hbmc_smooth", lib().hbmc_smooth(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, int(sweeps),
+                                            int(mode), _dptr(work), work.numel(), _stream(stream)))
+    return x
 
 
 def hbmc_spmv(m: Matrix, x, y=None, nrhs: int = 1, stream=None):
@@ -369,9 +426,13 @@ class Solver:
 
     @staticmethod
     def setup(A, bs: int, w: int, precision: int = HBMC_F64, shift: float = 0.0,
-              device="cuda", kernel: int = HBMC_KERNEL_AUTO, sys_ptr=None) -> "Solver":
+              device="cuda", kernel: int = HBMC_KERNEL_AUTO, sys_ptr=None,
+              omega: float | None = None) -> "Solver":
+        """IC(0) factor, or the SSOR splitting with relaxation omega when
+        omega is given."""
         o = hbmc_order(A, bs, w) if sys_ptr is None else hbmc_order_batch(A, sys_ptr, bs, w)
-        f = ic0_factor(o, A, precision, shift).set_kernel(kernel).upload(device)
+        f = ic0_factor(o, A, precision, shift) if omega is None else ssor_factor(o, A, precision, omega)
+        f = f.set_kernel(kernel).upload(device)
         m = hbmc_matrix_create(o, A).upload(device)
         return Solver(o, f, m)
 

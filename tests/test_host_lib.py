@@ -33,7 +33,7 @@ def test_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "hbmc.h")).read()
     header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
     declared = set(re.findall(r"\b([a-z0-9_]+)\s*\(", header)) - {"defined"}
-    declared = {d for d in declared if d.startswith(("hbmc_", "ic0_", "iccg_"))}
+    declared = {d for d in declared if d.startswith(("hbmc_", "ic0_", "iccg_", "ssor_"))}
     assert declared == set(hbmc.SYMBOLS)
     L = hbmc.lib()
     for name in declared:
@@ -98,6 +98,76 @@ def test_factor_shift(orc):
     d, *_ = hbmc.ic0_factor(o, A, shift=0.3).export()
     s = orc.system(A, 4, 8, shift=0.3)
     assert np.allclose(d, s.d, rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("omega", [1.0, 1.3])
+@pytest.mark.parametrize("name,make,bs,w", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_ssor_factor_matches_oracle(orc, name, make, bs, w, omega):
+    """The SSOR splitting is bit-exact: L is Abar's strict lower part and
+    d = abar_ii / omega, one rounding each on both sides."""
+    A = make()
+    f = hbmc.ssor_factor(hbmc.hbmc_order(A, bs, w), A, omega=omega)
+    d, rp, ci, v = f.export()
+    s = orc.system(A, bs, w)
+    dref, fac = orc.core.ssor_split(s.Ab, omega)
+    L = sp.tril(sp.csr_matrix((fac, s.Ab.col, s.Ab.rowptr), shape=(s.Ab.n, s.Ab.n)), k=-1).tocsr()
+    L.sort_indices()
+    assert np.array_equal(rp, L.indptr) and np.array_equal(ci, L.indices)
+    assert np.array_equal(v, L.data) and np.array_equal(d, dref)
+
+
+def test_ssor_factor_errors():
+    A = inputs.grid2d_5pt(6)
+    o = hbmc.hbmc_order(A, 4, 8)
+    for bad in (0.0, 2.0, -0.5, float("nan")):
+        with pytest.raises(hbmc.HbmcError) as e:
+            hbmc.ssor_factor(o, A, omega=bad)
+        assert e.value.code == hbmc.HBMC_EINVAL
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ssor_factor(o, _bad(A, p0=-1.0))    # negative diagonal
+    assert e.value.code == hbmc.HBMC_EDIAG
+
+
+@pytest.mark.parametrize("name,make,bs,w", [
+    ("diff3d_40_bs8_w64", lambda: inputs.diffusion3d(40, 1.0, 2), 8, 64),
+    ("knn_40000_bs4_w16", lambda: inputs.knn_laplacian(40000, 13, 4, 5), 4, 16),
+    ("random_bs2_w32", lambda: inputs.random_spd(30000, 0.0002, 8), 2, 32),
+    ("grid_ragged_bs4_w8", lambda: inputs.grid2d_5pt(301, 257), 4, 8),
+])
+def test_setup_independent_of_threads(name, make, bs, w):
+    """The parallel setup (chunks joined in order, colors in turn) gives the
+    same device images, bit for bit, for any number of threads; the kNN case
+    has off-diagonal IC(0) updates inside level-1 blocks and across colors."""
+    A = make()
+    images = []
+    try:
+        for t in (1, 3, 8):
+            hbmc.set_num_threads(t)
+            o = hbmc.hbmc_order(A, bs, w)
+            images.append((hbmc.ic0_factor(o, A).image(), hbmc.ssor_factor(o, A, omega=1.3).image(),
+                            hbmc.hbmc_matrix_create(o, A).image(), o.perm()[0]))
+    finally:
+        hbmc.set_num_threads(0)
+    for other in images[1:]:
+        for a, b in zip(images[0], other):
+            assert np.array_equal(a, b)
+
+
+def test_setup_threads_batch():
+    mats = [inputs.poisson3d(n) for n in (9, 14, 11)]
+    A, sys_ptr = inputs.block_diag(mats)
+    images = []
+    try:
+        for t in (1, 5):
+            hbmc.set_num_threads(t)
+            o = hbmc.hbmc_order_batch(A, sys_ptr, 4, 16)
+            images.append((hbmc.ic0_factor(o, A).image(), hbmc.hbmc_matrix_create(o, A).image()))
+    finally:
+        hbmc.set_num_threads(0)
+    assert all(np.array_equal(a, b) for a, b in zip(*images))
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.set_num_threads(-1)
+    assert e.value.code == hbmc.HBMC_EINVAL
 
 
 def _bad(A, **kw):
