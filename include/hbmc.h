@@ -168,7 +168,7 @@ int hbmc_matrix_image(const hbmc_matrix_t *m, void *host, size_t bytes);
 
 /* Host threads used by the setup (hbmc_order*, ic0_factor, ssor_factor,
  * hbmc_matrix_create): permutation, factorization (the colors in turn, the
- * level-1 blocks of a color in parallel, Section 4.2) and layout packing
+ * level-1 blocks of a color in parallel, Section 4.3) and layout packing
  * (tiles in parallel chunks joined in order).  0 (the default) = all
  * hardware threads.  Results are the same bits for every setting.  A
  * process-wide setting; HBMC_EINVAL for threads < 0. */
@@ -206,7 +206,7 @@ void hbmc_factor_destroy(hbmc_factor_t *f);
 /* ---- preconditioning step --------------------------------------------------
  * ic0_apply: z = M^-1 r, i.e. the forward substitution y = L^-1 r and the
  * backward substitution z = U^-1 y (Section 2, eqs. "for" and "back"), run
- * color by color (Section 4.2.2, eqs. "for2", "for3", "BAMC3"): within a
+ * color by color (Section 4.3, eqs. "for2", "for3", "BAMC3"): within a
  * color the level-1 blocks are independent, and inside a level-1 block the
  * bs steps of eqs. "y2-2", "y2-3" each solve w independent rows.  The
  * backward substitution runs the colors in reverse.

@@ -64,8 +64,8 @@ struct Levels {
 
 // The strictly lower pattern of Abar (row pointers); checks that no
 // coupling joins two level-1 blocks of one color or two lanes of one
-// level-1 block (Section 4.2: the blocks of a color are independent), which
-// the parallel factorization relies on.
+// level-1 block (Section 4.3, eq. "BAMC1": the level-1 blocks of a color are
+// independent), which the parallel factorization relies on.
 int lower_pattern(const Csr &a, int64_t n, const Levels &lv, std::vector<int64_t> &lrp) {
     lrp.assign(n + 1, 0);
     for (size_t c = 0; c + 1 < lv.color_start.size(); ++c) {

@@ -4,7 +4,7 @@
 // parallel.
 //
 // Forward substitution y = L^-1 r, then backward substitution z = U^-1 y
-// (Section 2), color by color (Section 4.2.2): one kernel launch per color
+// (Section 2), color by color (Section 4.3): one kernel launch per color
 // phase, the launch boundary being the synchronization between colors
 // (Section 4.4.3).  The last color runs its forward and backward sweeps in
 // one launch, since no later color feeds its backward sweep.
