@@ -105,6 +105,7 @@ struct Mat {
     const int32_t *icol;
     const double *ival;
     int64_t n;
+    bool fuse_p;             // host side: one right-hand side forms p inside the product
 };
 
 __device__ inline uint64_t readlane64(uint64_t v, int lane) {
@@ -541,7 +542,8 @@ Mat mat_of(const hbmc_matrix_s *m) {
     return Mat{at<double>(m->dev, m->off_diag), at<int32_t>(m->dev, o.soff),
                at<int32_t>(m->dev, o.sbase), at<uint64_t>(m->dev, o.smask),
                at<double>(m->dev, o.sval), at<int32_t>(m->dev, o.ioff),
-               at<int32_t>(m->dev, o.icol), at<double>(m->dev, o.ival), m->n_pad};
+               at<int32_t>(m->dev, o.icol), at<double>(m->dev, o.ival),
+               m->n_pad, m->fuse_p};
 }
 
 Sys sys_of(const hbmc_factor_s *f) {
@@ -638,7 +640,7 @@ inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock -
 
 // One CG iteration (everything after the first preconditioning step); the
 // direction is read from p[parity] and written to p[1 - parity].
-//   q = A p, p = z + beta p_old (two kernels for several right-hand sides)  |  alpha = rho / (p, q)  |
+//   q = A p, p = z + beta p_old (two kernels for several right-hand sides or a mostly indexed matrix)  |  alpha = rho / (p, q)  |
 //   x += alpha p, r -= alpha q, z = M^-1 r, partials of ||r||^2 and (r, z)  |
 //   stopping test, beta
 int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipStream_t s,
@@ -647,7 +649,7 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
     const int K = w.K;
     const unsigned nst = unsigned(f->nsys) * K;
     double *p_old = w.p[parity], *p_new = w.p[1 - parity];
-    if (K == 1) {
+    if (K == 1 && m.fuse_p) {
         VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     } else {
         VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);

@@ -671,6 +671,11 @@ extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, 
         }
         for (const Packed &pk : part) m->off.append(pk);
         part.clear();
+        {
+            int64_t strided = 0;
+            for (uint64_t mask : m->off.smask) strided += __builtin_popcountll(mask);
+            m->fuse_p = 2 * strided >= m->off.entries;
+        }
         m->off.finish();
         {
             const Packed &e = m->off;

@@ -230,6 +230,10 @@ struct hbmc_matrix_s {
     int64_t n_pad = 0;
     std::vector<double> diag;   // [n_pad]
     hbmc::Packed off;           // off-diagonal entries, 64-row slices from row 0
+    // CG forms the search direction inside the product (gathering z and the
+    // old direction at every coupling) when most couplings sit in strided
+    // slots; otherwise it updates the direction first and gathers it alone
+    bool fuse_p = true;
     hbmc::ImageBuilder image;
     size_t off_diag = 0;
     PackedOffsets offs{};
