@@ -80,8 +80,12 @@ struct Sys {
 constexpr int kLoads = 16;
 __device__ inline double sys_total(const double *part, const int32_t *ranges, int nc, int s, int tmul) {
     double acc = 0.0;
-    for (int c = 0; c < nc; ++c) {
-        const int a = ranges[(s * nc + c) * 2] * tmul, b = ranges[(s * nc + c) * 2 + 1] * tmul;
+    for (int c = 0; c < nc;) {
+        // ranges of consecutive colors that meet are summed as one (a single
+        // system's partials are one range over all colors)
+        const int a = ranges[(s * nc + c) * 2] * tmul;
+        int b = ranges[(s * nc + c) * 2 + 1] * tmul;
+        for (++c; c < nc && ranges[(s * nc + c) * 2] * tmul == b; ++c) b = ranges[(s * nc + c) * 2 + 1] * tmul;
         for (int i0 = a + int(threadIdx.x); i0 < b; i0 += kFin * kLoads) {
             double v[kLoads];
 #pragma unroll
