@@ -427,7 +427,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
                 s.col.resize((base + len) * kTileLanes, -1);
                 for (int j = 0; j < kTileLanes; ++j)
                     for (size_t t = 0; t < ls[j].size(); ++t) {
-                        s.col[(base + t) * kTileLanes + j] = ls[j][t].first;
+                        s.col[(base + t) * kTileLanes + j] = int8_t(ls[j][t].first);
                         s.val[(base + t) * kTileLanes + j] = ls[j][t].second;
                     }
                 tile_slots += int32_t(len);

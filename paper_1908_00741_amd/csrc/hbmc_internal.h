@@ -33,11 +33,13 @@ constexpr int kMinStridedLanes = 48;
 int check_csr(int32_t n, const int64_t *rowptr, const int32_t *col, const double *val);
 
 // A sliced-ELL array on the host: slot offsets per slice, then slot-major
-// values and columns, kTileLanes entries per slot.
+// values and columns, kTileLanes entries per slot.  Used for the couplings
+// inside level-1 blocks, whose "column" is the source step (0..bs-1, -1 for
+// none): one byte each.
 struct Sell {
     std::vector<int32_t> off;   // [slices + 1]
     std::vector<double> val;    // [slots * kTileLanes]
-    std::vector<int32_t> col;   // [slots * kTileLanes]
+    std::vector<int8_t> col;    // [slots * kTileLanes]
     int64_t slots() const { return off.empty() ? 0 : off.back(); }
     // room for the slices of parts (before appending them)
     void reserve_for(const std::vector<const Sell *> &parts) {

@@ -90,7 +90,7 @@ struct Tri {
     Ext ext;
     const int32_t *int_off;
     const void *int_val;
-    const int32_t *int_lp;
+    const int8_t *int_lp;    // source step of each in-block coupling (-1: none)
     int64_t int_pad;
 };
 
@@ -251,7 +251,7 @@ __device__ inline void stage_steps(const Tri &E, int64_t gt, int l0, int l1, int
     const int64_t ib = E.int_off[gt];
     const int64_t s0 = E.int_off[gt + l0] - ib, s1 = E.int_off[gt + l1] - ib;
     const T *val = static_cast<const T *>(E.int_val) + ib * kLanes;
-    const int32_t *lp = E.int_lp + ib * kLanes;
+    const int8_t *lp = E.int_lp + ib * kLanes;
 #pragma unroll 4
     for (int64_t s = s0; s < s1; ++s) {
         sv[s * kLanes + jc] = val[s * kLanes + jc];
@@ -525,7 +525,7 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
                    dev_at<int32_t>(f->dev, x.ioff), dev_at<int32_t>(f->dev, x.icol),
                    dev_at<void>(f->dev, x.ival), e.strided(), e.indexed()},
                dev_at<int32_t>(f->dev, o.int_off), dev_at<void>(f->dev, o.int_val),
-               dev_at<int32_t>(f->dev, o.int_lp), i.slots()};
+               dev_at<int8_t>(f->dev, o.int_lp), i.slots()};
 }
 
 // Which kernel runs the phases: one wavefront per tile (k_sweep) or one
