@@ -106,6 +106,8 @@ struct Mat {
     const uint64_t *smask;
     const double *sval;
     const int32_t *ioff;
+    const uint64_t *imask;   // lanes of each indexed slot
+    const int64_t *ivoff;    // first packed entry of each indexed slot
     const int32_t *icol;
     const double *ival;
     int64_t n;
@@ -211,8 +213,11 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) 
     }
 #pragma unroll 4
     for (int64_t s = m.ioff[g]; s < m.ioff[g + 1]; ++s) {
-        const int64_t e = s * kLanes + jc;
-        const int32_t c = m.icol[e];
+        // packed slot: lane jc's entry is its rank among the slot's lanes
+        const uint64_t mask = m.imask[s];
+        const bool on = (mask >> jc) & 1;
+        const int64_t e = m.ivoff[s] + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
+        const int32_t c = on ? m.icol[e] : -1;
         const double v = m.ival[e];
         const double xv = x((c >= 0 ? c : 0) * int64_t(K) + r.q);
         acc = c >= 0 ? acc + v * xv : acc;
@@ -546,6 +551,7 @@ Mat mat_of(const hbmc_matrix_s *m) {
     return Mat{at<double>(m->dev, m->off_diag), at<int32_t>(m->dev, o.soff),
                at<int32_t>(m->dev, o.sbase), at<uint64_t>(m->dev, o.smask),
                at<double>(m->dev, o.sval), at<int32_t>(m->dev, o.ioff),
+               at<uint64_t>(m->dev, o.imask), at<int64_t>(m->dev, o.ivoff),
                at<int32_t>(m->dev, o.icol), at<double>(m->dev, o.ival),
                m->n_pad, m->fuse_p};
 }

@@ -186,6 +186,8 @@ size_t add_packed(ImageBuilder &im, const Packed &p, bool f32, PackedOffsets &o)
     o.smask = im.add(p.smask);
     o.sval = f32 ? im.add(cast<float>(p.sval)) : im.add(p.sval);
     o.ioff = im.add(p.ioff);
+    o.imask = im.add(p.imask);
+    o.ivoff = im.add(p.ivoff);
     o.icol = im.add(p.icol);
     o.ival = f32 ? im.add(cast<float>(p.ival)) : im.add(p.ival);
     return o.soff;
@@ -241,44 +243,55 @@ int Packed::add_group(const std::vector<CouplingSpan> &lanes, int64_t limit, int
     }
     soff.push_back(int32_t(sbase.size()));
     max_strided = std::max(max_strided, int32_t(cands.size()));
-    // the rest, per lane in column order, as indexed slots
+    // the rest, per lane in column order, as indexed slots: slot t holds the
+    // t-th left-over coupling of each lane that has one, in lane order
+    thread_local std::vector<int32_t> left;   // left-over entries of each lane, lane by lane
+    thread_local std::vector<int32_t> lfirst;
+    left.clear();
+    lfirst.assign(nl + 1, 0);
     int32_t len = 0;
     for (int j = 0; j < nl; ++j) {
-        int32_t left = 0;
-        for (int32_t i = first[j]; i < first[j + 1]; ++i) left += !used[i];
-        len = std::max(len, left);
+        for (int32_t i = first[j]; i < first[j + 1]; ++i)
+            if (!used[i]) left.push_back(i - first[j]);
+        lfirst[j + 1] = int32_t(left.size());
+        len = std::max(len, lfirst[j + 1] - lfirst[j]);
     }
     const int64_t base = ioff.back();
     ioff.push_back(int32_t(base + len));
-    icol.resize((base + len) * kTileLanes, -1);
-    ival.resize((base + len) * kTileLanes, 0.0);
-    for (int j = 0; j < nl; ++j) {
-        int64_t t = 0;
-        for (size_t i = 0; i < lanes[j].size(); ++i)
-            if (!used[first[j] + i]) {
-                icol[(base + t) * kTileLanes + j] = lanes[j][i].first;
-                ival[(base + t) * kTileLanes + j] = lanes[j][i].second;
-                ++t;
-            }
+    for (int32_t t = 0; t < len; ++t) {
+        uint64_t mask = 0;
+        ivoff.push_back(int64_t(icol.size()));
+        for (int j = 0; j < nl; ++j) {
+            if (lfirst[j] + t >= lfirst[j + 1]) continue;
+            const Coupling &c = lanes[j][left[lfirst[j] + t]];
+            mask |= uint64_t(1) << j;
+            icol.push_back(c.first);
+            ival.push_back(c.second);
+        }
+        imask.push_back(mask);
     }
     max_indexed = std::max(max_indexed, len);
     return int(cands.size());
 }
 
 void Packed::reserve_for(const std::vector<const Packed *> &parts) {
-    size_t so = soff.size(), sb = sbase.size(), sv = sval.size(), io = ioff.size(), iv = icol.size();
+    size_t so = soff.size(), sb = sbase.size(), sv = sval.size(), io = ioff.size(), is = imask.size(),
+           iv = icol.size();
     for (const Packed *p : parts) {
         so += p->soff.size(); sb += p->sbase.size(); sv += p->sval.size();
-        io += p->ioff.size(); iv += p->icol.size();
+        io += p->ioff.size(); is += p->imask.size(); iv += p->icol.size();
     }
     soff.reserve(so); sbase.reserve(sb + 1); smask.reserve(sb + 1); sval.reserve(sv + kTileLanes);
-    ioff.reserve(io); icol.reserve(iv + kTileLanes); ival.reserve(iv + kTileLanes);
+    ioff.reserve(io); imask.reserve(is + 1); ivoff.reserve(is + 1); icol.reserve(iv + 1); ival.reserve(iv + 1);
 }
 
 void Packed::append(const Packed &o) {
     const int32_t sb = soff.back(), ib = ioff.back();
+    const int64_t eb = int64_t(icol.size());
     for (size_t i = 1; i < o.soff.size(); ++i) soff.push_back(sb + o.soff[i]);
     for (size_t i = 1; i < o.ioff.size(); ++i) ioff.push_back(ib + o.ioff[i]);
+    for (int64_t v : o.ivoff) ivoff.push_back(eb + v);
+    imask.insert(imask.end(), o.imask.begin(), o.imask.end());
     sbase.insert(sbase.end(), o.sbase.begin(), o.sbase.end());
     smask.insert(smask.end(), o.smask.begin(), o.smask.end());
     sval.insert(sval.end(), o.sval.begin(), o.sval.end());
@@ -293,8 +306,10 @@ void Packed::finish() {
     sbase.push_back(0);
     smask.push_back(0);
     sval.resize(sval.size() + kTileLanes, 0.0);
-    icol.resize(icol.size() + kTileLanes, -1);
-    ival.resize(ival.size() + kTileLanes, 0.0);
+    imask.push_back(0);                       // the padding slot: no lanes, one dummy entry
+    ivoff.push_back(int64_t(icol.size()));
+    icol.push_back(-1);
+    ival.push_back(0.0);
 }
 
 namespace {
@@ -543,8 +558,8 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
             size_t est = 256 + vb(dinv) + vb(f->perm) + vb(f->iperm) + vb(f->tile_sys) + vb(f->part_sys) +
                          vb(f->sys_tiles) + vb(f->sys_parts);
             for (const Packed *e : {&f->fext, &f->bext})
-                est += vb(e->soff) + vb(e->sbase) + vb(e->smask) + vb(e->sval) + vb(e->ioff) + vb(e->icol) +
-                       vb(e->ival);
+                est += vb(e->soff) + vb(e->sbase) + vb(e->smask) + vb(e->sval) + vb(e->ioff) + vb(e->imask) +
+                       vb(e->ivoff) + vb(e->icol) + vb(e->ival);
             for (const Sell *i : {&f->fint, &f->bint}) est += vb(i->off) + vb(i->col) + vb(i->val);
             im.bytes.reserve(est);
         }
@@ -681,7 +696,7 @@ extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, 
             const Packed &e = m->off;
             auto vb = [](const auto &v) { return v.size() * sizeof(v[0]) + 256; };
             m->image.bytes.reserve(256 + vb(m->diag) + vb(e.soff) + vb(e.sbase) + vb(e.smask) + vb(e.sval) +
-                                   vb(e.ioff) + vb(e.icol) + vb(e.ival));
+                                   vb(e.ioff) + vb(e.imask) + vb(e.ivoff) + vb(e.icol) + vb(e.ival));
         }
         m->off_diag = m->image.add(m->diag);
         add_packed<double>(m->image, m->off, false, m->offs);

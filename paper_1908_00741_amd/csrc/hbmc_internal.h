@@ -92,15 +92,6 @@ void release_graphs(::hbmc_factor_s *f);
 // Unique id for each upload of a device image (keys the graph cache).
 uint64_t next_uid();
 
-// Couplings of groups of kTileLanes rows, one row per lane, in two kinds of
-// slots.  A strided slot has one base per slot: lane j couples to column
-// base + j when bit j of the slot's lane mask is set.  On HBMC-ordered
-// structured grids most couplings line up this way, because the 64 lanes
-// are 64 consecutive BMC blocks whose neighbours are consecutive too; such
-// a slot needs no index array and its loads do not wait for indices.  What
-// does not line up goes to indexed slots (one column per lane, -1 = none).
-// Each array ends with one all-padding slot that loads may target instead
-// of branching.
 // Allocator whose resize() leaves new elements of trivial types
 // uninitialized: large setup arrays are first written by the threads that
 // fill them, not zeroed by one thread beforehand.
@@ -132,14 +123,28 @@ struct CouplingRows {
     RawVec<Coupling> data;
     CouplingSpan row(int64_t r) const { return {data.data() + ptr[r], size_t(ptr[r + 1] - ptr[r])}; }
 };
+// Couplings of groups of kTileLanes rows, one row per lane, in two kinds of
+// slots.  A strided slot has one base per slot: lane j couples to column
+// base + j when bit j of the slot's lane mask is set.  On HBMC-ordered
+// structured grids most couplings line up this way, because the 64 lanes
+// are 64 consecutive BMC blocks whose neighbours are consecutive too; such
+// a slot needs no index array and its loads do not wait for indices.  What
+// does not line up goes to indexed slots: slot t of a group holds the t-th
+// left-over coupling of every lane that has one, packed in lane order (the
+// lane mask says which lanes; lane j's entry is number popcount(mask below
+// j) from the slot's first entry), so that lanes without one cost nothing.
+// Each array ends with one all-padding slot that loads may target instead
+// of branching.
 struct Packed {
     std::vector<int32_t> soff{0};   // [groups + 1] strided slots per group
     std::vector<int32_t> sbase;     // [strided + 1]
     std::vector<uint64_t> smask;    // [strided + 1]
     std::vector<double> sval;       // [(strided + 1) * kTileLanes]
     std::vector<int32_t> ioff{0};   // [groups + 1] indexed slots per group
-    std::vector<int32_t> icol;      // [(indexed + 1) * kTileLanes]
-    std::vector<double> ival;       // [(indexed + 1) * kTileLanes]
+    std::vector<uint64_t> imask;    // [indexed + 1] lanes with an entry in the slot
+    std::vector<int64_t> ivoff;     // [indexed + 1] the slot's first entry in icol / ival
+    std::vector<int32_t> icol;      // [entries in indexed slots + 1] columns
+    std::vector<double> ival;       // [entries in indexed slots + 1] values
     int32_t max_strided = 0, max_indexed = 0;   // per group
     int64_t entries = 0;                        // couplings stored
     // lanes[j]: couplings of lane j's row (sorted by column), or null.
@@ -175,7 +180,7 @@ struct hbmc_order_s {
 
 // Offsets (bytes, inside a device image) of a Packed layout.
 struct PackedOffsets {
-    size_t soff, sbase, smask, sval, ioff, icol, ival;
+    size_t soff, sbase, smask, sval, ioff, imask, ivoff, icol, ival;
 };
 
 // Offsets of one triangular direction.

@@ -79,10 +79,20 @@ struct Ext {
     const uint64_t *smask;
     const void *sval;
     const int32_t *ioff;
+    const uint64_t *imask;   // lanes of each indexed slot
+    const int64_t *ivoff;    // first packed entry of each indexed slot
     const int32_t *icol;
     const void *ival;
     int64_t spad, ipad;   // index of the padding slots
 };
+
+// Entry of chain lane jc in a packed indexed slot (mask, first entry): its
+// rank among the slot's lanes; a lane without an entry reads the slot's
+// first entry (every slot has one) and must not use it.
+__device__ inline int64_t packed_entry(uint64_t mask, int64_t first, int jc, bool &on) {
+    on = (mask >> jc) & 1;
+    return first + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
+}
 
 // One direction: couplings to other colors (ext) and inside the level-1
 // block (int).
@@ -154,7 +164,8 @@ struct Lane {
 // product.  Strided slots read z[base + jc]; the bases and lane masks of the
 // tile's strided slots (at most 64) are fetched by one vector load, one slot
 // per lane, and broadcast with readlane, so no load waits on another.
-// Indexed slots first load the lane's column.
+// Indexed slots first load the slot's lane mask and first entry, then the
+// lane's column.
 template <int BS, int CH, typename T>
 __device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
                                  const double *__restrict__ z) {
@@ -207,8 +218,11 @@ __device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, c
         for (int l = 0; l < BS; ++l)
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                const int64_t e = (c0 + k < io[l + 1] - io[l] ? int64_t(io[l]) + c0 + k : E.ipad) * kLanes + jc;
-                col[l][k] = E.icol[e];
+                const int64_t slot = c0 + k < io[l + 1] - io[l] ? int64_t(io[l]) + c0 + k : E.ipad;
+                bool on;
+                const int64_t e = packed_entry(E.imask[slot], E.ivoff[slot], jc, on);
+                const int32_t c = E.icol[e];
+                col[l][k] = on ? c : -1;
                 v[l][k] = val[e];
             }
         T g[BS][CH];
@@ -522,7 +536,8 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
     const PackedOffsets &x = o.ext;
     return Tri{Ext{dev_at<int32_t>(f->dev, x.soff), dev_at<int32_t>(f->dev, x.sbase),
                    dev_at<uint64_t>(f->dev, x.smask), dev_at<void>(f->dev, x.sval),
-                   dev_at<int32_t>(f->dev, x.ioff), dev_at<int32_t>(f->dev, x.icol),
+                   dev_at<int32_t>(f->dev, x.ioff), dev_at<uint64_t>(f->dev, x.imask),
+                   dev_at<int64_t>(f->dev, x.ivoff), dev_at<int32_t>(f->dev, x.icol),
                    dev_at<void>(f->dev, x.ival), e.strided(), e.indexed()},
                dev_at<int32_t>(f->dev, o.int_off), dev_at<void>(f->dev, o.int_val),
                dev_at<int8_t>(f->dev, o.int_lp), i.slots()};
