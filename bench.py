@@ -77,9 +77,9 @@ def main() -> int:
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--ext", default="fp32,fp32_grid,batch,rhs,graph,orderings,smoother",
+    ap.add_argument("--ext", default="fp32,fp32_grid,batch,rhs,graph,orderings,smoother,refactor",
                     help="comma-separated extension comparisons to run after the headline "
-                         "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother); empty for none")
+                         "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother, refactor); empty for none")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--calibrate", action="store_true",
                     help="first run dst = 2 * src on 256 MiB tensors, a kernel that reads "
@@ -202,6 +202,8 @@ def main() -> int:
                     ext[name] = experiments.orderings(dev, log=log)
                 elif name == "smoother":
                     ext[name] = experiments.smoother(dev, log=log)
+                elif name == "refactor":
+                    ext[name] = experiments.refactor(dev, log=log)
                 elif name == "batch":
                     ext[name] = experiments.batch(dev, log=log)
                 elif name == "rhs":

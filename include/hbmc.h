@@ -59,6 +59,7 @@ extern "C" {
 typedef struct hbmc_order_s hbmc_order_t;
 typedef struct hbmc_factor_s hbmc_factor_t;
 typedef struct hbmc_matrix_s hbmc_matrix_t;
+typedef struct hbmc_revalue_s hbmc_revalue_t;
 
 /* Message of the last error raised on the calling thread ("" if none). */
 const char *hbmc_last_error(void);
@@ -271,6 +272,36 @@ int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);
 int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
                int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
                hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
+
+/* ---- new values, same pattern: factor and matrix rebuilt on the device ------
+ * For sequences of matrices with one sparsity pattern (time steps, nonlinear
+ * iterations): the ordering and the layouts stay, and the numeric work runs
+ * on the GPU.  ic0_refactor recomputes IC(0) (Section 2, eq. "ILU"; the same
+ * arithmetic, term for term, as ic0_factor) with the colors in turn and the
+ * level-1 blocks of a color in parallel (Section 4.3: a row needs only rows
+ * of earlier colors and earlier rows of its own chain), one thread per BMC
+ * block, then rewrites the factor's device values in place (L, U = D^-1 L^T,
+ * diaginv).  hbmc_matrix_revalue rewrites Abar's device values.
+ * hbmc_revalue_create: from the order and the caller's CSR pattern (the one
+ * given to ic0_factor / hbmc_matrix_create); host arrays are read during
+ * the call only.  Device memory: hbmc_revalue_device_bytes, caller-
+ * allocated, 256-byte aligned, passed to hbmc_revalue_upload (pattern data
+ * and scratch for the factorization).
+ * val: device FP64 values in the caller's CSR order (rowptr[n] entries),
+ * symmetric with a positive diagonal (not checked on the device).
+ * ic0_refactor: f from ic0_factor (HBMC_EINVAL for an SSOR factor), uploaded,
+ * same order; shift as for ic0_factor.  Synchronous (reads the pivot check):
+ * HBMC_EBREAKDOWN if a pivot is not > 0, after which f must not be used until
+ * a successful refactor.  hbmc_matrix_revalue: asynchronous on stream.
+ * Errors: HBMC_EINVAL (mismatched sizes, order or pattern), HBMC_ENOTREADY,
+ * HBMC_EHIP. */
+int hbmc_revalue_create(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
+                        hbmc_revalue_t **out);
+int hbmc_revalue_device_bytes(const hbmc_revalue_t *rv, size_t *bytes);
+int hbmc_revalue_upload(hbmc_revalue_t *rv, void *dev, size_t bytes, void *stream);
+void hbmc_revalue_destroy(hbmc_revalue_t *rv);
+int ic0_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double shift, void *stream);
+int hbmc_matrix_revalue(hbmc_matrix_t *m, const hbmc_revalue_t *rv, const double *val, void *stream);
 
 /* ---- smoother ----------------------------------------------------------------
  * hbmc_smooth: sweeps steps of  x <- x + c M^-1 (b - Abar x)  (Section 2: the

@@ -348,6 +348,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
                                  : ssor_rows(a, n, param, lv, f->lrp, f->lcol, f->lval, f->d);
         if (st) { delete f; return st; }
         f->smooth_scale = kind == Split::kSsor ? 2.0 - param : 1.0;
+        f->ssor = kind == Split::kSsor;
 
         std::vector<double> dinv(n);
         // color of each HBMC row
@@ -715,3 +716,75 @@ extern "C" int hbmc_matrix_device_bytes(const hbmc_matrix_t *m, size_t *bytes) {
 }
 
 extern "C" void hbmc_matrix_destroy(hbmc_matrix_t *m) { delete m; }
+
+// ---------------------------------------------------------------------------
+// Pattern data for device refactorization
+// ---------------------------------------------------------------------------
+extern "C" int hbmc_revalue_create(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col,
+                                   hbmc_revalue_t **out) {
+    clear_error();
+    if (!out) return fail(HBMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!o) return fail(HBMC_EINVAL, "null argument");
+    int st = check_csr(o->n, rowptr, col, nullptr);
+    if (st) return st;
+    try {
+        auto *rv = new hbmc_revalue_s;
+        rv->n = o->n; rv->bs = o->bs; rv->w = o->w; rv->nc = o->nc;
+        rv->n_pad = o->n_pad;
+        rv->nnz = rowptr[o->n];
+        rv->color_start = o->color_start;
+        rv->tile_base.assign(o->nc + 1, 0);
+        for (int c = 0; c < o->nc; ++c) {
+            const int64_t lanes = (o->color_start[c + 1] - o->color_start[c]) / o->bs;
+            rv->tile_base[c + 1] = rv->tile_base[c] + (lanes + kTileLanes - 1) / kTileLanes;
+        }
+        // Abar's pattern with the source entry of every value: the caller's
+        // entry positions, permuted like the values
+        std::vector<double> pos(size_t(rv->nnz));
+        for (int64_t p = 0; p < rv->nnz; ++p) pos[p] = double(p);   // exact below 2^53
+        const Csr a = permute(*o, rowptr, col, pos.data());
+        pos.clear();
+        pos.shrink_to_fit();
+        const int64_t n = rv->n_pad;
+        rv->arp.assign(a.rp.begin(), a.rp.end());
+        rv->aci.assign(a.ci.begin(), a.ci.end());
+        rv->amap.resize(a.v.size());
+        parallel_for(n, kGrain, [&](int64_t r) {
+            for (int64_t p = a.rp[r]; p < a.rp[r + 1]; ++p)
+                rv->amap[p] = o->iperm[r] < 0 ? -1 : int64_t(a.v[p]);
+        });
+        const Levels lv{rv->color_start, int64_t(o->bs) * o->w, o->w};
+        if ((st = lower_pattern(a, n, lv, rv->lrp))) { delete rv; return st; }
+        rv->lcol.resize(rv->lrp[n]);
+        parallel_for(n, kGrain, [&](int64_t r) {
+            int64_t q = rv->lrp[r];
+            for (int64_t p = a.rp[r]; p < a.rp[r + 1] && a.ci[p] < r; ++p) rv->lcol[q++] = a.ci[p];
+        });
+        auto &im = rv->image;
+        rv->off_cs = im.add(rv->color_start);
+        rv->off_tb = im.add(rv->tile_base);
+        rv->off_arp = im.add(rv->arp);
+        rv->off_aci = im.add(rv->aci);
+        rv->off_amap = im.add(rv->amap);
+        rv->off_lrp = im.add(rv->lrp);
+        rv->off_lcol = im.add(rv->lcol);
+        auto up = [](size_t x) { return (x + 255) & ~size_t(255); };
+        rv->off_lval = up(im.bytes.size());
+        rv->off_d = up(rv->off_lval + rv->lcol.size() * sizeof(double));
+        rv->off_flag = up(rv->off_d + size_t(n) * sizeof(double));
+        rv->scratch_end = up(rv->off_flag + 256);
+        *out = rv;
+        return HBMC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HBMC_ENOMEM, "out of host memory in hbmc_revalue_create");
+    }
+}
+
+extern "C" int hbmc_revalue_device_bytes(const hbmc_revalue_t *rv, size_t *bytes) {
+    if (!rv || !bytes) return fail(HBMC_EINVAL, "null argument");
+    *bytes = rv->scratch_end;
+    return HBMC_OK;
+}
+
+extern "C" void hbmc_revalue_destroy(hbmc_revalue_t *rv) { delete rv; }

@@ -196,6 +196,7 @@ struct hbmc_factor_s {
     int32_t nsys = 1;
     int64_t n_pad = 0;
     double smooth_scale = 1.0;         // c of the smoothing step x += c M^-1 r: 1 (IC(0)), 2 - omega (SSOR)
+    bool ssor = false;                 // the SSOR splitting rather than IC(0)
     std::vector<int64_t> color_start;
     std::vector<int64_t> sys_ptr;      // [nsys + 1] original rows of each system
     // systems: tile and 64-row group -> system; per system and color the
@@ -230,6 +231,22 @@ struct hbmc_factor_s {
         void *exec;
     };
     std::vector<Graph> graphs;
+};
+
+// Pattern data for recomputing a factor and a matrix from new values of
+// the same matrix on the device (ic0_refactor, hbmc_matrix_revalue).
+struct hbmc_revalue_s {
+    int32_t n = 0, bs = 0, w = 0, nc = 0;
+    int64_t n_pad = 0, nnz = 0;           // nnz: entries of the caller's CSR
+    std::vector<int64_t> color_start, tile_base;
+    std::vector<int64_t> arp, amap;       // Abar rows; source entry of each Abar entry (-1: dummy diagonal 1)
+    std::vector<int32_t> aci;
+    std::vector<int64_t> lrp;             // strictly lower pattern of Abar
+    std::vector<int32_t> lcol;
+    hbmc::ImageBuilder image;             // the arrays above; device scratch follows the image
+    size_t off_cs = 0, off_tb = 0, off_arp = 0, off_aci = 0, off_amap = 0, off_lrp = 0, off_lcol = 0;
+    size_t off_lval = 0, off_d = 0, off_flag = 0, scratch_end = 0;
+    void *dev = nullptr;
 };
 
 struct hbmc_matrix_s {

@@ -16,6 +16,9 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
 - smoother: symmetric Gauss-Seidel / SSOR and forward Gauss-Seidel steps
   on the HBMC substitution kernels (time per step, bytes per step), and
   SSOR-preconditioned CG against IC(0)-preconditioned CG;
+- refactor: new coefficients of the 128^3 problem (same pattern): the
+  factor and matrix rebuilt on the host and uploaded against recomputed on
+  the device (ic0_refactor, hbmc_matrix_revalue);
 - orderings: multi-color (bs = 1), block multi-color (w = 1: one block per
   lane, rows of a lane 1 apart) and hierarchical block multi-color ordering
   of the same problem, FP64: iterations, time and time per iteration (the
@@ -264,4 +267,36 @@ def smoother(device, N=128, bs=8, w=64, steps=20, tol=1e-7, log=print):
         res[name] = {"ms": round(t * 1e3, 3), **_stats(st)}
         log(f"[ext smoother] {name}: {st.iters} its, {t * 1e3:.2f} ms")
         del sv
+    return res
+
+
+def refactor(device, N=128, bs=8, w=64, reps=3, log=print):
+    """New values of the same pattern: host rebuild (ordering kept) against
+    the device refactorization; both give the same device images."""
+    import torch
+    A = inputs.diffusion3d(N, 1.0, 2)
+    B = inputs.diffusion3d(N, 1.0, 5)
+    o = hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ic0_factor(o, A).upload(device)
+    m = hbmc.hbmc_matrix_create(o, A).upload(device)
+    rv = hbmc.Revalue(o, A).upload(device)
+    vb = torch.from_numpy(B.val).to(device)
+    res = {"workload": f"diffusion3d {N}^3: coefficients of seed 2 replaced by those of seed 5 (same pattern), "
+                       f"HBMC bs={bs} w={w}, FP64"}
+
+    def host():
+        fh = hbmc.ic0_factor(o, B).upload(device)
+        mh = hbmc.hbmc_matrix_create(o, B).upload(device)
+        return fh, mh
+
+    def dev():
+        hbmc.ic0_refactor(f, rv, vb)
+        hbmc.hbmc_matrix_revalue(m, rv, vb)
+        return f, m
+    t_host, _ = _timed(host, reps)
+    t_dev, _ = _timed(dev, reps)
+    res["host_rebuild_ms"] = round(t_host * 1e3, 2)
+    res["device_refactor_ms"] = round(t_dev * 1e3, 3)
+    res["speedup"] = round(t_host / t_dev, 1)
+    log(f"[ext refactor] host rebuild {t_host * 1e3:.1f} ms, device refactor {t_dev * 1e3:.2f} ms")
     return res

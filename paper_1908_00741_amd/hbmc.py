@@ -32,6 +32,8 @@ SYMBOLS = (
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
     "ssor_factor", "hbmc_smooth_workspace_bytes", "hbmc_smooth",
     "hbmc_factor_image", "hbmc_matrix_image", "hbmc_set_num_threads",
+    "hbmc_revalue_create", "hbmc_revalue_device_bytes", "hbmc_revalue_upload", "hbmc_revalue_destroy",
+    "ic0_refactor", "hbmc_matrix_revalue",
 )
 
 
@@ -102,6 +104,13 @@ def lib():
         L.hbmc_factor_image.argtypes = [P, P, sz]
         L.hbmc_matrix_image.argtypes = [P, P, sz]
         L.hbmc_set_num_threads.argtypes = [i32]
+        L.hbmc_revalue_create.argtypes = [P, P, P, P]
+        L.hbmc_revalue_device_bytes.argtypes = [P, P]
+        L.hbmc_revalue_upload.argtypes = [P, P, sz, P]
+        L.hbmc_revalue_destroy.argtypes = [P]
+        L.hbmc_revalue_destroy.restype = None
+        L.ic0_refactor.argtypes = [P, P, P, f64, P]
+        L.hbmc_matrix_revalue.argtypes = [P, P, P, P]
         _lib = L
     return _lib
 
@@ -243,6 +252,58 @@ def ic0_factor(order: Order, A, precision: int = HBMC_F64, shift: float = 0.0) -
     _check("ic0_factor", lib().ic0_factor(order.handle, _ptr(rp), _ptr(ci), _ptr(v), precision,
                                           float(shift), C.byref(h)))
     return Factor(h, order, precision)
+
+
+class Revalue:
+    """Handle of hbmc_revalue_create: the pattern data with which
+    ic0_refactor and hbmc_matrix_revalue take new values of the same
+    matrix on the device."""
+
+    def __init__(self, order: Order, A):
+        rp, ci, _ = _csr_arrays(A)
+        h = C.c_void_p()
+        _check("hbmc_revalue_create", lib().hbmc_revalue_create(order.handle, _ptr(rp), _ptr(ci), C.byref(h)))
+        self._h = h
+        self.nnz = int(rp[-1])
+        self.dev = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        b = C.c_size_t(0)
+        _check("hbmc_revalue_device_bytes", lib().hbmc_revalue_device_bytes(self._h, C.byref(b)))
+        self.dev = torch.empty(max(b.value, 256), dtype=torch.uint8, device=device)
+        _check("hbmc_revalue_upload", lib().hbmc_revalue_upload(self._h, _dptr(self.dev), b.value,
+                                                                _stream(stream)))
+        return self
+
+    def __del__(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.hbmc_revalue_destroy(self._h)
+            self._h = None
+
+
+def _val_check(rv: Revalue, val):
+    import torch
+    if not (val.is_cuda and val.dtype == torch.float64 and val.is_contiguous() and val.numel() == rv.nnz):
+        raise ValueError(f"val must be a contiguous float64 device tensor of {rv.nnz} entries")
+
+
+def ic0_refactor(f: Factor, rv: Revalue, val, shift: float = 0.0, stream=None) -> Factor:
+    """IC(0) of new values (the caller's CSR order, same pattern) computed on
+    the device, written into f's device image."""
+    _val_check(rv, val)
+    _check("ic0_refactor", lib().ic0_refactor(f.handle, rv.handle, _dptr(val), float(shift), _stream(stream)))
+    return f
+
+
+def hbmc_matrix_revalue(m: Matrix, rv: Revalue, val, stream=None) -> Matrix:
+    _val_check(rv, val)
+    _check("hbmc_matrix_revalue", lib().hbmc_matrix_revalue(m.handle, rv.handle, _dptr(val), _stream(stream)))
+    return m
 
 
 def set_num_threads(threads: int = 0) -> None:

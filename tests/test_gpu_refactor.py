@@ -1,0 +1,131 @@
+"""Device refactorization (ic0_refactor, hbmc_matrix_revalue): new values of
+the same pattern, IC(0) recomputed on the GPU color by color.
+
+Bars: the device performs the host factorization's arithmetic term for term
+in the same order (IEEE division and products, no contraction possible in
+these expressions), so the rewritten device images equal, byte for byte,
+the images that ic0_factor and hbmc_matrix_create build on the host from
+the same values; solves with them agree bit for bit as well.
+"""
+import numpy as np
+import pytest
+
+from paper_1908_00741_amd import hbmc, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    assert t.cuda.is_available(), "GPU tests need a GPU"
+    return t
+
+
+def _image(torch, h, nbytes):
+    torch.cuda.synchronize()
+    return h.dev[:nbytes].cpu().numpy()
+
+
+def _revalued(A, seed):
+    """Same pattern, new symmetric values with a dominant positive diagonal."""
+    rng = np.random.default_rng(seed)
+    S = A.to_scipy().tocoo()
+    off = S.row != S.col
+    w = rng.uniform(0.5, 1.5, S.nnz)
+    # symmetric weights: take the weight of the (min, max) pair
+    key = np.minimum(S.row, S.col).astype(np.int64) * A.n + np.maximum(S.row, S.col)
+    uniq, inv = np.unique(key, return_inverse=True)
+    wsym = rng.uniform(0.5, 1.5, uniq.size)[inv]
+    vals = S.data * np.where(off, wsym, 1.0)
+    import scipy.sparse as sp
+    B = sp.csr_matrix((vals, (S.row, S.col)), shape=S.shape)
+    rowsum = np.asarray(abs(B).sum(axis=1)).ravel() - abs(B.diagonal())
+    B.setdiag(rowsum * rng.uniform(1.01, 1.3, A.n) + 1e-3)
+    B.sort_indices()
+    out = inputs.from_scipy(B)
+    assert np.array_equal(out.rowptr, A.rowptr) and np.array_equal(out.col, A.col)
+    return out
+
+
+CASES = [
+    ("c1_grid64_bs4_w8", lambda: inputs.grid2d_5pt(64), 4, 8),
+    ("diff3d_20_bs8_w64", lambda: inputs.diffusion3d(20, 1.0, 2), 8, 64),
+    ("knn_6000_bs8_w64", lambda: inputs.knn_laplacian(6000, 13, 4, 5), 8, 64),
+    ("knn_3000_bs4_w8", lambda: inputs.knn_laplacian(3000, 13, 6, 7), 4, 8),
+    ("random_bs1_w64_mc", lambda: inputs.random_spd(1500, 0.004, 7), 1, 64),
+    ("random_bs2_w32", lambda: inputs.random_spd(999, 0.006, 8), 2, 32),
+    ("random_bs32_w2", lambda: inputs.random_spd(1200, 0.004, 10), 32, 2),
+    ("random_w1_bmc", lambda: inputs.random_spd(700, 0.008, 11), 8, 1),
+    ("path_short", lambda: inputs.path_1d(5), 4, 8),
+]
+
+
+@pytest.mark.parametrize("precision", [hbmc.HBMC_F64, hbmc.HBMC_F32], ids=["f64", "f32"])
+@pytest.mark.parametrize("name,make,bs,w", CASES, ids=[c[0] for c in CASES])
+def test_refactor_matches_host_factor(torch, name, make, bs, w, precision):
+    print(f"case refactor {name} precision {precision}", flush=True)
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ic0_factor(o, A, precision).upload()
+    m = hbmc.hbmc_matrix_create(o, A).upload()
+    rv = hbmc.Revalue(o, A).upload()
+    # the same values: the images come back unchanged
+    hbmc.ic0_refactor(f, rv, torch.from_numpy(A.val).cuda())
+    assert np.array_equal(_image(torch, f, f.device_bytes()), f.image())
+    # new values and a shift: equal to the host build of the same values
+    B = _revalued(A, 3)
+    vb = torch.from_numpy(B.val).cuda()
+    hbmc.ic0_refactor(f, rv, vb, shift=0.05)
+    hbmc.hbmc_matrix_revalue(m, rv, vb)
+    fresh = hbmc.ic0_factor(o, B, precision, 0.05)
+    assert np.array_equal(_image(torch, f, f.device_bytes()), fresh.image())
+    assert np.array_equal(_image(torch, m, m.device_bytes()), hbmc.hbmc_matrix_create(o, B).image())
+
+
+def test_refactor_solve_128(torch):
+    """128^3: refactor for new coefficients, then a solve bit-identical to
+    the one with a freshly built factor and matrix."""
+    print("case refactor 128", flush=True)
+    A = inputs.diffusion3d(128, 1.0, 2)
+    B = inputs.diffusion3d(128, 1.0, 5)          # same pattern, other coefficients
+    assert np.array_equal(A.col, B.col)
+    o = hbmc.hbmc_order(A, 8, 64)
+    sv = hbmc.Solver(o, hbmc.ic0_factor(o, A).upload(), hbmc.hbmc_matrix_create(o, A).upload())
+    rv = hbmc.Revalue(o, A).upload()
+    vb = torch.from_numpy(B.val).cuda()
+    hbmc.ic0_refactor(sv.factor, rv, vb)
+    hbmc.hbmc_matrix_revalue(sv.matrix, rv, vb)
+    fresh = hbmc.Solver.setup(B, 8, 64)
+    b = torch.from_numpy(inputs.uniform_rhs(B.n, 3)).cuda()
+    x1, s1 = sv.solve(b, tol=1e-7)
+    x1 = x1.cpu().numpy()
+    x2, s2 = fresh.solve(b, tol=1e-7)
+    assert s1.iters == s2.iters and s1.status == hbmc.HBMC_OK
+    assert np.array_equal(x1, x2.cpu().numpy())
+
+
+def test_refactor_breakdown_and_errors(torch):
+    import scipy.sparse as sp
+    A = inputs.from_scipy(sp.csr_matrix(np.array([[3.0, 1.0], [1.0, 3.0]])))
+    o = hbmc.hbmc_order(A, 1, 1)
+    f = hbmc.ic0_factor(o, A).upload()
+    rv = hbmc.Revalue(o, A).upload()
+    bad = torch.tensor([1.0, 2.0, 2.0, 1.0], dtype=torch.float64, device="cuda")   # pivot 1 - 4 < 0
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ic0_refactor(f, rv, bad)
+    assert e.value.code == hbmc.HBMC_EBREAKDOWN
+    hbmc.ic0_refactor(f, rv, torch.from_numpy(A.val).cuda())        # usable again
+    assert np.array_equal(_image(torch, f, f.device_bytes()), f.image())
+    s = hbmc.ssor_factor(o, A).upload()
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ic0_refactor(s, rv, torch.from_numpy(A.val).cuda())
+    assert e.value.code == hbmc.HBMC_EINVAL
+    G = inputs.grid2d_5pt(6)
+    og = hbmc.hbmc_order(G, 4, 8)
+    fg = hbmc.ic0_factor(og, G).upload()
+    with pytest.raises(hbmc.HbmcError) as e:                          # another order
+        hbmc.ic0_refactor(fg, rv, torch.from_numpy(A.val).cuda())
+    assert e.value.code == hbmc.HBMC_EINVAL
+    with pytest.raises(ValueError):
+        hbmc.ic0_refactor(f, rv, torch.zeros(3, dtype=torch.float64, device="cuda"))

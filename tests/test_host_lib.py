@@ -116,6 +116,20 @@ def test_ssor_factor_matches_oracle(orc, name, make, bs, w, omega):
     assert np.array_equal(v, L.data) and np.array_equal(d, dref)
 
 
+def test_revalue_create():
+    """Pattern data for device refactorization: host-only construction and
+    its CSR checks."""
+    A = inputs.diffusion3d(10, 1.0, 2)
+    o = hbmc.hbmc_order(A, 8, 16)
+    rv = hbmc.Revalue(o, A)
+    assert rv.nnz == int(A.rowptr[-1])
+    col = A.col.copy()
+    col[[0, 1]] = col[[1, 0]]
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.Revalue(o, inputs.CSR(A.n, A.rowptr, col, A.val))
+    assert e.value.code == hbmc.HBMC_EINVAL
+
+
 def test_ssor_factor_errors():
     A = inputs.grid2d_5pt(6)
     o = hbmc.hbmc_order(A, 4, 8)
