@@ -7,7 +7,8 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
   by latency) and on the 128^3 diffusion problem (bound by bandwidth);
 - batch: 128 Poisson systems of uneven size (16^3 .. 64^3) solved together
   (one set of launches per iteration, per-system stopping tests, FP32
-  preconditioner) against solving them one by one in FP64;
+  preconditioner, autotuned bs, w and kernel) against solving them one by
+  one in FP64;
 - rhs: 32 right-hand sides of the 128^3 lognormal diffusion problem solved
   together (factor read once per apply for all of them, autotuned
   right-hand-side tile, FP32 preconditioner) against 32 FP64 solves;
@@ -107,8 +108,9 @@ def fp32_grid(device, N=128, bs=8, w=64, tol=1e-7, log=print):
     return res
 
 
-def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, log=print):
-    """Uneven batch in one set of launches against one-by-one FP64 solves."""
+def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, tune=True, log=print):
+    """Uneven batch in one set of launches (autotuned bs, w and kernel, FP32
+    preconditioner) against one-by-one FP64 solves (bs 8, w 64)."""
     import torch
     sizes = inputs.batch_sizes(count, seed, lo, hi)
     log(f"[ext batch] {count} Poisson systems, N in [{sizes.min()}, {sizes.max()}]")
@@ -116,15 +118,26 @@ def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, log=pri
     A, sys_ptr = inputs.block_diag(mats)
     rhs = [inputs.uniform_rhs(M.n, 1000 + s) for s, M in enumerate(mats)]
     res = {"workload": f"{count} 7-point Poisson systems, N ~ U{{{lo}..{hi}}} (seed {seed}), "
-                       f"n total {A.n}, b~U[-1,1], HBMC bs={bs} w={w}, tol {tol:g}"}
-    t0 = time.perf_counter()
-    sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F32, device=device, sys_ptr=sys_ptr)
-    res["setup_s"] = round(time.perf_counter() - t0, 2)
+                       f"n total {A.n}, b~U[-1,1], tol {tol:g}"}
     bb = torch.from_numpy(np.concatenate(rhs)).to(device)
+    kernel = hbmc.HBMC_KERNEL_AUTO
+    if tune:
+        choice = autotune.tune(A, bb, sys_ptr=sys_ptr, precision=hbmc.HBMC_F32, tol=tol, bs_list=(4, 8, 16),
+                               w_list=(32, 64), reps=1, device=device, log=log)
+        bs, w, kernel = choice.bs, choice.w, choice.kernel
+        res["autotune"] = {"bs": bs, "w": w, "kernel": kernel,
+                           "trials": [[t.bs, t.w, t.kernel, round(t.seconds * 1e3, 2), t.iters]
+                                      for t in choice.trials]}
+        del choice
+        torch.cuda.empty_cache()
+    t0 = time.perf_counter()
+    sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F32, device=device, sys_ptr=sys_ptr, kernel=kernel)
+    res["setup_s"] = round(time.perf_counter() - t0, 2)
     t, (x, st) = _timed(lambda: sv.solve(bb, tol=tol))
-    res["batched_f32"] = {"ms": round(t * 1e3, 3), **_stats(st)}
-    log(f"[ext batch] batched FP32: {t * 1e3:.2f} ms")
+    res["batched_f32"] = {"ms": round(t * 1e3, 3), "bs": bs, "w": w, "kernel": kernel, **_stats(st)}
+    log(f"[ext batch] batched FP32 (bs={bs} w={w} kernel={kernel}): {t * 1e3:.2f} ms")
     del sv
+    bs, w = 8, 64
     total, its, worst, conv = 0.0, [], 0.0, True
     for s, M in enumerate(mats):
         one = hbmc.Solver.setup(M, bs, w, hbmc.HBMC_F64, device=device)
