@@ -301,6 +301,10 @@ int hbmc_revalue_device_bytes(const hbmc_revalue_t *rv, size_t *bytes);
 int hbmc_revalue_upload(hbmc_revalue_t *rv, void *dev, size_t bytes, void *stream);
 void hbmc_revalue_destroy(hbmc_revalue_t *rv);
 int ic0_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double shift, void *stream);
+/* The same for a factor from ssor_factor (d = abar_ii / omega, L = the
+ * strictly lower part of Abar; no pivots to check); HBMC_EINVAL for an
+ * IC(0) factor or omega outside (0, 2).  Synchronous. */
+int ssor_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double omega, void *stream);
 int hbmc_matrix_revalue(hbmc_matrix_t *m, const hbmc_revalue_t *rv, const double *val, void *stream);
 
 /* ---- smoother ----------------------------------------------------------------

@@ -91,8 +91,10 @@ __device__ inline int64_t row_of(const Rv &R, int c, int64_t lam, int l) {
     return R.cs[c] + (lam / R.w) * l1 + int64_t(l) * R.w + lam % R.w;
 }
 
-// Lower values and (shifted) diagonals of Abar, from the caller's values.
-__global__ void k_rv_gather(Rv R, const double *__restrict__ val, double shift) {
+// Lower values and diagonals of Abar, from the caller's values: the
+// diagonal times (1 + shift) for IC(0), divided by omega for the SSOR
+// splitting (ssor != 0).
+__global__ void k_rv_gather(Rv R, const double *__restrict__ val, double shift, int ssor, double omega) {
     const int64_t r = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (r >= R.n_pad) return;
     int64_t q = R.lrp[r];
@@ -100,7 +102,7 @@ __global__ void k_rv_gather(Rv R, const double *__restrict__ val, double shift) 
         const int32_t c = R.aci[p];
         const double v = R.amap[p] >= 0 ? val[R.amap[p]] : 1.0;
         if (c < r) R.lval[q++] = v;
-        else if (c == r) R.d[r] = v * (1.0 + shift);
+        else if (c == r) R.d[r] = ssor ? v / omega : v * (1.0 + shift);
     }
 }
 
@@ -265,34 +267,55 @@ extern "C" int hbmc_revalue_upload(hbmc_revalue_t *rv, void *dev, size_t bytes, 
     return HBMC_OK;
 }
 
-extern "C" int ic0_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double shift,
-                            void *stream) {
+namespace {
+
+// The factor of either splitting from new values, then its device values.
+int refactor(hbmc_factor_s *f, const hbmc_revalue_s *rv, const double *val, bool ssor, double param,
+             void *stream) {
     clear_error();
     if (!f || !rv || !val) return fail(HBMC_EINVAL, "null argument");
     if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
     if (!rv->dev) return fail(HBMC_ENOTREADY, "revalue data not uploaded");
-    if (f->ssor) return fail(HBMC_EINVAL, "ic0_refactor needs an IC(0) factor");
-    if (!(shift >= 0.0)) return fail(HBMC_EINVAL, "shift must be >= 0");
+    if (f->ssor != ssor)
+        return fail(HBMC_EINVAL, ssor ? "ssor_refactor needs an SSOR factor" : "ic0_refactor needs an IC(0) factor");
+    if (!ssor && !(param >= 0.0)) return fail(HBMC_EINVAL, "shift must be >= 0");
+    if (ssor && !(param > 0.0 && param < 2.0)) return fail(HBMC_EINVAL, "omega must lie in (0, 2) (got %g)", param);
     if (!same_order(rv, f->n_pad, f->n, f->bs, f->w, f->nc, f->color_start) || rv->lcol.size() != f->lcol.size())
         return fail(HBMC_EINVAL, "revalue data of another order or pattern");
     auto s = static_cast<hipStream_t>(stream);
     const Rv R = rv_of(rv);
-    HIP_TRY(hipMemsetAsync(R.flag, 0, sizeof(int32_t), s));
-    hipLaunchKernelGGL(k_rv_gather, dim3(unsigned((rv->n_pad + 255) / 256)), dim3(256), 0, s, R, val, shift);
-    for (int c = 0; c < rv->nc; ++c) {
-        const int64_t lanes = (rv->color_start[c + 1] - rv->color_start[c]) / rv->bs;
-        if (lanes > 0)
-            hipLaunchKernelGGL(k_rv_ic0, dim3(unsigned((lanes + 127) / 128)), dim3(128), 0, s, R, c);
-    }
+    hipLaunchKernelGGL(k_rv_gather, dim3(unsigned((rv->n_pad + 255) / 256)), dim3(256), 0, s, R, val,
+                       ssor ? 0.0 : param, ssor ? 1 : 0, ssor ? param : 1.0);
     HIP_TRY(hipGetLastError());
-    int32_t bad = 0;
-    HIP_TRY(hipMemcpyAsync(&bad, R.flag, sizeof bad, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (bad) return fail(HBMC_EBREAKDOWN, "IC(0) pivot not > 0 on the device");
+    if (!ssor) {
+        HIP_TRY(hipMemsetAsync(R.flag, 0, sizeof(int32_t), s));
+        for (int c = 0; c < rv->nc; ++c) {
+            const int64_t lanes = (rv->color_start[c + 1] - rv->color_start[c]) / rv->bs;
+            if (lanes > 0)
+                hipLaunchKernelGGL(k_rv_ic0, dim3(unsigned((lanes + 127) / 128)), dim3(128), 0, s, R, c);
+        }
+        HIP_TRY(hipGetLastError());
+        int32_t bad = 0;
+        HIP_TRY(hipMemcpyAsync(&bad, R.flag, sizeof bad, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        if (bad) return fail(HBMC_EBREAKDOWN, "IC(0) pivot not > 0 on the device");
+    }
     const int st = f->precision == HBMC_F64 ? pack_factor<double>(f, R, s) : pack_factor<float>(f, R, s);
     if (st) return st;
     HIP_TRY(hipStreamSynchronize(s));
     return HBMC_OK;
+}
+
+}  // namespace
+
+extern "C" int ic0_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double shift,
+                            void *stream) {
+    return refactor(f, rv, val, false, shift, stream);
+}
+
+extern "C" int ssor_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double omega,
+                             void *stream) {
+    return refactor(f, rv, val, true, omega, stream);
 }
 
 extern "C" int hbmc_matrix_revalue(hbmc_matrix_t *m, const hbmc_revalue_t *rv, const double *val, void *stream) {

@@ -33,7 +33,7 @@ SYMBOLS = (
     "ssor_factor", "hbmc_smooth_workspace_bytes", "hbmc_smooth",
     "hbmc_factor_image", "hbmc_matrix_image", "hbmc_set_num_threads",
     "hbmc_revalue_create", "hbmc_revalue_device_bytes", "hbmc_revalue_upload", "hbmc_revalue_destroy",
-    "ic0_refactor", "hbmc_matrix_revalue",
+    "ic0_refactor", "ssor_refactor", "hbmc_matrix_revalue",
 )
 
 
@@ -110,6 +110,7 @@ def lib():
         L.hbmc_revalue_destroy.argtypes = [P]
         L.hbmc_revalue_destroy.restype = None
         L.ic0_refactor.argtypes = [P, P, P, f64, P]
+        L.ssor_refactor.argtypes = [P, P, P, f64, P]
         L.hbmc_matrix_revalue.argtypes = [P, P, P, P]
         _lib = L
     return _lib
@@ -297,6 +298,13 @@ def ic0_refactor(f: Factor, rv: Revalue, val, shift: float = 0.0, stream=None) -
     the device, written into f's device image."""
     _val_check(rv, val)
     _check("ic0_refactor", lib().ic0_refactor(f.handle, rv.handle, _dptr(val), float(shift), _stream(stream)))
+    return f
+
+
+def ssor_refactor(f: Factor, rv: Revalue, val, omega: float = 1.0, stream=None) -> Factor:
+    """The SSOR splitting of new values (same pattern), on the device."""
+    _val_check(rv, val)
+    _check("ssor_refactor", lib().ssor_refactor(f.handle, rv.handle, _dptr(val), float(omega), _stream(stream)))
     return f
 
 

@@ -83,6 +83,20 @@ def test_refactor_matches_host_factor(torch, name, make, bs, w, precision):
     assert np.array_equal(_image(torch, m, m.device_bytes()), hbmc.hbmc_matrix_create(o, B).image())
 
 
+@pytest.mark.parametrize("name,make,bs,w", CASES[:4], ids=[c[0] for c in CASES[:4]])
+def test_ssor_refactor_matches_host(torch, name, make, bs, w):
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ssor_factor(o, A, hbmc.HBMC_F64, 1.3).upload()
+    rv = hbmc.Revalue(o, A).upload()
+    B = _revalued(A, 4)
+    hbmc.ssor_refactor(f, rv, torch.from_numpy(B.val).cuda(), omega=1.1)
+    assert np.array_equal(_image(torch, f, f.device_bytes()), hbmc.ssor_factor(o, B, hbmc.HBMC_F64, 1.1).image())
+    with pytest.raises(hbmc.HbmcError) as e:
+        hbmc.ssor_refactor(f, rv, torch.from_numpy(B.val).cuda(), omega=2.0)
+    assert e.value.code == hbmc.HBMC_EINVAL
+
+
 def test_refactor_solve_128(torch):
     """128^3: refactor for new coefficients, then a solve bit-identical to
     the one with a freshly built factor and matrix."""
