@@ -1,5 +1,7 @@
 """Pins of the oracle's IC(0), preconditioner and PCG.
 
+- IC(0) against a brute-force dense elimination with every update outside
+  A's pattern discarded (n <= 400);
 - IC(0) is pinned by its defining property: M = (D+L) D^-1 (D+L^T) agrees
   with A on A's pattern (no-fill incomplete factorization, Section 2 eq.
   "ILU"); where the ordering creates no fill M = A, so (D+L) D^-1/2 is the
@@ -57,6 +59,29 @@ def test_ic0_matches_A_on_pattern(orc, name, make, bs, w):
     scale = np.abs(Ab.data).max()
     assert np.abs(R.data).max() <= 1e-13 * scale if R.nnz else True
     assert np.all(s.d > 0)
+
+
+@pytest.mark.parametrize("name,make,bs,w", CASES, ids=[c[0] for c in CASES])
+def test_ic0_matches_dense_masked_elimination(orc, name, make, bs, w):
+    """Brute force: Gaussian elimination of the dense reordered matrix in
+    index order, every update that falls outside A's pattern discarded
+    (zero-fill incomplete LDL^T); its pivots and multipliers L_ij = l_ij d_j
+    equal the oracle's d and L."""
+    s = orc.system(make(), bs, w)
+    Ad = _Abar(s).toarray()
+    keep = Ad != 0.0
+    a = Ad.copy()
+    n = a.shape[0]
+    for k in range(n):
+        piv = a[k, k]
+        col = a[k + 1:, k].copy()
+        upd = np.outer(col, col) / piv
+        blk = a[k + 1:, k + 1:]
+        blk -= np.where(keep[k + 1:, k + 1:], upd, 0.0)
+    L, D = _lower_upper(s)
+    assert np.allclose(np.diag(a), s.d, rtol=1e-13, atol=0)
+    Ld = np.tril(a, -1)
+    assert np.allclose(L.toarray(), Ld, rtol=0, atol=1e-13 * np.abs(Ad).max())
 
 
 def test_ic0_has_fill_outside_pattern(orc):
