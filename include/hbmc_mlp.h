@@ -39,7 +39,9 @@ extern "C" {
 /* C = A B in FP32, C [M][N] with row stride ldc.  nsplit > 1 splits K into
  * nsplit ranges and writes nsplit partial products to C + z * M * ldc
  * (z = 0 .. nsplit-1; C must hold nsplit * M * ldc floats); mlp_sum_rows
- * adds them in a fixed order. */
+ * adds them in a fixed order.  HBMC_EINVAL for an unknown layout or a
+ * leading dimension below its row width (lda, ldb as listed with the
+ * layouts; ldc >= N), before anything is launched. */
 int mlp_gemm(int32_t dtype, int32_t layout, int32_t M, int32_t N, int32_t K, const void *A, int64_t lda,
              const void *B, int64_t ldb, float *C, int64_t ldc, int32_t nsplit, void *stream);
 

@@ -72,6 +72,17 @@ struct Epi {
     float *loss_part, *dbias_part;
 };
 
+// Column of k in LDS row `row`.  BF16 rows hold four 16-byte chunks of 8 k;
+// chunk c sits at c ^ ((row / 16) % 4).  Staging an m- or n-contiguous
+// operand writes, in one instruction, one k of rows 8 apart (rows 8 j + i,
+// j = 0..7), which the 80-byte row pitch alone puts on two bank groups;
+// the XOR spreads them over the 64 banks.  Sixteen consecutive rows share
+// one permutation, so the MFMA's 16-byte reads of 16 consecutive rows stay
+// as they were.  FP32 rows are not permuted.
+template <typename T> __device__ inline int swz(int row, int k);
+template <> __device__ inline int swz<uint16_t>(int row, int k) { return ((((k >> 3) ^ (row >> 4)) & 3) << 3) | (k & 7); }
+template <> __device__ inline int swz<float>(int, int k) { return k; }
+
 // The MFMA step for one K slice of KT held in LDS: acc += A[32 rows of the
 // wavefront][KT] * B[KT][32 columns of the wavefront].  A fragment is 8
 // consecutive k of one row (BF16) or 1 (FP32); the instruction pairs the
@@ -83,8 +94,8 @@ __device__ inline void mma_slice<uint16_t>(f32x16 &acc, const uint16_t (*sA)[LDK
                                            int ra, int cb, int l) {
 #pragma unroll
     for (int kk = 0; kk < KT; kk += 16) {
-        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sA[ra][kk + 8 * (l >> 5)]);
-        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sB[cb][kk + 8 * (l >> 5)]);
+        const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sA[ra][swz<uint16_t>(ra, kk + 8 * (l >> 5))]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sB[cb][swz<uint16_t>(cb, kk + 8 * (l >> 5))]);
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
 }
@@ -97,20 +108,103 @@ __device__ inline void mma_slice<float>(f32x16 &acc, const float (*sA)[LDK], con
     }
 }
 
+// One K slice of a BF16 tile pair staged with 16-byte loads, one per thread
+// and operand (BM x KT and BN x KT values are 256 x 8): the caller
+// guarantees whole tiles (M, N multiples of 64, the slice inside K) and
+// 16-byte aligned rows.  vec_load fetches a slice into registers (issued a
+// slice ahead, so that the loads overlap the MFMA work); vec_store puts it
+// into LDS: k-contiguous rows as they are, m- or n-contiguous rows
+// transposed on the way.
+template <int LAYOUT>
+__device__ inline uint4 vec_load_a(const uint16_t *__restrict__ A, int64_t lda, int m0, int k0, int tid) {
+    if (LAYOUT == MLP_TN)   // A stored [K][M]: a row holds 64 m
+        return *reinterpret_cast<const uint4 *>(A + int64_t(k0 + (tid >> 3)) * lda + m0 + (tid & 7) * 8);
+    // A stored [M][K]: a row holds the slice's 32 k
+    return *reinterpret_cast<const uint4 *>(A + int64_t(m0 + (tid >> 2)) * lda + k0 + (tid & 3) * 8);
+}
+
+template <int LAYOUT>
+__device__ inline uint4 vec_load_b(const uint16_t *__restrict__ B, int64_t ldb, int n0, int k0, int tid) {
+    if (LAYOUT == MLP_NT)   // B stored [N][K]
+        return *reinterpret_cast<const uint4 *>(B + int64_t(n0 + (tid >> 2)) * ldb + k0 + (tid & 3) * 8);
+    // B stored [K][N]: a row holds 64 n
+    return *reinterpret_cast<const uint4 *>(B + int64_t(k0 + (tid >> 3)) * ldb + n0 + (tid & 7) * 8);
+}
+
+// Value i (0..7) of the eight BF16 values held in v, taken with shifts so
+// that v stays in registers.
+__device__ inline uint16_t half_of(uint4 v, int i) {
+    const uint32_t w = i < 2 ? v.x : i < 4 ? v.y : i < 6 ? v.z : v.w;
+    return uint16_t(w >> (16 * (i & 1)));
+}
+
+template <bool TRANSPOSED>
+__device__ inline void vec_store(uint4 v, uint16_t (*s)[LDK], int tid) {
+    if (TRANSPOSED) {
+        const int k = tid >> 3, r8 = (tid & 7) * 8;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) s[r8 + i][swz<uint16_t>(r8 + i, k)] = half_of(v, i);
+    } else {
+        const int r = tid >> 2;
+        *reinterpret_cast<uint4 *>(&s[r][swz<uint16_t>(r, (tid & 3) * 8)]) = v;
+    }
+}
+
+// Output tile (mt, nt) and K range z of a workgroup in a one-dimensional
+// grid of Mt * Nt * nsplit.  Workgroups go to the eight XCDs in turn (g % 8),
+// each with its own L2; the remap hands XCD x a contiguous range of tile
+// numbers t, which run m fastest, then n, then z, so the row tiles that
+// share a column block of B (and, under a K split, all tiles of one z) run
+// side by side on one XCD and read that block from HBM once.
+__device__ inline void tile_of(int Mt, int Nt, int &mt, int &nt, int &z) {
+    const int64_t G = gridDim.x, g = blockIdx.x;
+    const int64_t per = G / 8, rem = G % 8, x = g % 8;
+    const int64_t t = x * per + (x < rem ? x : rem) + g / 8;
+    mt = int(t % Mt);
+    nt = int((t / Mt) % Nt);
+    z = int(t / (int64_t(Mt) * Nt));
+}
+
 // C = A B for logical A [M][K] and B [K][N].  LAYOUT: MLP_NN (A stored
 // [M][K], B stored [K][N]), MLP_TN (A stored [K][M]), MLP_NT (B stored
-// [N][K]).  blockIdx.z: K split (k in [z * kchunk, (z + 1) * kchunk)).
-template <typename T, int LAYOUT, int EPI>
+// [N][K]).  z: K split (k in [z * kchunk, (z + 1) * kchunk)).
+// VEC: BF16 whole tiles with aligned rows, staged with 16-byte loads.
+template <typename T, int LAYOUT, int EPI, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T *__restrict__ A, int64_t lda,
                                                    const T *__restrict__ B, int64_t ldb, int kchunk, Epi ep) {
     __shared__ __align__(16) T sA[BM][LDK];
     __shared__ __align__(16) T sB[BN][LDK];
     const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
-    const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-    const int kbeg = blockIdx.z * kchunk, kend = min(K, kbeg + kchunk);
+    const int Mt = (M + BM - 1) / BM, Nt = (N + BN - 1) / BN;
+    int mt, nt, z;
+    tile_of(Mt, Nt, mt, nt, z);
+    const int m0 = mt * BM, n0 = nt * BN;
+    const int kbeg = z * kchunk, kend = min(K, kbeg + kchunk);
     f32x16 acc = {};
-    for (int k0 = kbeg; k0 < kend; k0 += KT) {
+    if constexpr (VEC) {
+        const auto *A16 = reinterpret_cast<const uint16_t *>(A);
+        const auto *B16 = reinterpret_cast<const uint16_t *>(B);
+        auto *sA16 = reinterpret_cast<uint16_t (*)[LDK]>(sA);
+        auto *sB16 = reinterpret_cast<uint16_t (*)[LDK]>(sB);
+        uint4 ra = {}, rb = {};
+        if (kbeg < kend) {
+            ra = vec_load_a<LAYOUT>(A16, lda, m0, kbeg, tid);
+            rb = vec_load_b<LAYOUT>(B16, ldb, n0, kbeg, tid);
+        }
+        for (int k0 = kbeg; k0 < kend; k0 += KT) {
+            vec_store<LAYOUT == MLP_TN>(ra, sA16, tid);
+            vec_store<LAYOUT != MLP_NT>(rb, sB16, tid);
+            __syncthreads();
+            if (k0 + KT < kend) {
+                ra = vec_load_a<LAYOUT>(A16, lda, m0, k0 + KT, tid);
+                rb = vec_load_b<LAYOUT>(B16, ldb, n0, k0 + KT, tid);
+            }
+            mma_slice<T>(acc, sA, sB, wm * 32 + (l & 31), wn * 32 + (l & 31), l);
+            __syncthreads();
+        }
+    }
+    for (int k0 = kbeg; !VEC && k0 < kend; k0 += KT) {
 #pragma unroll
         for (int e = 0; e < BM * KT / kThreads; ++e) {
             const int idx = tid + kThreads * e;
@@ -121,7 +215,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
             float v = 0.0f;
             if (gm < M && gk < kend)
                 v = LAYOUT == MLP_TN ? ld(A, int64_t(gk) * lda + gm) : ld(A, int64_t(gm) * lda + gk);
-            sA[m][k] = cvt<T>(v);
+            sA[m][swz<T>(m, k)] = cvt<T>(v);
         }
 #pragma unroll
         for (int e = 0; e < BN * KT / kThreads; ++e) {
@@ -133,7 +227,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
             float v = 0.0f;
             if (gn < N && gk < kend)
                 v = LAYOUT == MLP_NT ? ld(B, int64_t(gn) * ldb + gk) : ld(B, int64_t(gk) * ldb + gn);
-            sB[n][k] = cvt<T>(v);
+            sB[n][swz<T>(n, k)] = cvt<T>(v);
         }
         __syncthreads();
         mma_slice<T>(acc, sA, sB, wm * 32 + (l & 31), wn * 32 + (l & 31), l);
@@ -146,7 +240,7 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
             const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
-            if (i < M && j < N) ep.C[blockIdx.z * ep.zstride + int64_t(i) * ep.ldc + j] = acc[r];
+            if (i < M && j < N) ep.C[z * ep.zstride + int64_t(i) * ep.ldc + j] = acc[r];
         }
     } else if (EPI == EPI_BIAS_ACT) {
         const float bj = ep.bias && j < N ? ep.bias[j] : 0.0f;
@@ -183,9 +277,9 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
         for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
         if (l == 0) sLoss[wave] = loss;
         __syncthreads();
-        if (tid < BN && n0 + tid < N) ep.dbias_part[int64_t(blockIdx.y) * N + n0 + tid] = sCol[0][tid] + sCol[1][tid];
+        if (tid < BN && n0 + tid < N) ep.dbias_part[int64_t(mt) * N + n0 + tid] = sCol[0][tid] + sCol[1][tid];
         if (tid == 0)
-            ep.loss_part[int64_t(blockIdx.y) * gridDim.x + blockIdx.x] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
+            ep.loss_part[int64_t(mt) * Nt + nt] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
     }
 }
 
@@ -373,19 +467,39 @@ __global__ void k_combine(int M, int64_t n, const T *__restrict__ G, const int32
 
 inline unsigned blocks_for(int64_t n, int t = 256) { return unsigned((n + t - 1) / t); }
 
+template <typename T, int EPI, bool VEC>
+int launch_layout(int layout, dim3 grid, hipStream_t s, int M, int N, int K, const T *a, int64_t lda,
+                  const T *b, int64_t ldb, int kchunk, const Epi &ep) {
+    switch (layout) {
+        case MLP_NN: hipLaunchKernelGGL((k_gemm<T, MLP_NN, EPI, VEC>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        case MLP_TN: hipLaunchKernelGGL((k_gemm<T, MLP_TN, EPI, VEC>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        case MLP_NT: hipLaunchKernelGGL((k_gemm<T, MLP_NT, EPI, VEC>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
+        default: return fail(HBMC_EINVAL, "unknown layout %d", layout);
+    }
+    return HBMC_OK;
+}
+
 template <typename T, int EPI>
 int launch_gemm(int layout, int M, int N, int K, const void *A, int64_t lda, const void *B, int64_t ldb,
                 int nsplit, const Epi &ep, hipStream_t s) {
     const int kchunk = ((K + nsplit - 1) / nsplit + KT - 1) / KT * KT;
-    const dim3 grid(unsigned((N + BN - 1) / BN), unsigned((M + BM - 1) / BM), unsigned(nsplit));
+    const dim3 grid(unsigned(int64_t((N + BN - 1) / BN) * ((M + BM - 1) / BM) * nsplit));
     const T *a = static_cast<const T *>(A);
     const T *b = static_cast<const T *>(B);
-    switch (layout) {
-        case MLP_NN: hipLaunchKernelGGL((k_gemm<T, MLP_NN, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
-        case MLP_TN: hipLaunchKernelGGL((k_gemm<T, MLP_TN, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
-        case MLP_NT: hipLaunchKernelGGL((k_gemm<T, MLP_NT, EPI>), grid, dim3(kThreads), 0, s, M, N, K, a, lda, b, ldb, kchunk, ep); break;
-        default: return fail(HBMC_EINVAL, "unknown layout %d", layout);
-    }
+    // the 16-byte staging: BF16, whole tiles, every K slice whole, rows and
+    // bases 16-byte aligned
+    bool vec = false;
+    if constexpr (sizeof(T) == 2)
+        vec = M % BM == 0 && N % BN == 0 && K % KT == 0 && lda % 8 == 0 &&
+                     ldb % 8 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
+                     reinterpret_cast<uintptr_t>(B) % 16 == 0;
+    int st;
+    if constexpr (sizeof(T) == 2)
+        st = vec ? launch_layout<T, EPI, true>(layout, grid, s, M, N, K, a, lda, b, ldb, kchunk, ep)
+                 : launch_layout<T, EPI, false>(layout, grid, s, M, N, K, a, lda, b, ldb, kchunk, ep);
+    else
+        st = launch_layout<T, EPI, false>(layout, grid, s, M, N, K, a, lda, b, ldb, kchunk, ep);
+    if (st) return st;
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -401,7 +515,9 @@ int gemm_dtype(int dtype, int layout, int M, int N, int K, const void *A, int64_
 int check_dims(int M, int N, int K, int nsplit) {
     if (M < 1 || N < 1 || K < 1) return fail(HBMC_EINVAL, "bad sizes M=%d N=%d K=%d", M, N, K);
     if (nsplit < 1 || nsplit > 65535) return fail(HBMC_EINVAL, "bad split %d", nsplit);
-    if ((N + BN - 1) / BN > INT32_MAX || (M + BM - 1) / BM > 65535) return fail(HBMC_EINVAL, "grid too large");
+    // one-dimensional grid: fewer than 2^32 threads
+    if (int64_t((N + BN - 1) / BN) * ((M + BM - 1) / BM) * nsplit * kThreads > int64_t(UINT32_MAX))
+        return fail(HBMC_EINVAL, "grid too large");
     return HBMC_OK;
 }
 
@@ -413,6 +529,11 @@ extern "C" int mlp_gemm(int32_t dtype, int32_t layout, int32_t M, int32_t N, int
     if (!A || !B || !C) return fail(HBMC_EINVAL, "null argument");
     int st = check_dims(M, N, K, nsplit);
     if (st) return st;
+    if (layout < MLP_NN || layout > MLP_NT) return fail(HBMC_EINVAL, "unknown layout %d", layout);
+    const int64_t wa = layout == MLP_TN ? M : K, wb = layout == MLP_NT ? K : N;
+    if (lda < wa || ldb < wb || ldc < N)
+        return fail(HBMC_EINVAL, "leading dimension below the row width (lda %lld of %lld, ldb %lld of %lld, ldc %lld of %d)",
+                    (long long)lda, (long long)wa, (long long)ldb, (long long)wb, (long long)ldc, N);
     Epi ep{};
     ep.C = C;
     ep.ldc = ldc;
@@ -593,7 +714,11 @@ size_t net_layout(int dtype, int M, int n_in, int hid, int n_out, NetWork *w, vo
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t nloss = int64_t((M + BM - 1) / BM) * ((n_out + BN - 1) / BN);
     const int64_t nrows = (M + BM - 1) / BM;
-    const int split = std::max(1, std::min(1024, n_out / 1024));
+    // K split of dY W3^T (K = n_out) into about 1024 workgroups over the
+    // output tiles, K ranges of at least 4096: more splits only add
+    // partial products to write and add up
+    const int tiles = ((M + BM - 1) / BM) * ((hid + BN - 1) / BN);
+    const int split = std::max(1, std::min((1024 + tiles - 1) / tiles, n_out / 4096));
     const size_t es = elem_size(dtype);
     const size_t sz[9] = {up(size_t(M) * hid * es), up(size_t(M) * hid * es), up(size_t(M) * n_out * es),
                           up(size_t(M) * hid * es), up(size_t(nloss) * 4), up(size_t(nrows) * n_out * 4),

@@ -47,14 +47,23 @@ def _to_dtype(torch, a, dtype):
 
 @pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
 @pytest.mark.parametrize("layout", [mlp.MLP_NN, mlp.MLP_TN, mlp.MLP_NT], ids=["NN", "TN", "NT"])
-@pytest.mark.parametrize("M,N,K,split", [(70, 130, 45, 1), (64, 64, 32, 1), (5, 300, 1000, 3), (128, 33, 12, 1)])
-def test_gemm(torch, dtype, layout, M, N, K, split):
-    print(f"gemm dtype {dtype} layout {layout} {M}x{N}x{K} split {split}", flush=True)
+@pytest.mark.parametrize("M,N,K,split,pad", [(70, 130, 45, 1, 0), (64, 64, 32, 1, 0), (5, 300, 1000, 3, 0),
+                                             (128, 33, 12, 1, 0), (128, 192, 256, 3, 0), (192, 128, 96, 1, 8),
+                                             (128, 64, 64, 1, 3)])
+def test_gemm(torch, dtype, layout, M, N, K, split, pad):
+    """Whole 64 x 64 tiles with K a multiple of 32 and rows 16-byte aligned
+    take the BF16 kernel's 16-byte staging (with a split over K, and with
+    rows padded by pad elements); a pad of 3 breaks the alignment and takes
+    the element-wise staging on the same shape."""
+    print(f"gemm dtype {dtype} layout {layout} {M}x{N}x{K} split {split} pad {pad}", flush=True)
     rng = np.random.default_rng(M + N + K)
     A = _bf16_exact(rng, (M, K))
     B = _bf16_exact(rng, (K, N))
     As = A.T.copy() if layout == mlp.MLP_TN else A
     Bs = B.T.copy() if layout == mlp.MLP_NT else B
+    if pad:
+        As = np.pad(As, ((0, 0), (0, pad)), constant_values=1e30)
+        Bs = np.pad(Bs, ((0, 0), (0, pad)), constant_values=1e30)
     lda = As.shape[1]
     ldb = Bs.shape[1]
     Cd = torch.zeros((split, M, N), dtype=torch.float32, device="cuda")
@@ -97,12 +106,15 @@ def _net(rng, dims):
     return ps
 
 
+@pytest.mark.parametrize("M,n", [(40, 777), (128, 768)], ids=["ragged", "whole_tiles"])
 @pytest.mark.parametrize("dtype,tol", [(mlp.MLP_F32, 1e-5), (mlp.MLP_BF16, 1e-2)], ids=["f32", "bf16"])
-def test_gradients_against_oracle(torch, dtype, tol):
+def test_gradients_against_oracle(torch, dtype, tol, M, n):
+    """Ragged: every product takes the element-wise staging; whole tiles
+    (batch and widths multiples of 64): the hidden and output layers and
+    their backward products take the BF16 16-byte staging."""
     from oracle import mlp as omlp
-    print(f"mlp gradient check dtype {dtype}", flush=True)
+    print(f"mlp gradient check dtype {dtype} batch {M} outputs {n}", flush=True)
     rng = np.random.default_rng(11)
-    M, n = 40, 777
     ps = _net(rng, [12, 256, 256, n])
     theta = rng.uniform(-1, 1, (M, 12)).astype(np.float32)
     target = rng.uniform(-1, 1, (M, n)).astype(np.float32)

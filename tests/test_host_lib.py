@@ -29,6 +29,22 @@ def test_exports_every_declared_mlp_symbol():
         assert hasattr(L, name), name
 
 
+def test_mlp_gemm_rejects_short_leading_dimensions():
+    """Argument errors come back before any launch: host buffers stand in
+    for the operands and are never read."""
+    import ctypes as C
+    from paper_1908_00741_amd import mlp
+    L = mlp.lib()
+    buf = (C.c_float * 64)()
+    p = C.cast(buf, C.c_void_p)
+    M, N, K = 8, 16, 4
+    # (layout, lda, ldb, ldc): each one short of its row width by one
+    for layout, lda, ldb, ldc in [(mlp.MLP_NN, K - 1, N, N), (mlp.MLP_NN, K, N - 1, N), (mlp.MLP_NN, K, N, N - 1),
+                                  (mlp.MLP_TN, M - 1, N, N), (mlp.MLP_NT, K, K - 1, N), (7, K, N, N)]:
+        code = L.mlp_gemm(mlp.MLP_BF16, layout, M, N, K, p, lda, p, ldb, p, ldc, 1, None)
+        assert code == hbmc.HBMC_EINVAL, (layout, lda, ldb, ldc)
+
+
 def test_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "hbmc.h")).read()
     header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
