@@ -242,7 +242,7 @@ def main(argv=None) -> int:
     ap.add_argument("--mode", choices=("combined", "direct"), default="combined",
                     help="combined: single-source solutions combined into targets on the fly; "
                          "direct: one solution per sampled theta")
-    ap.add_argument("--steps", type=int, default=36000, help="Adam steps (combined)")
+    ap.add_argument("--steps", type=int, default=100000, help="Adam steps (combined)")
     ap.add_argument("--epochs", type=int, default=100, help="epochs (direct)")
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
