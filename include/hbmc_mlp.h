@@ -2,7 +2,7 @@
  * 256 -> 256 -> n with ReLU after the hidden layers, trained with a mean
  * squared error on solutions that iccg_solve produced (scaled by 1/s) and
  * Adam.  Not part of the paper's method: a start vector for CG, whose
- * result is still judged by the solver's own residual test.
+ * result still has to pass the solver's own residual test.
  *
  * Conventions.  All matrices are row-major, all pointers are device memory
  * unless stated, and every call is asynchronous on stream (a hipStream_t,
@@ -114,6 +114,23 @@ int mlp_backward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t
 int mlp_adam_step(int32_t dtype, int32_t count, const int64_t *sizes, float *const *w, float *const *m,
                   float *const *v, const float *const *g, void *const *wc, float lr, float beta1, float beta2,
                   float eps, int32_t step, void *stream);
+
+/* One training step: mlp_backward followed by mlp_adam_step on the six
+ * parameters (W1, b1, W2, b2, W3, b3), with equal results bit for bit,
+ * except that the gradient of W3 is never stored (grad[4] is left as it
+ * was): the product h2^T dY applies Adam to W3 as it forms each gradient
+ * value, which saves writing and re-reading one FP32 value per weight of the
+ * output layer.  w, m, v, grad: host arrays of six device pointers (FP32
+ * master weights, Adam moments, gradients); wc: host array of six device
+ * pointers to the compute-type copies, of which the weights' (wc[0], wc[2],
+ * wc[4]) feed the products and are rewritten by the update (the biases'
+ * may be NULL); the biases that the products add are w[1], w[3], w[5].
+ * step >= 1 sets the bias corrections.  *loss as for mlp_backward, from
+ * the weights before the update. */
+int mlp_train_step(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                   const void *T, float *const *w, float *const *m, float *const *v, float *const *grad,
+                   void *const *wc, float lr, float beta1, float beta2, float eps, int32_t step, float *loss,
+                   void *work, size_t work_bytes, void *stream);
 
 /* Right-hand side of the warm-start workload: b (FP64 [N^3], index
  * x + N y + N^2 z) = sum over q < 4 of a_q exp(-|p - c_q|^2 / (2 w_q^2)) at

@@ -4,7 +4,7 @@ Three knobs, searched one after the other, each keeping the best value of
 the ones before:
 
 1. the BMC block size bs -- it changes the preconditioner (larger blocks
-   usually mean fewer iterations and longer chains), so it is judged by the
+   usually mean fewer iterations and longer chains), so it is scored by the
    time of a whole solve to the tolerance;
 2. the level-1 width w -- the iteration count does not depend on it (the
    HBMC ordering is equivalent to the BMC ordering of the same blocks,

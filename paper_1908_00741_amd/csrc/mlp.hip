@@ -49,10 +49,10 @@ template <typename T> __device__ inline T cvt(float v);
 template <> __device__ inline uint16_t cvt<uint16_t>(float v) { return f2bf(v); }
 template <> __device__ inline float cvt<float>(float v) { return v; }
 
-constexpr int BM = 64, BN = 64, KT = 32, LDK = KT + 8;   // LDS rows padded by 16 bytes
+constexpr int BM = 64, BN = 64, KT = 64, LDK = KT + 8;   // LDS rows padded by 16 bytes
 constexpr int kThreads = 256;
 
-enum { EPI_STORE = 0, EPI_BIAS_ACT = 1, EPI_MSE = 2 };
+enum { EPI_STORE = 0, EPI_BIAS_ACT = 1, EPI_MSE = 2, EPI_ADAM = 3 };
 
 struct Epi {
     // EPI_STORE: C[z * zstride + i * ldc + j] = acc (FP32)
@@ -70,17 +70,40 @@ struct Epi {
     const void *T;
     float scale;
     float *loss_part, *dbias_part;
+    // EPI_ADAM: acc is the gradient of parameter e = i * ldc + j of
+    // (aw, am, av, awc); one Adam update of it (adam_one), nothing stored
+    float *aw, *am, *av;
+    void *awc;
+    float lr, b1, b2, eps, c1, c2;
 };
 
-// Column of k in LDS row `row`.  BF16 rows hold four 16-byte chunks of 8 k;
+// One Adam update of parameter e with gradient g: moments m, v, master
+// weight w, and (when wc is not null) its compute-type copy.  c1 and c2 are
+// the bias corrections 1 / (1 - beta1^t) and 1 / (1 - beta2^t).  The one
+// definition serves the stand-alone update and the product epilogue, so the
+// two give the same bits.
+template <typename T>
+__device__ inline void adam_one(int64_t e, float g, float *__restrict__ w, float *__restrict__ m,
+                                float *__restrict__ v, T *__restrict__ wc, float lr, float b1, float b2, float eps,
+                                float c1, float c2) {
+    const float mi = b1 * m[e] + (1.0f - b1) * g;
+    const float vi = b2 * v[e] + (1.0f - b2) * g * g;
+    m[e] = mi;
+    v[e] = vi;
+    const float wi = w[e] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+    w[e] = wi;
+    if (wc) wc[e] = cvt<T>(wi);
+}
+
+// Column of k in LDS row `row`.  BF16 rows hold eight 16-byte chunks of 8 k;
 // chunk c sits at c ^ ((row / 16) % 4).  Staging an m- or n-contiguous
 // operand writes, in one instruction, one k of rows 8 apart (rows 8 j + i,
-// j = 0..7), which the 80-byte row pitch alone puts on two bank groups;
+// j = 0..7), which the 144-byte row pitch alone puts on two bank groups;
 // the XOR spreads them over the 64 banks.  Sixteen consecutive rows share
 // one permutation, so the MFMA's 16-byte reads of 16 consecutive rows stay
 // as they were.  FP32 rows are not permuted.
 template <typename T> __device__ inline int swz(int row, int k);
-template <> __device__ inline int swz<uint16_t>(int row, int k) { return ((((k >> 3) ^ (row >> 4)) & 3) << 3) | (k & 7); }
+template <> __device__ inline int swz<uint16_t>(int row, int k) { return (((k >> 3) ^ ((row >> 4) & 3)) << 3) | (k & 7); }
 template <> __device__ inline int swz<float>(int, int k) { return k; }
 
 // The MFMA step for one K slice of KT held in LDS: acc += A[32 rows of the
@@ -108,27 +131,30 @@ __device__ inline void mma_slice<float>(f32x16 &acc, const float (*sA)[LDK], con
     }
 }
 
-// One K slice of a BF16 tile pair staged with 16-byte loads, one per thread
-// and operand (BM x KT and BN x KT values are 256 x 8): the caller
-// guarantees whole tiles (M, N multiples of 64, the slice inside K) and
-// 16-byte aligned rows.  vec_load fetches a slice into registers (issued a
-// slice ahead, so that the loads overlap the MFMA work); vec_store puts it
-// into LDS: k-contiguous rows as they are, m- or n-contiguous rows
-// transposed on the way.
+// One K slice of a BF16 tile pair staged with 16-byte loads, two per thread
+// and operand (BM x KT and BN x KT values are 2 x 256 x 8; half h = 0, 1
+// covers 32 of the 64 rows in memory): the caller guarantees whole tiles
+// (M, N multiples of 64, the slice inside K) and 16-byte aligned rows.
+// vec_load_* fetch a slice into registers (issued a slice ahead, so that
+// the loads overlap the MFMA work); vec_store puts it into LDS:
+// k-contiguous rows as they are, m- or n-contiguous rows transposed on the
+// way.
 template <int LAYOUT>
-__device__ inline uint4 vec_load_a(const uint16_t *__restrict__ A, int64_t lda, int m0, int k0, int tid) {
+__device__ inline uint4 vec_load_a(const uint16_t *__restrict__ A, int64_t lda, int m0, int k0, int tid, int h) {
+    const int row = (tid >> 3) + 32 * h, col = (tid & 7) * 8;
     if (LAYOUT == MLP_TN)   // A stored [K][M]: a row holds 64 m
-        return *reinterpret_cast<const uint4 *>(A + int64_t(k0 + (tid >> 3)) * lda + m0 + (tid & 7) * 8);
-    // A stored [M][K]: a row holds the slice's 32 k
-    return *reinterpret_cast<const uint4 *>(A + int64_t(m0 + (tid >> 2)) * lda + k0 + (tid & 3) * 8);
+        return *reinterpret_cast<const uint4 *>(A + int64_t(k0 + row) * lda + m0 + col);
+    // A stored [M][K]: a row holds the slice's 64 k
+    return *reinterpret_cast<const uint4 *>(A + int64_t(m0 + row) * lda + k0 + col);
 }
 
 template <int LAYOUT>
-__device__ inline uint4 vec_load_b(const uint16_t *__restrict__ B, int64_t ldb, int n0, int k0, int tid) {
+__device__ inline uint4 vec_load_b(const uint16_t *__restrict__ B, int64_t ldb, int n0, int k0, int tid, int h) {
+    const int row = (tid >> 3) + 32 * h, col = (tid & 7) * 8;
     if (LAYOUT == MLP_NT)   // B stored [N][K]
-        return *reinterpret_cast<const uint4 *>(B + int64_t(n0 + (tid >> 2)) * ldb + k0 + (tid & 3) * 8);
+        return *reinterpret_cast<const uint4 *>(B + int64_t(n0 + row) * ldb + k0 + col);
     // B stored [K][N]: a row holds 64 n
-    return *reinterpret_cast<const uint4 *>(B + int64_t(k0 + (tid >> 3)) * ldb + n0 + (tid & 7) * 8);
+    return *reinterpret_cast<const uint4 *>(B + int64_t(k0 + row) * ldb + n0 + col);
 }
 
 // Value i (0..7) of the eight BF16 values held in v, taken with shifts so
@@ -139,14 +165,13 @@ __device__ inline uint16_t half_of(uint4 v, int i) {
 }
 
 template <bool TRANSPOSED>
-__device__ inline void vec_store(uint4 v, uint16_t (*s)[LDK], int tid) {
-    if (TRANSPOSED) {
-        const int k = tid >> 3, r8 = (tid & 7) * 8;
+__device__ inline void vec_store(uint4 v, uint16_t (*s)[LDK], int tid, int h) {
+    const int row = (tid >> 3) + 32 * h, col = (tid & 7) * 8;   // as loaded
+    if (TRANSPOSED) {   // row is a k; col the first of eight m (or n)
 #pragma unroll
-        for (int i = 0; i < 8; ++i) s[r8 + i][swz<uint16_t>(r8 + i, k)] = half_of(v, i);
-    } else {
-        const int r = tid >> 2;
-        *reinterpret_cast<uint4 *>(&s[r][swz<uint16_t>(r, (tid & 3) * 8)]) = v;
+        for (int i = 0; i < 8; ++i) s[col + i][swz<uint16_t>(col + i, row)] = half_of(v, i);
+    } else {            // row is an m (or n); col the first of eight k
+        *reinterpret_cast<uint4 *>(&s[row][swz<uint16_t>(row, col)]) = v;
     }
 }
 
@@ -187,18 +212,24 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
         const auto *B16 = reinterpret_cast<const uint16_t *>(B);
         auto *sA16 = reinterpret_cast<uint16_t (*)[LDK]>(sA);
         auto *sB16 = reinterpret_cast<uint16_t (*)[LDK]>(sB);
-        uint4 ra = {}, rb = {};
+        uint4 ra0 = {}, ra1 = {}, rb0 = {}, rb1 = {};
         if (kbeg < kend) {
-            ra = vec_load_a<LAYOUT>(A16, lda, m0, kbeg, tid);
-            rb = vec_load_b<LAYOUT>(B16, ldb, n0, kbeg, tid);
+            ra0 = vec_load_a<LAYOUT>(A16, lda, m0, kbeg, tid, 0);
+            ra1 = vec_load_a<LAYOUT>(A16, lda, m0, kbeg, tid, 1);
+            rb0 = vec_load_b<LAYOUT>(B16, ldb, n0, kbeg, tid, 0);
+            rb1 = vec_load_b<LAYOUT>(B16, ldb, n0, kbeg, tid, 1);
         }
         for (int k0 = kbeg; k0 < kend; k0 += KT) {
-            vec_store<LAYOUT == MLP_TN>(ra, sA16, tid);
-            vec_store<LAYOUT != MLP_NT>(rb, sB16, tid);
+            vec_store<LAYOUT == MLP_TN>(ra0, sA16, tid, 0);
+            vec_store<LAYOUT == MLP_TN>(ra1, sA16, tid, 1);
+            vec_store<LAYOUT != MLP_NT>(rb0, sB16, tid, 0);
+            vec_store<LAYOUT != MLP_NT>(rb1, sB16, tid, 1);
             __syncthreads();
             if (k0 + KT < kend) {
-                ra = vec_load_a<LAYOUT>(A16, lda, m0, k0 + KT, tid);
-                rb = vec_load_b<LAYOUT>(B16, ldb, n0, k0 + KT, tid);
+                ra0 = vec_load_a<LAYOUT>(A16, lda, m0, k0 + KT, tid, 0);
+                ra1 = vec_load_a<LAYOUT>(A16, lda, m0, k0 + KT, tid, 1);
+                rb0 = vec_load_b<LAYOUT>(B16, ldb, n0, k0 + KT, tid, 0);
+                rb1 = vec_load_b<LAYOUT>(B16, ldb, n0, k0 + KT, tid, 1);
             }
             mma_slice<T>(acc, sA, sB, wm * 32 + (l & 31), wn * 32 + (l & 31), l);
             __syncthreads();
@@ -241,6 +272,14 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
         for (int r = 0; r < 16; ++r) {
             const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
             if (i < M && j < N) ep.C[z * ep.zstride + int64_t(i) * ep.ldc + j] = acc[r];
+        }
+    } else if (EPI == EPI_ADAM) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = m0 + wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3);
+            if (i < M && j < N)
+                adam_one<T>(int64_t(i) * ep.ldc + j, acc[r], ep.aw, ep.am, ep.av, static_cast<T *>(ep.awc), ep.lr,
+                            ep.b1, ep.b2, ep.eps, ep.c1, ep.c2);
         }
     } else if (EPI == EPI_BIAS_ACT) {
         const float bj = ep.bias && j < N ? ep.bias[j] : 0.0f;
@@ -327,15 +366,7 @@ __global__ void k_adam(int64_t n, float *__restrict__ w, float *__restrict__ m, 
                        const float *__restrict__ g, T *__restrict__ wc, float lr, float b1, float b2, float eps,
                        float c1, float c2) {
     const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    const float wi = w[i] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-    w[i] = wi;
-    if (wc) wc[i] = cvt<T>(wi);
+    if (i < n) adam_one<T>(i, g[i], w, m, v, wc, lr, b1, b2, eps, c1, c2);
 }
 
 template <typename T>
@@ -512,6 +543,13 @@ int gemm_dtype(int dtype, int layout, int M, int N, int K, const void *A, int64_
     return fail(HBMC_EINVAL, "unknown dtype %d", dtype);
 }
 
+// Adam's bias corrections for step t (1-based): 1 / (1 - beta^t), in FP64
+// and rounded once.
+void bias_corrections(float beta1, float beta2, int step, float &c1, float &c2) {
+    c1 = float(1.0 / (1.0 - std::pow(double(beta1), step)));
+    c2 = float(1.0 / (1.0 - std::pow(double(beta2), step)));
+}
+
 int check_dims(int M, int N, int K, int nsplit) {
     if (M < 1 || N < 1 || K < 1) return fail(HBMC_EINVAL, "bad sizes M=%d N=%d K=%d", M, N, K);
     if (nsplit < 1 || nsplit > 65535) return fail(HBMC_EINVAL, "bad split %d", nsplit);
@@ -619,8 +657,8 @@ extern "C" int mlp_relu_bwd(int32_t dtype, int64_t n, const float *dh, const voi
 extern "C" int mlp_adam(int32_t dtype, int64_t n, float *w, float *m, float *v, const float *g, void *wc,
                         float lr, float beta1, float beta2, float eps, int32_t step, void *stream) {
     if (!w || !m || !v || !g || n < 1 || step < 1) return fail(HBMC_EINVAL, "bad argument");
-    const float c1 = float(1.0 / (1.0 - std::pow(double(beta1), step)));
-    const float c2 = float(1.0 / (1.0 - std::pow(double(beta2), step)));
+    float c1, c2;
+    bias_corrections(beta1, beta2, step, c1, c2);
     auto s = static_cast<hipStream_t>(stream);
     if (dtype == MLP_BF16)
         hipLaunchKernelGGL(k_adam<uint16_t>, dim3(blocks_for(n)), dim3(256), 0, s, n, w, m, v, g,
@@ -777,6 +815,64 @@ extern "C" int mlp_forward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidde
     return HBMC_OK;
 }
 
+namespace {
+
+// Optimizer state of the six parameters for a training step whose output
+// layer takes its Adam update in the weight-gradient product.
+struct FusedAdam {
+    float *const *w, *const *m, *const *v;
+    void *const *wc;
+    float lr, b1, b2, eps, c1, c2;
+};
+
+// Loss and gradients of the network (mlp_backward).  With fa, the gradient
+// of W3 is not stored: the product h2^T dY applies Adam to W3 (master, moments
+// and compute copy W[2]) in its epilogue, after dY W3^T has read W3.
+int backward_impl(int dtype, int M, int n_in, int h, int n, const void *X, const void *T, const void *const *W,
+                  const float *const *b, float *const *grad, float *loss, const NetWork &w, hipStream_t s,
+                  const FusedAdam *fa) {
+    void *stream = s;
+    MLP_TRY(mlp_linear_fwd(dtype, M, h, n_in, X, W[0], b[0], 1, w.h1, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd(dtype, M, h, h, w.h1, W[1], b[1], 1, w.h2, nullptr, stream));
+    MLP_TRY(mlp_linear_fwd_mse(dtype, M, n, h, w.h2, W[2], b[2], T, 2.0f / (float(M) * float(n)), w.dY, w.loss,
+                               w.dbias, stream));
+    if (loss) {
+        hipLaunchKernelGGL(k_total, dim3(1), dim3(1024), 0, s, w.nloss, w.loss, loss);
+        HIP_TRY(hipGetLastError());
+    }
+    MLP_TRY(mlp_sum_rows(w.nrows, n, w.dbias, n, grad[5], stream));                          // db3
+    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, n, w.dY, n, W[2], n, w.part, h, w.split, stream));   // dY W3^T
+    MLP_TRY(mlp_sum_rows(w.split, int64_t(M) * h, w.part, int64_t(M) * h, w.dh, stream));
+    if (fa) {                                                                                 // h2^T dY -> Adam
+        Epi ep{};
+        ep.ldc = n;
+        ep.aw = fa->w[4];
+        ep.am = fa->m[4];
+        ep.av = fa->v[4];
+        ep.awc = fa->wc[4];
+        ep.lr = fa->lr;
+        ep.b1 = fa->b1;
+        ep.b2 = fa->b2;
+        ep.eps = fa->eps;
+        ep.c1 = fa->c1;
+        ep.c2 = fa->c2;
+        MLP_TRY(check_dims(h, n, M, 1));
+        MLP_TRY(gemm_dtype<EPI_ADAM>(dtype, MLP_TN, h, n, M, w.h2, h, w.dY, n, 1, ep, s));
+    } else {
+        MLP_TRY(mlp_gemm(dtype, MLP_TN, h, n, M, w.h2, h, w.dY, n, grad[4], n, 1, stream));   // h2^T dY
+    }
+    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h2, w.dz, w.dzf, stream));
+    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[3], stream));                                    // db2
+    MLP_TRY(mlp_gemm(dtype, MLP_TN, h, h, M, w.h1, h, w.dz, h, grad[2], h, 1, stream));        // h1^T dz2
+    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, h, w.dz, h, W[1], h, w.dh, h, 1, stream));           // dz2 W2^T
+    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h1, w.dz, w.dzf, stream));
+    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[1], stream));                                    // db1
+    MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, grad[0], h, 1, stream));     // x^T dz1
+    return HBMC_OK;
+}
+
+}  // namespace
+
 extern "C" int mlp_backward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
                             const void *T, const void *const *W, const float *const *b, float *const *grad,
                             float *loss, void *work, size_t work_bytes, void *stream) {
@@ -788,27 +884,36 @@ extern "C" int mlp_backward(int32_t dtype, int32_t M, int32_t n_in, int32_t hidd
         return fail(HBMC_EINVAL, "workspace too small");
     NetWork w{};
     net_layout(dtype, M, n_in, hidden, n_out, &w, work);
-    auto s = static_cast<hipStream_t>(stream);
-    const int h = hidden, n = n_out;
-    MLP_TRY(mlp_linear_fwd(dtype, M, h, n_in, X, W[0], b[0], 1, w.h1, nullptr, stream));
-    MLP_TRY(mlp_linear_fwd(dtype, M, h, h, w.h1, W[1], b[1], 1, w.h2, nullptr, stream));
-    MLP_TRY(mlp_linear_fwd_mse(dtype, M, n, h, w.h2, W[2], b[2], T, 2.0f / (float(M) * float(n)), w.dY, w.loss,
-                               w.dbias, stream));
-    if (loss) {
-        hipLaunchKernelGGL(k_total, dim3(1), dim3(1024), 0, s, w.nloss, w.loss, loss);
-        HIP_TRY(hipGetLastError());
-    }
-    MLP_TRY(mlp_sum_rows(w.nrows, n, w.dbias, n, grad[5], stream));                          // db3
-    MLP_TRY(mlp_gemm(dtype, MLP_TN, h, n, M, w.h2, h, w.dY, n, grad[4], n, 1, stream));        // h2^T dY
-    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, n, w.dY, n, W[2], n, w.part, h, w.split, stream));   // dY W3^T
-    MLP_TRY(mlp_sum_rows(w.split, int64_t(M) * h, w.part, int64_t(M) * h, w.dh, stream));
-    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h2, w.dz, w.dzf, stream));
-    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[3], stream));                                    // db2
-    MLP_TRY(mlp_gemm(dtype, MLP_TN, h, h, M, w.h1, h, w.dz, h, grad[2], h, 1, stream));        // h1^T dz2
-    MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, h, w.dz, h, W[1], h, w.dh, h, 1, stream));           // dz2 W2^T
-    MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h1, w.dz, w.dzf, stream));
-    MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[1], stream));                                    // db1
-    MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, grad[0], h, 1, stream));     // x^T dz1
+    return backward_impl(dtype, M, n_in, hidden, n_out, X, T, W, b, grad, loss, w, static_cast<hipStream_t>(stream),
+                         nullptr);
+}
+
+extern "C" int mlp_train_step(int32_t dtype, int32_t M, int32_t n_in, int32_t hidden, int32_t n_out, const void *X,
+                              const void *T, float *const *w, float *const *m, float *const *v, float *const *grad,
+                              void *const *wc, float lr, float beta1, float beta2, float eps, int32_t step,
+                              float *loss, void *work, size_t work_bytes, void *stream) {
+    if (!w || !m || !v || !grad || !wc) return fail(HBMC_EINVAL, "null argument");
+    for (int i = 0; i < 6; ++i)
+        if (!w[i] || !m[i] || !v[i] || !grad[i]) return fail(HBMC_EINVAL, "null parameter array %d", i);
+    if (step < 1) return fail(HBMC_EINVAL, "step %d < 1", step);
+    const void *W[3] = {wc[0], wc[2], wc[4]};
+    const float *b[3] = {w[1], w[3], w[5]};
+    MLP_TRY(check_net(dtype, M, n_in, hidden, n_out, W, b));
+    if (!X || !T || !work) return fail(HBMC_EINVAL, "null argument");
+    if (work_bytes < net_layout(dtype, M, n_in, hidden, n_out, nullptr, nullptr))
+        return fail(HBMC_EINVAL, "workspace too small");
+    NetWork nw{};
+    net_layout(dtype, M, n_in, hidden, n_out, &nw, work);
+    FusedAdam fa{w, m, v, wc, lr, beta1, beta2, eps, 0.0f, 0.0f};
+    bias_corrections(beta1, beta2, step, fa.c1, fa.c2);
+    MLP_TRY(backward_impl(dtype, M, n_in, hidden, n_out, X, T, W, b, grad, loss, nw,
+                          static_cast<hipStream_t>(stream), &fa));
+    const int64_t sizes[6] = {int64_t(n_in) * hidden, hidden, int64_t(hidden) * hidden, hidden,
+                              int64_t(hidden) * n_out, n_out};
+    for (int i = 0; i < 6; ++i)
+        if (i != 4)
+            MLP_TRY(mlp_adam(dtype, sizes[i], w[i], m[i], v[i], grad[i], wc[i], lr, beta1, beta2, eps, step,
+                             stream));
     return HBMC_OK;
 }
 

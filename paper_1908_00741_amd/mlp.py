@@ -21,7 +21,8 @@ MLP_NN, MLP_TN, MLP_NT = 0, 1, 2
 
 SYMBOLS = ("mlp_gemm", "mlp_linear_fwd", "mlp_linear_fwd_mse", "mlp_mse_parts", "mlp_sum_rows",
            "mlp_relu_bwd", "mlp_adam", "mlp_cast", "mlp_cast_f64", "mlp_to_f64", "mlp_gaussian_rhs",
-           "mlp_combine", "mlp_workspace_bytes", "mlp_forward", "mlp_backward", "mlp_adam_step")
+           "mlp_combine", "mlp_workspace_bytes", "mlp_forward", "mlp_backward", "mlp_adam_step",
+           "mlp_train_step")
 
 _ready = False
 
@@ -47,6 +48,8 @@ def lib():
         L.mlp_forward.argtypes = [i32, i32, i32, i32, i32, P, P, P, P, P, P, C.c_size_t, P]
         L.mlp_backward.argtypes = [i32, i32, i32, i32, i32, P, P, P, P, P, P, P, C.c_size_t, P]
         L.mlp_adam_step.argtypes = [i32, i32, P, P, P, P, P, P, f32, f32, f32, f32, i32, P]
+        L.mlp_train_step.argtypes = [i32, i32, i32, i32, i32, P, P, P, P, P, P, P, f32, f32, f32, f32, i32, P, P,
+                                     C.c_size_t, P]
         _ready = True
     return L
 
@@ -216,6 +219,22 @@ class MLP:
         _ck("mlp_adam_step", lib().mlp_adam_step(self.dtype, k, sizes, arr(self.master), arr(self.m), arr(self.v),
                                                  arr(self.grad), arr(self.comp), opt.lr, opt.beta1, opt.beta2,
                                                  opt.eps, self.step_no, _s(stream)))
+
+    def train_step(self, theta, target, opt: Adam, stream=None):
+        """loss_and_grads then adam_step in one call, with the output layer's
+        update applied in its weight-gradient product (self.grad[4] is not
+        written).  Returns the loss tensor of loss_and_grads."""
+        M = theta.shape[0]
+        B = self.load_input(theta, stream)
+        n_in, h, _, n = self.dims
+        self.step_no += 1
+        arr = lambda ts: (C.c_void_p * 6)(*[t.data_ptr() for t in ts])
+        _ck("mlp_train_step", lib().mlp_train_step(self.dtype, M, n_in, h, n, _p(B["x"]), _p(target),
+                                                   arr(self.master), arr(self.m), arr(self.v), arr(self.grad),
+                                                   arr(self.comp), opt.lr, opt.beta1, opt.beta2, opt.eps,
+                                                   self.step_no, _p(B["loss"]), _p(B["work"]), B["work"].numel(),
+                                                   _s(stream)))
+        return B["loss"]
 
     def state(self):
         """Host copies of the master weights, moments and step (checkpoint)."""

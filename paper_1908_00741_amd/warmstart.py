@@ -161,13 +161,13 @@ class WarmStart:
             th = np.concatenate([S[np.arange(4), k], W[np.arange(4), k], amp], axis=1)
             idx = k + per * np.arange(4)
             mlp.combine(self.dtype, G, idx, amp, 1.0, T)
-            parts = self.net.loss_and_grads(torch.from_numpy(features(th)).to(self.device), T)
+            rate = lr * 0.5 * (1.0 + np.cos(np.pi * (step - 1) / steps))
+            # loss of the weights before this step's update
+            parts = self.net.train_step(torch.from_numpy(features(th)).to(self.device), T, mlp.Adam(lr=float(rate)))
             if step % log_every == 0 or step == steps:
                 loss = float(parts.cpu().numpy().astype(np.float64).sum()) / (batch * self.n)
                 curve.append([step, loss])
                 log(f"[warmstart] step {step}: loss {loss:.4e} ({time.perf_counter() - t0:.1f} s)")
-            rate = lr * 0.5 * (1.0 + np.cos(np.pi * (step - 1) / steps))
-            self.net.adam_step(mlp.Adam(lr=float(rate)))
         torch.cuda.synchronize()
         return {"steps": steps, "batch": batch, "lr": lr, "schedule": "cosine",
                 "seconds": round(time.perf_counter() - t0, 2), "curve": curve}
@@ -189,10 +189,9 @@ class WarmStart:
             for k in rng.permutation(len(starts)):
                 a = starts[k]
                 e = min(count, a + batch)
-                parts = self.net.loss_and_grads(th[a:e], targets[a:e])
+                parts = self.net.train_step(th[a:e], targets[a:e], opt)
                 if logging:   # loss before this batch's update (host sum of the partials)
                     total += float(parts.cpu().numpy().astype(np.float64).sum())
-                self.net.adam_step(opt)
             if logging:
                 loss = total / (count * self.n)
                 curve.append([ep + 1, loss])

@@ -47,14 +47,15 @@ def _to_dtype(torch, a, dtype):
 
 @pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
 @pytest.mark.parametrize("layout", [mlp.MLP_NN, mlp.MLP_TN, mlp.MLP_NT], ids=["NN", "TN", "NT"])
-@pytest.mark.parametrize("M,N,K,split,pad", [(70, 130, 45, 1, 0), (64, 64, 32, 1, 0), (5, 300, 1000, 3, 0),
-                                             (128, 33, 12, 1, 0), (128, 192, 256, 3, 0), (192, 128, 96, 1, 8),
-                                             (128, 64, 64, 1, 3)])
+@pytest.mark.parametrize("M,N,K,split,pad", [(70, 130, 45, 1, 0), (64, 64, 32, 1, 0), (64, 64, 64, 1, 0),
+                                             (5, 300, 1000, 3, 0), (128, 33, 12, 1, 0), (128, 192, 256, 3, 0),
+                                             (192, 128, 128, 1, 8), (128, 64, 64, 1, 3)])
 def test_gemm(torch, dtype, layout, M, N, K, split, pad):
-    """Whole 64 x 64 tiles with K a multiple of 32 and rows 16-byte aligned
-    take the BF16 kernel's 16-byte staging (with a split over K, and with
-    rows padded by pad elements); a pad of 3 breaks the alignment and takes
-    the element-wise staging on the same shape."""
+    """Whole 64 x 64 tiles with K a multiple of 64 (the K slice) and rows
+    16-byte aligned take the BF16 kernel's 16-byte staging (with a split
+    over K whose last range is empty, and with rows padded by pad
+    elements); a pad of 3 breaks the alignment and K = 32 a whole slice, so
+    those take the element-wise staging."""
     print(f"gemm dtype {dtype} layout {layout} {M}x{N}x{K} split {split} pad {pad}", flush=True)
     rng = np.random.default_rng(M + N + K)
     A = _bf16_exact(rng, (M, K))
@@ -137,6 +138,36 @@ def test_gradients_against_oracle(torch, dtype, tol, M, n):
         assert abs(loss - L) <= bar * abs(L)
         for k, (g, gr) in enumerate(zip(grads, gs)):
             assert np.linalg.norm(g - gr) <= bar * np.linalg.norm(gr), (k, bar)
+
+
+@pytest.mark.parametrize("M,n", [(40, 777), (128, 768)], ids=["ragged", "whole_tiles"])
+@pytest.mark.parametrize("dtype", [mlp.MLP_F32, mlp.MLP_BF16], ids=["f32", "bf16"])
+def test_train_step_matches_separate_calls(torch, dtype, M, n):
+    """mlp_train_step (W3's Adam update inside its weight-gradient product)
+    against loss_and_grads + adam_step on the same weights and batches: the
+    same bits in every master weight, moment, compute copy and loss, over
+    two steps; W3's gradient array is left as it was."""
+    print(f"train step dtype {dtype} batch {M} outputs {n}", flush=True)
+    rng = np.random.default_rng(5)
+    ps = _net(rng, [12, 256, 256, n])
+    nets = [mlp.MLP(n, dtype=dtype) for _ in range(2)]
+    for net in nets:
+        net.set_weights(ps)
+    nets[1].grad[4].fill_(12345.0)
+    opt = mlp.Adam(lr=3e-3)
+    for it in range(2):
+        theta = torch.from_numpy(rng.uniform(-1, 1, (M, 12)).astype(np.float32)).cuda()
+        tgt = _to_dtype(torch, rng.uniform(-1, 1, (M, n)).astype(np.float32), dtype)
+        l0 = nets[0].loss_and_grads(theta, tgt).clone()
+        nets[0].adam_step(opt)
+        l1 = nets[1].train_step(theta, tgt, opt).clone()
+        torch.cuda.synchronize()
+        assert torch.equal(l0, l1), it
+        for k in range(6):
+            for name in ("master", "m", "v", "comp"):
+                a, b = getattr(nets[0], name)[k], getattr(nets[1], name)[k]
+                assert torch.equal(a, b), (it, k, name)
+    assert bool((nets[1].grad[4] == 12345.0).all())
 
 
 def test_adam_step(torch):

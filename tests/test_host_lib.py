@@ -45,6 +45,29 @@ def test_mlp_gemm_rejects_short_leading_dimensions():
         assert code == hbmc.HBMC_EINVAL, (layout, lda, ldb, ldc)
 
 
+def test_mlp_train_step_rejects_bad_arguments():
+    """Argument errors of the fused training step come back before any
+    launch (host buffers stand in for device arrays and are never read)."""
+    import ctypes as C
+    from paper_1908_00741_amd import mlp
+    L = mlp.lib()
+    buf = (C.c_float * 64)()
+    p = C.cast(buf, C.c_void_p)
+    six = (C.c_void_p * 6)(*([p.value] * 6))
+    holed = (C.c_void_p * 6)(*([p.value] * 3 + [None] + [p.value] * 2))
+
+    def call(w=six, m=six, v=six, g=six, wc=six, step=1, dtype=mlp.MLP_BF16, M=4, work_bytes=1 << 40):
+        return L.mlp_train_step(dtype, M, 12, 256, 64, p, p, w, m, v, g, wc, 1e-3, 0.9, 0.999, 1e-8, step, p, p,
+                                work_bytes, None)
+    assert call(step=0) == hbmc.HBMC_EINVAL
+    assert call(m=holed) == hbmc.HBMC_EINVAL
+    assert call(wc=(C.c_void_p * 6)(*([p.value] * 4 + [None, p.value]))) == hbmc.HBMC_EINVAL   # W3 copy missing
+    assert call(dtype=7) == hbmc.HBMC_EINVAL
+    assert call(M=0) == hbmc.HBMC_EINVAL
+    assert call(work_bytes=16) == hbmc.HBMC_EINVAL
+    assert call(w=None) == hbmc.HBMC_EINVAL
+
+
 def test_exports_every_declared_symbol():
     header = open(os.path.join(ROOT, "include", "hbmc.h")).read()
     header = re.sub(r"/\*.*?\*/", "", header, flags=re.S)
