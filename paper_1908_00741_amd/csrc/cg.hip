@@ -97,6 +97,34 @@ __device__ inline double sys_total(const double *part, const int32_t *ranges, in
     return block_sum(acc);
 }
 
+// sys_total of two partial arrays over the same ranges in one pass (loads of
+// both in flight together); each total is added in the same order as by
+// sys_total, so the results are the same bits.  Valid in thread 0.
+__device__ inline void sys_total2(const double *pa, const double *pb, const int32_t *ranges, int nc, int s,
+                                  int tmul, double &ta, double &tb) {
+    double acc_a = 0.0, acc_b = 0.0;
+    for (int c = 0; c < nc;) {
+        const int a = ranges[(s * nc + c) * 2] * tmul;
+        int b = ranges[(s * nc + c) * 2 + 1] * tmul;
+        for (++c; c < nc && ranges[(s * nc + c) * 2] * tmul == b; ++c) b = ranges[(s * nc + c) * 2 + 1] * tmul;
+        for (int i0 = a + int(threadIdx.x); i0 < b; i0 += kFin * kLoads) {
+            double va[kLoads], vb[kLoads];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) {
+                const bool in = i0 + k * kFin < b;
+                va[k] = in ? pa[i0 + k * kFin] : 0.0;
+                vb[k] = in ? pb[i0 + k * kFin] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) acc_a += va[k];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) acc_b += vb[k];
+        }
+    }
+    ta = block_sum(acc_a);
+    tb = block_sum(acc_b);
+}
+
 // Abar: diagonal plus off-diagonal couplings in 64-row groups of strided
 // and indexed slots (a wavefront covers rows of one group).
 struct Mat {
@@ -445,8 +473,8 @@ __global__ void __launch_bounds__(kFin) k_fin_rr_beta(const double *part_rr, con
     const int b = blockIdx.x, s = b / K, q = b % K;
     CgState &c = st[b];
     if (c.done) return;
-    const double rr = sys_total(part_rr + q * ptiles, sys.tiles, sys.nc, s, tmul);
-    const double rz = sys_total(part_rz + q * ptiles, sys.tiles, sys.nc, s, tmul);
+    double rr, rz;
+    sys_total2(part_rr + q * ptiles, part_rz + q * ptiles, sys.tiles, sys.nc, s, tmul, rr, rz);
     if (threadIdx.x) return;
     c.rr = rr;
     c.it += 1;
