@@ -82,17 +82,26 @@ struct Epi {
 // the bias corrections 1 / (1 - beta1^t) and 1 / (1 - beta2^t).  The one
 // definition serves the stand-alone update and the product epilogue, so the
 // two give the same bits.
+__device__ inline void adam_math(float g, float m, float v, float w, float lr, float b1, float b2, float eps,
+                                 float c1, float c2, float &mo, float &vo, float &wo) {
+    // no fused multiply-adds: whether b1 m + (1 - b1) g fuses one product or
+    // the other would otherwise depend on the surrounding code
+#pragma clang fp contract(off)
+    mo = b1 * m + (1.0f - b1) * g;
+    vo = b2 * v + (1.0f - b2) * g * g;
+    wo = w - lr * (mo * c1) / (sqrtf(vo * c2) + eps);
+}
+
 template <typename T>
 __device__ inline void adam_one(int64_t e, float g, float *__restrict__ w, float *__restrict__ m,
                                 float *__restrict__ v, T *__restrict__ wc, float lr, float b1, float b2, float eps,
                                 float c1, float c2) {
-    const float mi = b1 * m[e] + (1.0f - b1) * g;
-    const float vi = b2 * v[e] + (1.0f - b2) * g * g;
-    m[e] = mi;
-    v[e] = vi;
-    const float wi = w[e] - lr * (mi * c1) / (sqrtf(vi * c2) + eps);
-    w[e] = wi;
-    if (wc) wc[e] = cvt<T>(wi);
+    float mo, vo, wo;
+    adam_math(g, m[e], v[e], w[e], lr, b1, b2, eps, c1, c2, mo, vo, wo);
+    m[e] = mo;
+    v[e] = vo;
+    w[e] = wo;
+    if (wc) wc[e] = cvt<T>(wo);
 }
 
 // Column of k in LDS row `row`.  BF16 rows hold eight 16-byte chunks of 8 k;
@@ -322,13 +331,24 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
     }
 }
 
-// out[j] = sum over i < R of src[i * ld + j], i in order
+// out[j] = sum over i < R of src[i * ld + j], i in order; the loads of
+// sixteen rows are issued before they are added (few columns, many rows:
+// one load latency per sixteen rows rather than per row)
 __global__ void k_sum_rows(int64_t R, int64_t N, const float *__restrict__ src, int64_t ld,
                            float *__restrict__ out) {
     const int64_t j = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (j >= N) return;
+    constexpr int kRows = 16;
     float s = 0.0f;
-    for (int64_t i = 0; i < R; ++i) s += src[i * ld + j];
+    int64_t i = 0;
+    for (; i + kRows <= R; i += kRows) {
+        float v[kRows];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) v[k] = src[(i + k) * ld + j];
+#pragma unroll
+        for (int k = 0; k < kRows; ++k) s += v[k];
+    }
+    for (; i < R; ++i) s += src[i * ld + j];
     out[j] = s;
 }
 
@@ -336,7 +356,16 @@ __global__ void k_sum_rows(int64_t R, int64_t N, const float *__restrict__ src, 
 __global__ void __launch_bounds__(1024) k_total(int64_t n, const float *__restrict__ src, float *__restrict__ out) {
     __shared__ double sh[16];
     double acc = 0.0;
-    for (int64_t i = threadIdx.x; i < n; i += 1024) acc += src[i];
+    int64_t i = threadIdx.x;
+    // sixteen loads in flight per thread, added in the order of i
+    for (; i + 15 * 1024 < n; i += 16 * 1024) {
+        float v[16];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) v[k] = src[i + k * 1024];
+#pragma unroll
+        for (int k = 0; k < 16; ++k) acc += v[k];
+    }
+    for (; i < n; i += 1024) acc += src[i];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
     if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;

@@ -233,6 +233,34 @@ class WarmStart:
                 "true_rel_res_max_x0_zero": float(r[:, 4].max()), "true_rel_res_max_warm": float(r[:, 5].max())}
 
 
+def time_steps(N, steps, batch=256, dtype=mlp.MLP_BF16, device="cuda:0", seed=0):
+    """Time of one fused training step (forward, backward, Adam) of the
+    12-256-256-N^3 network on a fixed synthetic batch (inputs uniform in
+    [-1, 1], targets standard normal), after three untimed steps."""
+    import torch
+    dev = torch.device(device)
+    n = N ** 3
+    rng = np.random.default_rng(seed)
+    net = mlp.MLP(n, dtype=dtype, seed=seed, device=dev)
+    theta = torch.from_numpy(rng.uniform(-1.0, 1.0, (batch, 12)).astype(np.float32)).to(dev)
+    tf = torch.from_numpy(rng.standard_normal((batch, n), dtype=np.float32)).to(dev)
+    target = torch.empty((batch, n), dtype=mlp._torch_dtype(dtype), device=dev)
+    mlp.cast(dtype, tf, target)
+    del tf
+    opt = mlp.Adam(lr=1e-3)
+    for _ in range(3):
+        net.train_step(theta, target, opt)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.train_step(theta, target, opt)
+    e1.record()
+    torch.cuda.synchronize()
+    return {"network": f"12-256-256-{n}", "dtype": "bf16" if dtype == mlp.MLP_BF16 else "f32", "batch": batch,
+            "steps": steps, "ms_per_step": round(e0.elapsed_time(e1) / steps, 4)}
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--N", type=int, default=96)
@@ -246,10 +274,16 @@ def main(argv=None) -> int:
     ap.add_argument("--batch", type=int, default=256)
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--f32", action="store_true", help="FP32 network (default BF16)")
+    ap.add_argument("--time-steps", type=int, default=0,
+                    help="only time this many training steps of the N^3 network on a synthetic batch")
     args = ap.parse_args(argv)
+    dtype = mlp.MLP_F32 if args.f32 else mlp.MLP_BF16
+    if args.time_steps > 0:
+        print(json.dumps(time_steps(args.N, args.time_steps, args.batch, dtype)), flush=True)
+        return 0
     import torch
     dev = torch.device("cuda:0")
-    ws = WarmStart(args.N, dtype=mlp.MLP_F32 if args.f32 else mlp.MLP_BF16, device=dev)
+    ws = WarmStart(args.N, dtype=dtype, device=dev)
     test_th = inputs.sample_sources(args.test, 12)
     if args.mode == "combined":
         log(f"[warmstart] {args.N}^3, {args.train} single-source solutions")

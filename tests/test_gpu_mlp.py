@@ -170,6 +170,20 @@ def test_train_step_matches_separate_calls(torch, dtype, M, n):
     assert bool((nets[1].grad[4] == 12345.0).all())
 
 
+@pytest.mark.parametrize("R,N,pad", [(1, 5, 0), (15, 257, 0), (16, 64, 3), (17, 1, 0), (300, 257, 7)])
+def test_sum_rows_in_order(torch, R, N, pad):
+    """Column sums in FP32, rows added in order: the same bits as a
+    sequential FP32 sum on the host (rows loaded sixteen at a time)."""
+    rng = np.random.default_rng(R * 31 + N)
+    src = rng.standard_normal((R, N + pad)).astype(np.float32)
+    out = torch.empty(N, dtype=torch.float32, device="cuda")
+    mlp.sum_rows(R, N, torch.from_numpy(src).cuda(), N + pad, out)
+    ref = np.zeros(N, dtype=np.float32)
+    for i in range(R):
+        ref = (ref + src[i, :N]).astype(np.float32)
+    assert np.array_equal(out.cpu().numpy(), ref)
+
+
 def test_adam_step(torch):
     from oracle import mlp as omlp
     rng = np.random.default_rng(5)
