@@ -15,6 +15,8 @@ Bars:
 - one Adam step against the published update: 1e-6 relative;
 - the Gaussian-source right-hand side against the input generator: 1e-12.
 """
+import ctypes as C
+
 import numpy as np
 import pytest
 
@@ -96,6 +98,56 @@ def test_linear_fwd(torch, dtype, M, N, K):
             ref = np.maximum(ref, 0.0)
         bound = np.abs(X).astype(np.float64) @ np.abs(W).astype(np.float64) + np.abs(b)
         assert np.all(np.abs(Yf.cpu().numpy() - ref) <= 1e-5 * bound + 1e-30)
+
+
+@pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
+@pytest.mark.parametrize("M,N,K", [(70, 333, 45), (128, 192, 128), (64, 64, 64)])
+def test_linear_fwd_mse(torch, dtype, M, N, K):
+    """Output layer with the loss: dY = scale (X W + b - T) in the compute
+    type, the loss partial of each 64 x 64 output tile and the bias-gradient
+    partial of each 64-row tile, against FP64 on inputs that bfloat16 holds
+    exactly (whole tiles take the 16-byte epilogue of the BF16 kernel)."""
+    print(f"linear_fwd_mse dtype {dtype} {M}x{N}x{K}", flush=True)
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    X = _bf16_exact(rng, (M, K))
+    W = _bf16_exact(rng, (K, N))
+    T = _bf16_exact(rng, (M, N))
+    b = (rng.integers(-64, 64, N) / 32.0).astype(np.float32)
+    scale = 2.0 / (M * N)
+    nl, nr = C.c_int64(0), C.c_int64(0)
+    mlp._ck("mlp_mse_parts", mlp.lib().mlp_mse_parts(M, N, C.byref(nl), C.byref(nr)))
+    Mt, Nt = (M + 63) // 64, (N + 63) // 64
+    assert (nl.value, nr.value) == (Mt * Nt, Mt)
+    dY = torch.empty((M, N), dtype=torch.int16 if dtype == mlp.MLP_BF16 else torch.float32, device="cuda")
+    loss = torch.empty(nl.value, dtype=torch.float32, device="cuda")
+    dbias = torch.empty((nr.value, N), dtype=torch.float32, device="cuda")
+    Xd, Wd, Td = _to_dtype(torch, X, dtype), _to_dtype(torch, W, dtype), _to_dtype(torch, T, dtype)
+    bd = torch.from_numpy(b).cuda()
+    mlp._ck("mlp_linear_fwd_mse", mlp.lib().mlp_linear_fwd_mse(dtype, M, N, K, mlp._p(Xd), mlp._p(Wd), mlp._p(bd),
+                                                               mlp._p(Td), scale, mlp._p(dY), mlp._p(loss),
+                                                               mlp._p(dbias), mlp._s()))
+    torch.cuda.synchronize()
+    y = X.astype(np.float64) @ W.astype(np.float64) + b
+    bound = np.abs(X).astype(np.float64) @ np.abs(W).astype(np.float64) + np.abs(b)
+    d = y - T
+    g = scale * d
+    if dtype == mlp.MLP_BF16:
+        got = (dY.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
+        got = got.view(np.float32).astype(np.float64)
+        assert np.all(np.abs(got - g) <= 2.0 ** -8 * np.abs(g) + scale * 1e-5 * bound + 1e-30)
+    else:
+        assert np.all(np.abs(dY.cpu().numpy() - g) <= scale * 1e-5 * bound + 1e-30)
+    lp = loss.cpu().numpy().astype(np.float64).reshape(Mt, Nt)
+    dp = dbias.cpu().numpy().astype(np.float64)
+    for mt in range(Mt):
+        rows = slice(64 * mt, min(M, 64 * mt + 64))
+        ref_db = g[rows].sum(axis=0)
+        tol_db = scale * (np.abs(d[rows]).sum(axis=0) * 1e-5 + 1e-5 * bound[rows].sum(axis=0))
+        assert np.all(np.abs(dp[mt] - ref_db) <= tol_db + 1e-30), mt
+        for nt in range(Nt):
+            cols = slice(64 * nt, min(N, 64 * nt + 64))
+            ref_l = (d[rows, cols] ** 2).sum()
+            assert abs(lp[mt, nt] - ref_l) <= 1e-5 * ref_l + 2e-5 * (np.abs(d[rows, cols]) * bound[rows, cols]).sum()
 
 
 def _net(rng, dims):
