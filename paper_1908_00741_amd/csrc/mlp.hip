@@ -206,8 +206,12 @@ __device__ inline void tile_of(int Mt, int Nt, int &mt, int &nt, int &z) {
 template <typename T, int LAYOUT, int EPI, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T *__restrict__ A, int64_t lda,
                                                    const T *__restrict__ B, int64_t ldb, int kchunk, Epi ep) {
-    __shared__ __align__(16) T sA[BM][LDK];
-    __shared__ __align__(16) T sB[BN][LDK];
+    // the staging tiles of A and B; after the K loop the whole-tile loss
+    // epilogue reuses the space for the FP32 output tile
+    constexpr int kStage = (BM + BN) * LDK * int(sizeof(T)), kOut = BM * (BN + 4) * 4;
+    __shared__ __align__(16) unsigned char smem[kStage > kOut ? kStage : kOut];
+    T (*sA)[LDK] = reinterpret_cast<T (*)[LDK]>(smem);
+    T (*sB)[LDK] = reinterpret_cast<T (*)[LDK]>(smem + BM * LDK * sizeof(T));
     const int tid = threadIdx.x, l = tid & 63, wave = tid >> 6;
     const int wm = wave >> 1, wn = wave & 1;
     const int Mt = (M + BM - 1) / BM, Nt = (N + BN - 1) / BN;
@@ -302,6 +306,66 @@ __global__ void __launch_bounds__(kThreads) k_gemm(int M, int N, int K, const T 
                 if (ep.Yf) ep.Yf[int64_t(i) * ep.ldc + j] = y;
             }
         }
+    } else if (VEC) {   // EPI_MSE, whole BF16 tiles
+        // The FP32 tile goes through LDS so that a thread owns runs of four
+        // columns (8-byte loads of T, 8-byte stores of dY): rows rg and
+        // rg + 32, columns c4..c4+3 and 32+c4..32+c4+3.
+        __shared__ float sCol[kThreads / 64][BN];
+        __shared__ float sLoss[kThreads / 64];
+        float (*sC)[BN + 4] = reinterpret_cast<float (*)[BN + 4]>(smem);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) sC[wm * 32 + 8 * (r >> 2) + 4 * (l >> 5) + (r & 3)][wn * 32 + (l & 31)] = acc[r];
+        __syncthreads();
+        const int c4 = (tid & 7) * 4, rg = tid >> 3;
+        const auto *T16 = static_cast<const uint16_t *>(ep.T);
+        auto *Y16 = static_cast<uint16_t *>(ep.Y);
+        float bj[8], col[8], loss = 0.0f;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            bj[k] = ep.bias ? ep.bias[n0 + 32 * (k >> 2) + c4 + (k & 3)] : 0.0f;
+            col[k] = 0.0f;
+        }
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int ii = rg + 32 * p;
+            const int64_t row = int64_t(m0 + ii) * ep.ldc + n0;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int jj = 32 * h + c4;
+                const float4 a = *reinterpret_cast<const float4 *>(&sC[ii][jj]);
+                const uint2 t = *reinterpret_cast<const uint2 *>(T16 + row + jj);
+                const float av[4] = {a.x, a.y, a.z, a.w};
+                const uint32_t tw[2] = {t.x, t.y};
+                uint32_t out[2] = {0u, 0u};
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const float d = av[q] + bj[4 * h + q] - bf2f(uint16_t(tw[q >> 1] >> (16 * (q & 1))));
+                    const float g = ep.scale * d;
+                    out[q >> 1] |= uint32_t(f2bf(g)) << (16 * (q & 1));
+                    col[4 * h + q] += g;
+                    loss += d * d;
+                }
+                *reinterpret_cast<uint2 *>(Y16 + row + jj) = make_uint2(out[0], out[1]);
+            }
+        }
+        // column partials over the wavefront's eight row groups (lane bits
+        // 3..5), then over the four wavefronts in order
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            col[k] += __shfl_xor(col[k], 8, 64);
+            col[k] += __shfl_xor(col[k], 16, 64);
+            col[k] += __shfl_xor(col[k], 32, 64);
+        }
+        if (l < 8) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k) sCol[wave][32 * (k >> 2) + c4 + (k & 3)] = col[k];
+        }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) loss += __shfl_xor(loss, o, 64);
+        if (l == 0) sLoss[wave] = loss;
+        __syncthreads();
+        if (tid < BN) ep.dbias_part[int64_t(mt) * N + n0 + tid] = (sCol[0][tid] + sCol[1][tid]) + (sCol[2][tid] + sCol[3][tid]);
+        if (tid == 0) ep.loss_part[int64_t(mt) * Nt + nt] = (sLoss[0] + sLoss[1]) + (sLoss[2] + sLoss[3]);
     } else {   // EPI_MSE
         __shared__ float sCol[2][BN];
         __shared__ float sLoss[kThreads / 64];
@@ -553,6 +617,9 @@ int launch_gemm(int layout, int M, int N, int K, const void *A, int64_t lda, con
         vec = M % BM == 0 && N % BN == 0 && K % KT == 0 && lda % 8 == 0 &&
                      ldb % 8 == 0 && reinterpret_cast<uintptr_t>(A) % 16 == 0 &&
                      reinterpret_cast<uintptr_t>(B) % 16 == 0;
+    if (EPI == EPI_MSE)   // the whole-tile loss epilogue: 8-byte runs of T and dY
+        vec = vec && ep.ldc % 4 == 0 && reinterpret_cast<uintptr_t>(ep.T) % 8 == 0 &&
+              reinterpret_cast<uintptr_t>(ep.Y) % 8 == 0;
     int st;
     if constexpr (sizeof(T) == 2)
         st = vec ? launch_layout<T, EPI, true>(layout, grid, s, M, N, K, a, lda, b, ldb, kchunk, ep)
