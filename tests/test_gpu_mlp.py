@@ -236,6 +236,15 @@ def test_sum_rows_in_order(torch, R, N, pad):
     assert np.array_equal(out.cpu().numpy(), ref)
 
 
+def test_time_steps_mode(torch):
+    """The step-timing mode of the warm-start CLI runs the fused step on a
+    small network and reports its time."""
+    from paper_1908_00741_amd import warmstart
+    r = warmstart.time_steps(16, 3, batch=64)
+    assert r["network"] == "12-256-256-4096" and r["batch"] == 64 and r["steps"] == 3
+    assert r["ms_per_step"] > 0.0
+
+
 def test_adam_step(torch):
     from oracle import mlp as omlp
     rng = np.random.default_rng(5)
