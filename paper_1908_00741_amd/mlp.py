@@ -212,13 +212,14 @@ class MLP:
         return B["loss"]
 
     def adam_step(self, opt: Adam, stream=None):
-        self.step_no += 1
+        step = self.step_no + 1   # counted once the call is accepted
         k = len(self.master)
         arr = lambda ts: (C.c_void_p * k)(*[t.data_ptr() for t in ts])
         sizes = (C.c_int64 * k)(*[t.numel() for t in self.master])
         _ck("mlp_adam_step", lib().mlp_adam_step(self.dtype, k, sizes, arr(self.master), arr(self.m), arr(self.v),
                                                  arr(self.grad), arr(self.comp), opt.lr, opt.beta1, opt.beta2,
-                                                 opt.eps, self.step_no, _s(stream)))
+                                                 opt.eps, step, _s(stream)))
+        self.step_no = step
 
     def train_step(self, theta, target, opt: Adam, stream=None):
         """loss_and_grads then adam_step in one call, with the output layer's
@@ -227,13 +228,14 @@ class MLP:
         M = theta.shape[0]
         B = self.load_input(theta, stream)
         n_in, h, _, n = self.dims
-        self.step_no += 1
+        step = self.step_no + 1   # counted once the call is accepted
         arr = lambda ts: (C.c_void_p * 6)(*[t.data_ptr() for t in ts])
         _ck("mlp_train_step", lib().mlp_train_step(self.dtype, M, n_in, h, n, _p(B["x"]), _p(target),
                                                    arr(self.master), arr(self.m), arr(self.v), arr(self.grad),
                                                    arr(self.comp), opt.lr, opt.beta1, opt.beta2, opt.eps,
-                                                   self.step_no, _p(B["loss"]), _p(B["work"]), B["work"].numel(),
+                                                   step, _p(B["loss"]), _p(B["work"]), B["work"].numel(),
                                                    _s(stream)))
+        self.step_no = step
         return B["loss"]
 
     def state(self):
