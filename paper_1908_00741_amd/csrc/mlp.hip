@@ -838,13 +838,13 @@ struct NetWork {   // workspace carve-up for a batch of M rows
     void *h1, *h2, *dY, *dz;
     float *loss, *dbias, *part, *dh, *dzf;
     int64_t nloss, nrows;
-    int split;
+    int split;    // K split of dY W3^T
+    int xsplit;   // K split of x^T dz1 (K = batch)
 };
 
 size_t elem_size(int dtype) { return dtype == MLP_BF16 ? 2 : 4; }
 
 size_t net_layout(int dtype, int M, int n_in, int hid, int n_out, NetWork *w, void *base) {
-    (void)n_in;
     auto up = [](size_t b) { return (b + 255) & ~size_t(255); };
     const int64_t nloss = int64_t((M + BM - 1) / BM) * ((n_out + BN - 1) / BN);
     const int64_t nrows = (M + BM - 1) / BM;
@@ -853,10 +853,14 @@ size_t net_layout(int dtype, int M, int n_in, int hid, int n_out, NetWork *w, vo
     // partial products to write and add up
     const int tiles = ((M + BM - 1) / BM) * ((hid + BN - 1) / BN);
     const int split = std::max(1, std::min((1024 + tiles - 1) / tiles, n_out / 4096));
+    // x^T dz1 has few output tiles (n_in rows): one K slice per split, at
+    // most four; its partials share the buffer of dY W3^T's
+    const int xsplit = std::max(1, std::min(4, M / KT));
+    const size_t part = std::max(size_t(split) * M * hid, xsplit > 1 ? size_t(xsplit) * n_in * hid : size_t(0));
     const size_t es = elem_size(dtype);
     const size_t sz[9] = {up(size_t(M) * hid * es), up(size_t(M) * hid * es), up(size_t(M) * n_out * es),
                           up(size_t(M) * hid * es), up(size_t(nloss) * 4), up(size_t(nrows) * n_out * 4),
-                          up(size_t(split) * M * hid * 4), up(size_t(M) * hid * 4), up(size_t(M) * hid * 4)};
+                          up(part * 4), up(size_t(M) * hid * 4), up(size_t(M) * hid * 4)};
     size_t total = 0;
     for (size_t v : sz) total += v;
     if (w && base) {
@@ -869,6 +873,7 @@ size_t net_layout(int dtype, int M, int n_in, int hid, int n_out, NetWork *w, vo
         w->nloss = nloss;
         w->nrows = nrows;
         w->split = split;
+        w->xsplit = xsplit;
     }
     return total;
 }
@@ -963,7 +968,12 @@ int backward_impl(int dtype, int M, int n_in, int h, int n, const void *X, const
     MLP_TRY(mlp_gemm(dtype, MLP_NT, M, h, h, w.dz, h, W[1], h, w.dh, h, 1, stream));           // dz2 W2^T
     MLP_TRY(mlp_relu_bwd(dtype, int64_t(M) * h, w.dh, w.h1, w.dz, w.dzf, stream));
     MLP_TRY(mlp_sum_rows(M, h, w.dzf, h, grad[1], stream));                                    // db1
-    MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, grad[0], h, 1, stream));     // x^T dz1
+    if (w.xsplit > 1) {                                                                         // x^T dz1
+        MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, w.part, h, w.xsplit, stream));
+        MLP_TRY(mlp_sum_rows(w.xsplit, int64_t(n_in) * h, w.part, int64_t(n_in) * h, grad[0], stream));
+    } else {
+        MLP_TRY(mlp_gemm(dtype, MLP_TN, n_in, h, M, X, n_in, w.dz, h, grad[0], h, 1, stream));
+    }
     return HBMC_OK;
 }
 
