@@ -116,6 +116,26 @@ def test_order_bit_exact_full_size_grids(orc, N, sigma, seed):
     assert np.array_equal(perm, ref.perm) and np.array_equal(cs, ref.color_start)
 
 
+def test_order_bit_exact_full_size_knn(orc):
+    """The 1M-point 13-NN Laplacian in its timed configuration (bs 2, w 32):
+    ordering bit-exact, and the factor (IC(0) with off-diagonal updates on
+    this graph) against the oracle's."""
+    A = inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3)
+    o = hbmc.hbmc_order(A, 2, 32)
+    ref = orc.order(A, 2, 32)
+    perm, cs = o.perm()
+    assert o.n_colors == ref.ncolors and o.n_pad == ref.n_pad
+    assert np.array_equal(perm, ref.perm) and np.array_equal(cs, ref.color_start)
+    d, rp, ci, v = hbmc.ic0_factor(o, A).export()
+    Ab = orc.permute(A, ref.perm, ref.n_pad)
+    dref, fac = orc.ic0(Ab)
+    Lref = sp.tril(sp.csr_matrix((fac, Ab.col, Ab.rowptr), shape=(Ab.n, Ab.n)), k=-1).tocsr()
+    Lref.sort_indices()
+    assert np.array_equal(rp, Lref.indptr) and np.array_equal(ci, Lref.indices)
+    assert np.allclose(v, Lref.data, rtol=1e-14, atol=0)
+    assert np.allclose(d, dref, rtol=1e-14, atol=0)
+
+
 @pytest.mark.parametrize("name,make,bs,w", CASES[:8], ids=[c[0] for c in CASES[:8]])
 def test_factor_matches_oracle(orc, name, make, bs, w):
     A = make()

@@ -279,3 +279,113 @@ def test_fp32_preconditioner_converges(orc):
     assert abs(r32.iters - r64.iters) <= 2
     true = np.linalg.norm(b - A.to_scipy() @ r32.x) / np.linalg.norm(b)
     assert true < 2e-7
+
+
+# ---------------------------------------------------------------------------
+# The FP32 preconditioner of the oracle (orc_apply_f32): the factor rounded
+# to binary32 and every operation of both substitutions carried out in
+# binary32.  Three pins that an FP64 substitution (or one that rounds only
+# its result) fails.
+# ---------------------------------------------------------------------------
+def test_apply_f32_worked_example(orc):
+    """A = [[2, -1], [-1, 2]] (bs = w = 1 keeps the numbering), r = [-1, 1].
+    IC(0) is exact here: d = (2, 3/2), L_10 = -1.  In binary32, with
+    1/d rounded to binary32 (fl(2/3) = 11184811 * 2^-24):
+      y0 = -1 * 0.5                               = -0.5
+      y1 = (1 - (-1)(-0.5)) * fl(2/3) = 0.5 * 11184811 * 2^-24
+                                                  = 11184811 * 2^-25 (exact)
+      z1 = y1
+      z0 = y0 - 0.5 * (-1 * z1) = -0.5 + 11184811 * 2^-26
+         = -22369621 * 2^-26, a tie between two binary32 neighbours,
+           rounded to the even one               = -11184810 * 2^-25.
+    The exact result is (-1/3, 1/3); rounding -1/3 once gives
+    -11184811 * 2^-25, so only per-operation binary32 arithmetic gives z0."""
+    A = inputs.path_1d(2)
+    s = orc.system(A, 1, 1)
+    assert np.array_equal(s.ordr.perm, [0, 1])
+    z = orc.apply(s.Ab, s.d, s.fac, np.array([-1.0, 1.0]), precision="f32")
+    assert z[0] == -11184810 * 2.0 ** -25
+    assert z[1] == 11184811 * 2.0 ** -25
+    z64 = orc.apply(s.Ab, s.d, s.fac, np.array([-1.0, 1.0]))
+    assert np.allclose(z64, [-1.0 / 3.0, 1.0 / 3.0], rtol=1e-15, atol=0)
+
+
+@pytest.mark.parametrize("name,make,bs,w", CASES, ids=[c[0] for c in CASES])
+def test_apply_f32_outputs_are_binary32(orc, name, make, bs, w):
+    """Every entry of the FP32 preconditioned vector is a binary32 number, it
+    is not the FP64 result, and it lies within a binary32 rounding bound of
+    the FP64 result: per unknown, the substitutions' error is at most about
+    (chain length + couplings) binary32 roundings of the magnitudes involved
+    (|r| + sum |L| |y| through the chain), bounded here by 1e-4 relative."""
+    s = orc.system(make(), bs, w)
+    r = np.random.default_rng(4).standard_normal(s.Ab.n)
+    z32 = orc.apply(s.Ab, s.d, s.fac, r, precision="f32")
+    z64 = orc.apply(s.Ab, s.d, s.fac, r)
+    assert np.array_equal(z32.astype(np.float32).astype(np.float64), z32)
+    assert not np.array_equal(z32, z64)
+    assert np.abs(z32 - z64).max() <= 1e-4 * np.abs(z64).max()
+    assert np.abs(z32 - z64).max() >= 1e-9 * np.abs(z64).max()
+
+
+def _round_binary(x, bits):
+    """x (a Fraction) rounded to the nearest number with a `bits`-bit
+    significand, ties to even (IEEE 754 round-to-nearest-even; normal range
+    only)."""
+    from fractions import Fraction
+    if x == 0:
+        return Fraction(0)
+    sign = -1 if x < 0 else 1
+    m = abs(x)
+    e = m.numerator.bit_length() - m.denominator.bit_length()
+    if Fraction(2) ** e > m:
+        e -= 1                                     # now 2^e <= m < 2^(e+1)
+    assert e >= -126, "subnormal range not emulated"
+    q = m * Fraction(2) ** (bits - 1 - e)          # in [2^(bits-1), 2^bits)
+    fl = q.numerator // q.denominator
+    rem = q - fl
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and fl % 2 == 1):
+        fl += 1
+    return sign * fl * Fraction(2) ** (e - (bits - 1))
+
+
+def test_apply_f32_matches_exact_binary32_emulation(orc):
+    """The FP32 substitutions against exact rational arithmetic with an
+    explicit binary32 round-to-nearest-even after every operation (and
+    binary64 rounding where the oracle's header says the value is formed in
+    FP64: 1/d before its conversion to binary32).  Forward, i ascending:
+    s = r_i; s = s - L_ij y_j over the row's lower entries in column order;
+    y_i = s * (1/d_i).  Backward, i descending: s = sum of L_ji z_j over
+    j > i in column order; z_i = y_i - (1/d_i) s.  Bit-identical results."""
+    from fractions import Fraction
+    A = inputs.random_spd(36, 0.12, 21)
+    s = orc.system(A, 3, 4)
+    Ab = s.Ab
+    r = np.random.default_rng(8).uniform(-1, 1, Ab.n)
+    z = orc.apply(Ab, s.d, s.fac, r, precision="f32")
+
+    def f32(x):
+        return _round_binary(x, 24)
+
+    def f64(x):
+        return _round_binary(x, 53)
+
+    n = Ab.n
+    dinv = [f32(f64(1 / Fraction(float(s.d[i])))) for i in range(n)]
+    pos = {(i, int(Ab.col[p])): p for i in range(n) for p in range(Ab.rowptr[i], Ab.rowptr[i + 1])}
+    y = [Fraction(0)] * n
+    for i in range(n):
+        acc = f32(Fraction(float(r[i])))
+        for p in range(Ab.rowptr[i], Ab.rowptr[i + 1]):
+            j = int(Ab.col[p])
+            if j < i:
+                acc = f32(acc - f32(f32(Fraction(float(s.fac[p]))) * y[j]))
+        y[i] = f32(acc * dinv[i])
+    zz = [Fraction(0)] * n
+    for i in range(n - 1, -1, -1):
+        acc = Fraction(0)
+        for p in range(Ab.rowptr[i], Ab.rowptr[i + 1]):
+            j = int(Ab.col[p])
+            if j > i:
+                acc = f32(acc + f32(f32(Fraction(float(s.fac[pos[(j, i)]]))) * zz[j]))
+        zz[i] = f32(y[i] - f32(dinv[i] * acc))
+    assert [float(v) for v in zz] == list(z)
