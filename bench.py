@@ -81,6 +81,8 @@ def main() -> int:
                     help="comma-separated extension comparisons to run after the headline "
                          "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother, refactor); empty for none")
     ap.add_argument("--N", type=int, default=128)
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the ic0_apply timings of the 1M-point kNN and 96^3 workloads")
     ap.add_argument("--calibrate", action="store_true",
                     help="first run dst = 2 * src on 256 MiB tensors, a kernel that reads "
                          "and writes exactly 256 MiB, for scaling hardware byte counters")
@@ -169,6 +171,40 @@ def main() -> int:
     log(f"[bench] 128 MB copy: {copy_gbs['cold']:.0f} GB/s cold, {copy_gbs['dirty']:.0f} GB/s after a "
         f"write-only flush")
 
+    # ---- ic0_apply on the other workloads (same cold method) ---------------
+    apply_cfg = {}
+    if not args.no_configs:
+        for name, make, cbs, cw, prec in (
+                ("knn1m_bs2_w32_f64", lambda: inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3), 2, 32,
+                 hbmc.HBMC_F64),
+                ("knn1m_bs2_w32_f32", None, 2, 32, hbmc.HBMC_F32),
+                ("diffusion96_bs8_w64_f64", lambda: inputs.diffusion3d(96, 0.5, 10), 8, 64, hbmc.HBMC_F64)):
+            if make is not None:
+                Ac = make()
+                oc = hbmc.hbmc_order(Ac, cbs, cw)
+            fc = hbmc.ic0_factor(oc, Ac, prec).upload(dev)
+            pc, _ = oc.perm()
+            rc_np = np.zeros(fc.n_pad)
+            rc_np[pc] = np.random.default_rng(17).uniform(-1, 1, Ac.n)
+            rc = torch.from_numpy(rc_np).to(dev)
+            zc = torch.empty_like(rc)
+            for _ in range(5):
+                hbmc.ic0_apply(fc, rc, zc)
+            tc = timed(args.apply_reps, "cold", lambda: hbmc.ic0_apply(fc, rc, zc))
+            nlc = (Ac.nnz - Ac.n) // 2
+            sv = 8 if prec == hbmc.HBMC_F64 else 4
+            Bc = apply_bytes(fc.n_pad, nlc, sv, sv, sv)
+            gc = Bc / (np.median(tc) * 1e-3) / 1e9
+            apply_cfg[name] = {"median_us_cold": round(float(np.median(tc)) * 1e3, 2), "bytes_per_apply": Bc,
+                               "gbs": round(gc, 1), "frac": round(gc / HBM_PEAK_GBS, 4),
+                               "n": Ac.n, "n_pad": fc.n_pad, "nnz_lower": nlc, "n_colors": fc.n_colors,
+                               "phases": 2 * fc.n_colors - 1}
+            log(f"[bench] apply {name}: {np.median(tc) * 1e3:.1f} us cold, {gc:.0f} GB/s algorithmic "
+                f"({gc / HBM_PEAK_GBS:.3f} of peak), {fc.n_colors} colors")
+            del fc, rc, zc
+        del Ac, oc
+        torch.cuda.empty_cache()
+
     # ---- ICCG steps --------------------------------------------------------
     b = torch.from_numpy(b_np).to(dev)
     x = torch.zeros_like(b)
@@ -184,6 +220,12 @@ def main() -> int:
     torch.cuda.synchronize()
     ms_per_step = (time.perf_counter() - t0) * 1e3 / max(args.steps, 1)
     log(f"[bench] ICCG {ms_per_step:.2f} ms per solve, {st.iters} iterations")
+    x64 = x.cpu().numpy()
+    # the same solve with the FP32 preconditioner (compared with the oracle below)
+    f32 = hbmc.ic0_factor(solver.order, A, hbmc.HBMC_F32).upload(dev)
+    x32, st32 = hbmc.Solver(solver.order, f32, solver.matrix).solve(b, tol=1e-7)
+    x32 = x32.cpu().numpy()
+    del f32
 
     # ---- extensions: speedups over plain FP64 single-RHS ICCG ---------------
     ext = {}
@@ -232,14 +274,21 @@ def main() -> int:
         t1 = time.perf_counter()
         res = oracle.pcg(ref.Ab, ref.d, ref.fac, bb, tol=1e-7, maxit=10000)
         t_sol = time.perf_counter() - t1
+        xo = res.x[perm]
+        err64 = float(np.linalg.norm(x64 - xo) / np.linalg.norm(xo))
+        err32 = float(np.linalg.norm(x32 - xo) / np.linalg.norm(xo))
+        log(f"[bench] against the oracle's FP64 solution: FP64 {err64:.2e}, FP32 preconditioner {err32:.2e}")
         cpu = {"value": round(B * reps / tcpu / 1e9, 4), "unit": "GB/s", "cores": 1,
                "kind": "oracle",
                "sample": f"{reps} sequential FP64 ic0_apply calls on the same 128^3 workload "
                          f"({tcpu:.1f} s); oracle PCG to 1e-7: {res.iters} iterations in {t_sol:.1f} s "
                          f"({t_sol * 1e3 / max(res.iters, 1):.0f} ms/iteration)",
                "time_to_solution_s": round(t_sol, 2), "iterations": res.iters,
-               "host_cpu_count": os.cpu_count()}
+               "host_cpu_count": os.cpu_count(),
+               "gpu_f64_rel_err_vs_oracle": err64, "gpu_f32_precond_rel_err_vs_oracle": err32,
+               "gpu_f32_precond_iterations": st32.iters, "gpu_f32_precond_true_rel_res": st32.true_rel_res}
 
+    traffic = measured_traffic()
     out = {
         "metric": METRIC, "value": round(gbs_cold, 2), "unit": "GB/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
@@ -251,7 +300,13 @@ def main() -> int:
                    "n_colors": f.n_colors, "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": round(gbs_cold, 2), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(gbs_cold / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(),
+                     "traffic": traffic,
+                     "basis": "achieved and frac use the algorithmic bytes of one apply (factor values and "
+                              "int32 indices read once, diaginv twice, r in, z out, y out and back); "
+                              "measured_* use the HBM bytes the counters report",
+                     "measured_gbs": None if traffic is None else round(traffic / (np.median(t_cold) * 1e-3) / 1e9, 1),
+                     "measured_frac": None if traffic is None else
+                     round(traffic / (np.median(t_cold) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
                      "kernel": "ic0_apply (2*n_colors-1 phase launches)",
                      "bytes_per_launch": B,
                      "cold_copy_gbs": round(copy_gbs["cold"], 1),
@@ -263,6 +318,7 @@ def main() -> int:
         "iccg": {"ms_to_1e-7": round(ms_per_step, 3), "iterations": st.iters,
                  "true_rel_res": st.true_rel_res, "ms_per_iteration": round(ms_per_step / max(st.iters, 1), 4),
                  "setup_s": round(setup_s, 2)},
+        "apply_configs": apply_cfg,
         "cpu_baseline": cpu,
         "extensions": ext,
     }

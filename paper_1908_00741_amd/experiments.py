@@ -8,7 +8,8 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
 - batch: 128 Poisson systems of uneven size (16^3 .. 64^3) solved together
   (one set of launches per iteration, per-system stopping tests, FP32
   preconditioner, autotuned bs, w and kernel) against solving them one by
-  one in FP64;
+  one in FP64, and the same batch with the FP64 preconditioner (batching
+  alone, without the precision change);
 - rhs: 32 right-hand sides of the 128^3 lognormal diffusion problem solved
   together (factor read once per apply for all of them, autotuned
   right-hand-side tile, FP32 preconditioner) against 32 FP64 solves;
@@ -137,6 +138,12 @@ def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, tune=Tr
     res["batched_f32"] = {"ms": round(t * 1e3, 3), "bs": bs, "w": w, "kernel": kernel, **_stats(st)}
     log(f"[ext batch] batched FP32 (bs={bs} w={w} kernel={kernel}): {t * 1e3:.2f} ms")
     del sv
+    # the same batch and knobs with the FP64 preconditioner: batching alone
+    sv = hbmc.Solver.setup(A, bs, w, hbmc.HBMC_F64, device=device, sys_ptr=sys_ptr, kernel=kernel)
+    t64, (x, st) = _timed(lambda: sv.solve(bb, tol=tol))
+    res["batched_f64"] = {"ms": round(t64 * 1e3, 3), "bs": bs, "w": w, "kernel": kernel, **_stats(st)}
+    log(f"[ext batch] batched FP64 (bs={bs} w={w} kernel={kernel}): {t64 * 1e3:.2f} ms")
+    del sv
     bs, w = 8, 64
     total, its, worst, conv = 0.0, [], 0.0, True
     for s, M in enumerate(mats):
@@ -150,7 +157,10 @@ def batch(device, count=128, lo=16, hi=64, seed=7, bs=8, w=64, tol=1e-7, tune=Tr
     res["one_by_one_f64"] = {"ms": round(total * 1e3, 3), "iters_max": max(its), "iters_min": min(its),
                              "true_rel_res_max": worst, "all_converged": conv}
     res["speedup"] = round(total / t, 3)
-    log(f"[ext batch] one by one FP64: {total * 1e3:.2f} ms, speedup {total / t:.2f}")
+    res["speedup_batching_alone_f64"] = round(total / t64, 3)
+    res["speedup_f32_over_f64_batched"] = round(t64 / t, 3)
+    log(f"[ext batch] one by one FP64: {total * 1e3:.2f} ms, speedup {total / t:.2f} "
+        f"(batching alone, FP64: {total / t64:.2f}; FP32 over FP64 batched: {t64 / t:.2f})")
     return res
 
 

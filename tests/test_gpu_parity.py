@@ -8,7 +8,25 @@ Bars (stated per test):
   over chains of at most bs steps per color and a few colors;
 - hbmc_spmv: 1e-14 relative, entry-wise;
 - iccg_solve FP64 at a fixed iteration count K: ||x - x_ref|| / ||x_ref||
-  <= 1e-10, and converged runs take the oracle's iteration count +-1.
+  <= 1e-10 for K <= 30, and converged runs take the oracle's iteration count
+  +-1;
+- iccg_solve at K up to the oracle's own count to 1e-7 (its full run):
+  two CG runs that differ only in rounding (summation order, contraction)
+  follow each other to ~1e-15 early on, but near convergence the unresolved
+  eigencomponents amplify the difference, and by how much swings by orders
+  of magnitude from one K to the next (measured with the oracle against
+  itself under the BMC and HBMC orderings, which are equivalent in exact
+  arithmetic, Section 3: 64^3 diffusion 3.6e-15 at K = 61, 2.3e-9 at
+  K = 113, 2.8e-12 at K = 123).  What stays small is the difference
+  relative to the iterate's own error: ||x_a(K) - x_b(K)|| <= 3.3e-3
+  ||x_a(K) - x*|| over every K measured (FP64; x* from an oracle solve to
+  1e-15).  The bar at half and at the full count is therefore
+  ||x - x_ref|| <= 1e-2 ||x_ref - x*|| (FP64) and 0.5 ||x_ref - x*|| (FP32
+  preconditioner, where the same measurement reaches 6e-2), and each
+  ||x - x_ref|| / ||x_ref|| is printed as a function of K;
+- FP32 preconditioner against the oracle's FP32 PCG: 1e-6 relative for
+  K <= 30 (an FP32 rounding of the preconditioned vector per iteration;
+  the oracle's two orderings differ by ~1e-8 there).
 """
 import json
 import os
@@ -169,22 +187,129 @@ def test_solve_converges_like_oracle(torch, orc, name, make, bs, w):
     assert np.linalg.norm(xh - ref.x) <= 1e-6 * np.linalg.norm(ref.x)
 
 
+def _iterate_parity(torch, s, solver, b, precision, ks, label):
+    """GPU and oracle iterates at fixed iteration counts ks (the last being
+    the oracle's full count to 1e-7), with the bars of the module docstring;
+    prints ||x - x_ref|| / ||x_ref|| per K.  Returns the oracle's x*."""
+    prec = "f64" if precision == hbmc.HBMC_F64 else "f32"
+    xstar = s.solve(b, tol=1e-14, maxit=20000).x
+    bd = _dev(torch, b)
+    rows = []
+    for K in ks:
+        ref = s.solve(b, tol=0.0, maxit=K, precision=prec)
+        x, st = solver.solve(bd, tol=0.0, maxit=K)
+        assert st.iters == K
+        x = _host(x)
+        d = np.linalg.norm(x - ref.x)
+        e = np.linalg.norm(ref.x - xstar)
+        rows.append((K, d / np.linalg.norm(ref.x), d / e))
+        print(f"{label} {prec} K={K}: |x-x_ref|/|x_ref| = {d / np.linalg.norm(ref.x):.3e}, "
+              f"|x-x_ref|/|x_ref-x*| = {d / e:.3e}", flush=True)
+    for K, rel, frac in rows:
+        if K <= 30:
+            assert rel <= (1e-10 if prec == "f64" else 1e-6), (label, K, rel)
+        else:
+            assert frac <= (1e-2 if prec == "f64" else 0.5), (label, K, frac)
+    return xstar
+
+
 def test_solve_full_size_128(torch, orc):
-    """128^3, bs=8, w=64: fixed-K parity against the oracle, and the converged
-    iteration count against the oracle's (stored by tests/golden/make_iters.py)."""
+    """128^3, bs=8, w=64 (the benchmark's solve): iterates at K = 10, the
+    oracle's half count and its full count against the oracle; the converged
+    iteration count against the oracle's."""
     print("case solve_full_128", flush=True)
     A = inputs.diffusion3d(128, 1.0, 2)
     b = inputs.uniform_rhs(A.n, 3)
     s = orc.system(A, 8, 64)
     solver = hbmc.Solver.setup(A, 8, 64)
-    K = 10
-    ref = s.solve(b, tol=0.0, maxit=K)
-    x, st = solver.solve(_dev(torch, b), tol=0.0, maxit=K)
-    assert np.linalg.norm(_host(x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
     golden = json.load(open(os.path.join(GOLDEN, "iterations.json")))["diffusion128_s1_bs8_w64"]
+    K = golden["iters"]
+    _iterate_parity(torch, s, solver, b, hbmc.HBMC_F64, [10, K // 2, K], "diffusion128")
     x, st = solver.solve(_dev(torch, b), tol=1e-7)
-    assert st.status == hbmc.HBMC_OK and abs(st.iters - golden["iters"]) <= 1
+    assert st.status == hbmc.HBMC_OK and abs(st.iters - K) <= 1
     assert st.true_rel_res < 1.5e-7
+
+
+def test_solve_full_count_c1(torch, orc):
+    """64x64 5-point Laplacian, bs 4, w 8, b = A 1: the oracle's full count."""
+    print("case solve_full_c1", flush=True)
+    A = inputs.grid2d_5pt(64)
+    b = inputs.row_sums(A)
+    s = orc.system(A, 4, 8)
+    K = s.solve(b, tol=1e-7).iters
+    solver = hbmc.Solver.setup(A, 4, 8)
+    _iterate_parity(torch, s, solver, b, hbmc.HBMC_F64, [10, 30, K // 2, K], "c1")
+    ref = s.solve(b, tol=0.0, maxit=K)
+    x, _ = solver.solve(_dev(torch, b), tol=0.0, maxit=K)
+    # well-conditioned: the tight bar holds through the whole run
+    assert np.linalg.norm(_host(x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+
+
+@pytest.fixture(scope="module")
+def knn100k(orc):
+    """The timed unstructured configuration at a size the oracle solves in
+    seconds: 13-NN Laplacian of 100,000 points, shift 1e-3, bs 2, w 32."""
+    A = inputs.knn_laplacian(100_000, 13, 4, 5, shift=1e-3)
+    b = inputs.uniform_rhs(A.n, 6)
+    return A, b, orc.system(A, 2, 32)
+
+
+@pytest.mark.parametrize("kernel", KERNELS, ids=KIDS)
+@pytest.mark.parametrize("precision", [hbmc.HBMC_F64, hbmc.HBMC_F32], ids=["f64", "f32"])
+def test_solve_full_count_knn(torch, orc, knn100k, precision, kernel):
+    """100k-point kNN, bs 2, w 32, FP64 and FP32 preconditioner, both
+    substitution kernels (the automatic choice is the row kernel here and at
+    1M points: fewer than 1024 tiles of 64 lanes per color): iterates up to
+    the oracle's full count, the converged count (FP64 +-1, FP32 +-2 against
+    the oracle's FP32 PCG), the true residual, and the error of the
+    converged solution against the oracle's FP64 solution (printed)."""
+    A, b, s = knn100k
+    prec = "f64" if precision == hbmc.HBMC_F64 else "f32"
+    print(f"case knn100k {prec} kernel {kernel}", flush=True)
+    o = hbmc.hbmc_order(A, 2, 32)
+    assert o.n_pad // (2 * 64) < 1024 * o.n_colors     # automatic rule -> rows kernel
+    f = hbmc.ic0_factor(o, A, precision).set_kernel(kernel).upload()
+    solver = hbmc.Solver(o, f, hbmc.hbmc_matrix_create(o, A).upload())
+    conv = s.solve(b, tol=1e-7, precision=prec)
+    K = conv.iters
+    xstar = _iterate_parity(torch, s, solver, b, precision, [10, 30, K // 2, K], "knn100k")
+    x, st = solver.solve(_dev(torch, b), tol=1e-7)
+    assert st.status == hbmc.HBMC_OK
+    assert abs(st.iters - K) <= (1 if prec == "f64" else 2), (st.iters, K)
+    assert st.true_rel_res < 1.5e-7
+    xh = _host(x)
+    x64 = s.solve(b, tol=1e-7).x
+    print(f"knn100k {prec} converged: {st.iters} its (oracle {K}), true residual {st.true_rel_res:.2e}, "
+          f"|x-x_oracle64|/|x_oracle64| = {np.linalg.norm(xh - x64) / np.linalg.norm(x64):.3e}, "
+          f"|x-x*|/|x*| = {np.linalg.norm(xh - xstar) / np.linalg.norm(xstar):.3e}", flush=True)
+
+
+@pytest.fixture(scope="module")
+def knn1m(orc):
+    A = inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3)
+    return A, orc.system(A, 2, 32)
+
+
+@pytest.mark.parametrize("precision", [hbmc.HBMC_F64, hbmc.HBMC_F32], ids=["f64", "f32"])
+def test_apply_full_size_knn(torch, orc, knn1m, precision):
+    """The 1M-point 13-NN Laplacian in the timed configuration (bs 2, w 32,
+    automatic kernel choice: rows), FP64 and FP32, against the oracle."""
+    A, s = knn1m
+    print(f"case apply_knn1m precision {precision}", flush=True)
+    o = hbmc.hbmc_order(A, 2, 32)
+    f = hbmc.ic0_factor(o, A, precision).upload()
+    r = np.random.default_rng(42).uniform(-1, 1, s.ordr.n_pad)
+    dummy = np.setdiff1d(np.arange(s.ordr.n_pad), s.ordr.perm)
+    r[dummy] = 0.0
+    z = _host(hbmc.ic0_apply(f, _dev(torch, r)))
+    if precision == hbmc.HBMC_F64:
+        zref = orc.apply(s.Ab, s.d, s.fac, r)
+        assert np.linalg.norm(z - zref) <= 1e-13 * np.linalg.norm(zref)
+        assert np.abs(z - zref).max() <= 1e-12 * np.abs(zref).max()
+    else:
+        zref = orc.apply(s.Ab, s.d, s.fac, r, "f32")
+        assert np.abs(z - zref).max() <= 1e-5 * np.abs(zref).max()
+    assert np.all(z[dummy] == 0.0)
 
 
 def test_solve_zero_rhs(torch):
