@@ -36,13 +36,6 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def apply_bytes(n: int, nnz_lower: int, s_v: int = 8, s_d: int = 8, s_y: int = 8) -> int:
-    """Algorithmic bytes of one ic0_apply: L and U values + int32 indices read
-    once, diaginv for the forward and backward sweeps, r read, z written, and
-    the intermediate y written and read back."""
-    return 2 * nnz_lower * (s_v + 4) + 2 * n * s_d + n * 8 + n * 8 + 2 * n * s_y
-
-
 PROFILE = os.path.join(ROOT, "profiles", "ic0_apply_diffusion128.md")
 PROFILED_SOURCES = ["paper_1908_00741_amd/csrc/sweep.h",
                     "paper_1908_00741_amd/csrc/sweep_bs8.hip",
@@ -116,42 +109,25 @@ def main() -> int:
     setup_s = time.perf_counter() - t0
     f = solver.factor
     nnz_lower = (A.nnz - A.n) // 2
+    from paper_1908_00741_amd.experiments import apply_bytes
     B = apply_bytes(f.n_pad, nnz_lower)
     log(f"[bench] setup {setup_s:.2f} s, n_pad {f.n_pad}, colors {f.n_colors}, "
         f"apply bytes {B / 1e6:.1f} MB")
 
     # ---- ic0_apply timing ------------------------------------------------
-    stream = torch.cuda.current_stream()
+    from paper_1908_00741_amd import experiments
     perm, _ = solver.order.perm()
     r_np = np.zeros(f.n_pad)
     r_np[perm] = np.random.default_rng(17).uniform(-1, 1, A.n)
     r = torch.from_numpy(r_np).to(dev)
     z = torch.empty_like(r)
-    flush = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-    flush2 = torch.zeros(1 << 27, dtype=torch.float64, device=dev)      # 1 GiB, read
-    sink = torch.empty((), dtype=torch.float64, device=dev)
     for _ in range(5):
         hbmc.ic0_apply(f, r, z)
     torch.cuda.synchronize()
-
-    def evict(i, clean):
-        flush.fill_(i & 255)
-        if clean:
-            torch.sum(flush2, dim=0, out=sink)
+    timer = experiments.ColdTimer(dev)
 
     def timed(reps, mode, fn=lambda: hbmc.ic0_apply(f, r, z)):
-        ts = []
-        for i in range(reps):
-            if mode != "warm":
-                evict(i, mode == "cold")
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
-            e0.record(stream)
-            fn()
-            e1.record(stream)
-            e1.synchronize()
-            ts.append(e0.elapsed_time(e1))
-        return np.array(ts)
+        return timer.times_ms(fn, reps, mode)
 
     t_cold = timed(args.apply_reps, "cold")
     t_dirty = timed(args.apply_reps, "dirty")
@@ -174,35 +150,16 @@ def main() -> int:
     # ---- ic0_apply on the other workloads (same cold method) ---------------
     apply_cfg = {}
     if not args.no_configs:
-        for name, make, cbs, cw, prec in (
-                ("knn1m_bs2_w32_f64", lambda: inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3), 2, 32,
-                 hbmc.HBMC_F64),
-                ("knn1m_bs2_w32_f32", None, 2, 32, hbmc.HBMC_F32),
-                ("diffusion96_bs8_w64_f64", lambda: inputs.diffusion3d(96, 0.5, 10), 8, 64, hbmc.HBMC_F64)):
-            if make is not None:
-                Ac = make()
-                oc = hbmc.hbmc_order(Ac, cbs, cw)
-            fc = hbmc.ic0_factor(oc, Ac, prec).upload(dev)
-            pc, _ = oc.perm()
-            rc_np = np.zeros(fc.n_pad)
-            rc_np[pc] = np.random.default_rng(17).uniform(-1, 1, Ac.n)
-            rc = torch.from_numpy(rc_np).to(dev)
-            zc = torch.empty_like(rc)
-            for _ in range(5):
-                hbmc.ic0_apply(fc, rc, zc)
-            tc = timed(args.apply_reps, "cold", lambda: hbmc.ic0_apply(fc, rc, zc))
-            nlc = (Ac.nnz - Ac.n) // 2
-            sv = 8 if prec == hbmc.HBMC_F64 else 4
-            Bc = apply_bytes(fc.n_pad, nlc, sv, sv, sv)
-            gc = Bc / (np.median(tc) * 1e-3) / 1e9
-            apply_cfg[name] = {"median_us_cold": round(float(np.median(tc)) * 1e3, 2), "bytes_per_apply": Bc,
-                               "gbs": round(gc, 1), "frac": round(gc / HBM_PEAK_GBS, 4),
-                               "n": Ac.n, "n_pad": fc.n_pad, "nnz_lower": nlc, "n_colors": fc.n_colors,
-                               "phases": 2 * fc.n_colors - 1}
-            log(f"[bench] apply {name}: {np.median(tc) * 1e3:.1f} us cold, {gc:.0f} GB/s algorithmic "
-                f"({gc / HBM_PEAK_GBS:.3f} of peak), {fc.n_colors} colors")
-            del fc, rc, zc
-        del Ac, oc
+        Ak = experiments.WORKLOADS["knn1m"]()
+        ok = hbmc.hbmc_order(Ak, 2, 32)
+        for name, Ac, oc, cbs, cw, prec in (
+                ("knn1m_bs2_w32_f64", Ak, ok, 2, 32, hbmc.HBMC_F64),
+                ("knn1m_bs2_w32_f32", Ak, ok, 2, 32, hbmc.HBMC_F32),
+                ("diffusion96_bs8_w64_f64", experiments.WORKLOADS["diffusion96"](), None, 8, 64, hbmc.HBMC_F64)):
+            apply_cfg[name] = experiments.apply_rate(dev, Ac, cbs, cw, prec, reps=args.apply_reps, timer=timer,
+                                                     order=oc, log=log, label=name)
+            torch.cuda.empty_cache()
+        del Ak, ok
         torch.cuda.empty_cache()
 
     # ---- ICCG steps --------------------------------------------------------
@@ -231,7 +188,6 @@ def main() -> int:
     ext = {}
     wanted = [e for e in args.ext.split(",") if e]
     if wanted:
-        from paper_1908_00741_amd import experiments
         for name in wanted:
             try:
                 if name == "graph":

@@ -546,12 +546,19 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
 // Which kernel runs the phases: one wavefront per tile (k_sweep) or one
 // workgroup of bs wavefronts per tile (k_rows, one right-hand side only).
 // Automatic choice: k_rows when the colors have few tiles on average (fewer
-// than 1024: a phase would not fill the chip with one wavefront per tile).
+// than 1024: a phase would not fill the chip with one wavefront per tile)
+// and most couplings sit in indexed slots (unstructured graphs: each step
+// has many couplings, whose loads k_rows spreads over bs wavefronts).  On
+// grids a step has a few strided slots, and k_rows' single chain wavefront
+// after the barrier costs more than it saves (96^3, bs 8: 75.7 against
+// 38.0 us per apply; 1M-point 13-NN graph, bs 2: 300 against 370 us).
 bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
     if (bs > 16 || K != 1 || nr != 1) return false;
     if (f->kernel == HBMC_KERNEL_SWEEP) return false;
     if (f->kernel == HBMC_KERNEL_ROWS) return true;
-    return f->tile_base[f->nc] < 1024 * int64_t(f->nc);
+    const int64_t strided = f->fext.strided() + f->bext.strided();
+    const int64_t indexed = f->fext.indexed() + f->bext.indexed();
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && indexed > strided;
 }
 
 template <int BS, typename T, int MI, bool CG, int NR>

@@ -24,7 +24,11 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
 - orderings: multi-color (bs = 1), block multi-color (w = 1: one block per
   lane, rows of a lane 1 apart) and hierarchical block multi-color ordering
   of the same problem, FP64: iterations, time and time per iteration (the
-  comparison of Section 5's tables, on one GPU).
+  comparison of Section 5's tables, on one GPU);
+- apply_rate: ic0_apply alone on a named workload, timed with HIP events
+  with the caches cold before each call (also the command line used for
+  per-workload profiles: ``python -m paper_1908_00741_amd.experiments
+  apply knn1m --bs 2 --w 32``).
 
 Setup (ordering, factorization, upload) is outside every timed region.
 """
@@ -61,6 +65,95 @@ def _stats(st):
     return {"iters_max": max(s.iters for s in sts), "iters_min": min(s.iters for s in sts),
             "true_rel_res_max": max(s.true_rel_res for s in sts),
             "all_converged": all(s.status == hbmc.HBMC_OK for s in sts)}
+
+
+HBM_PEAK_GBS = 8000.0
+
+
+def apply_bytes(n: int, nnz_lower: int, s_v: int = 8, s_d: int = 8, s_y: int = 8) -> int:
+    """Algorithmic bytes of one ic0_apply: L and U values + int32 indices read
+    once, diaginv for the forward and backward sweeps, r read, z written, and
+    the intermediate y written and read back."""
+    return 2 * nnz_lower * (s_v + 4) + 2 * n * s_d + n * 8 + n * 8 + 2 * n * s_y
+
+
+class ColdTimer:
+    """HIP-event timing of one call on the current stream, with the caches
+    put in a known state before each call: "cold" writes 1 GiB (evicting the
+    4 MB L2s and the 256 MB MALL) and then reads a different 1 GiB (so the
+    MALL holds clean lines and the timed call's misses pay no write-backs);
+    "dirty" only writes; "warm" runs back to back."""
+
+    def __init__(self, device):
+        import torch
+        self.torch = torch
+        self.flush = torch.empty(1 << 30, dtype=torch.uint8, device=device)
+        self.flush2 = torch.zeros(1 << 27, dtype=torch.float64, device=device)
+        self.sink = torch.empty((), dtype=torch.float64, device=device)
+
+    def evict(self, i, clean=True):
+        self.flush.fill_(i & 255)
+        if clean:
+            self.torch.sum(self.flush2, dim=0, out=self.sink)
+
+    def times_ms(self, fn, reps, mode="cold"):
+        torch = self.torch
+        stream = torch.cuda.current_stream()
+        ts = []
+        for i in range(reps):
+            if mode != "warm":
+                self.evict(i, mode == "cold")
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        return np.array(ts)
+
+
+WORKLOADS = {
+    "diffusion128": lambda: inputs.diffusion3d(128, 1.0, 2),
+    "diffusion96": lambda: inputs.diffusion3d(96, 0.5, 10),
+    "knn1m": lambda: inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3),
+}
+
+
+def apply_rate(device, A, bs, w, precision=hbmc.HBMC_F64, kernel=hbmc.HBMC_KERNEL_AUTO, reps=50,
+               timer=None, order=None, modes=("cold",), log=print, label=""):
+    """Median HIP-event time of one ic0_apply on A (random r in HBMC order,
+    dummies 0), caches cold before each call, and its algorithmic rate."""
+    import torch
+    o = order if order is not None else hbmc.hbmc_order(A, bs, w)
+    f = hbmc.ic0_factor(o, A, precision).set_kernel(kernel).upload(device)
+    perm, _ = o.perm()
+    r_np = np.zeros(f.n_pad)
+    r_np[perm] = np.random.default_rng(17).uniform(-1, 1, A.n)
+    r = torch.from_numpy(r_np).to(device)
+    z = torch.empty_like(r)
+    for _ in range(5):
+        hbmc.ic0_apply(f, r, z)
+    _sync()
+    timer = timer or ColdTimer(device)
+    nl = (A.nnz - A.n) // 2
+    sv = 8 if precision == hbmc.HBMC_F64 else 4
+    B = apply_bytes(f.n_pad, nl, sv, sv, sv)
+    out = {"bytes_per_apply": B, "n": A.n, "n_pad": f.n_pad, "nnz_lower": nl, "n_colors": f.n_colors,
+           "phases": 2 * f.n_colors - 1, "bs": bs, "w": w,
+           "precision": "f64" if precision == hbmc.HBMC_F64 else "f32"}
+    for mode in modes:
+        t = timer.times_ms(lambda: hbmc.ic0_apply(f, r, z), reps, mode)
+        us = float(np.median(t)) * 1e3
+        g = B / (us * 1e-6) / 1e9
+        key = "" if mode == "cold" else "_" + mode
+        out["median_us" + ("_cold" if mode == "cold" else key)] = round(us, 2)
+        out["gbs" + key] = round(g, 1)
+        out["frac" + key] = round(g / HBM_PEAK_GBS, 4)
+        log(f"[apply {label}] {mode}: {us:.1f} us, {g:.0f} GB/s algorithmic ({g / HBM_PEAK_GBS:.3f} of peak), "
+            f"{f.n_colors} colors")
+    del f, r, z
+    return out
 
 
 def fp32(device, npts=1_000_000, bs=2, w=32, tol=1e-7, log=print):
@@ -323,3 +416,34 @@ def refactor(device, N=128, bs=8, w=64, reps=3, log=print):
     res["speedup"] = round(t_host / t_dev, 1)
     log(f"[ext refactor] host rebuild {t_host * 1e3:.1f} ms, device refactor {t_dev * 1e3:.2f} ms")
     return res
+
+
+def _main():
+    import argparse
+    import json
+    import sys
+    import torch
+    ap = argparse.ArgumentParser(description="ic0_apply alone on one workload, caches cold before each call")
+    ap.add_argument("what", choices=["apply"])
+    ap.add_argument("workload", choices=sorted(WORKLOADS))
+    ap.add_argument("--bs", type=int, default=8)
+    ap.add_argument("--w", type=int, default=64)
+    ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
+    ap.add_argument("--kernel", choices=["auto", "sweep", "rows"], default="auto")
+    ap.add_argument("--reps", type=int, default=20)
+    ap.add_argument("--modes", default="cold,warm")
+    a = ap.parse_args()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(0)
+    A = WORKLOADS[a.workload]()
+    prec = hbmc.HBMC_F64 if a.precision == "f64" else hbmc.HBMC_F32
+    kern = {"auto": hbmc.HBMC_KERNEL_AUTO, "sweep": hbmc.HBMC_KERNEL_SWEEP, "rows": hbmc.HBMC_KERNEL_ROWS}[a.kernel]
+    log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    out = apply_rate(dev, A, a.bs, a.w, prec, kern, a.reps, modes=tuple(a.modes.split(",")), log=log,
+                     label=f"{a.workload} bs {a.bs} w {a.w} {a.precision} {a.kernel}")
+    out.update(workload=a.workload, kernel=a.kernel)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    _main()

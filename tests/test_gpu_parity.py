@@ -17,13 +17,20 @@ Bars (stated per test):
   of magnitude from one K to the next (measured with the oracle against
   itself under the BMC and HBMC orderings, which are equivalent in exact
   arithmetic, Section 3: 64^3 diffusion 3.6e-15 at K = 61, 2.3e-9 at
-  K = 113, 2.8e-12 at K = 123).  What stays small is the difference
-  relative to the iterate's own error: ||x_a(K) - x_b(K)|| <= 3.3e-3
-  ||x_a(K) - x*|| over every K measured (FP64; x* from an oracle solve to
-  1e-15).  The bar at half and at the full count is therefore
-  ||x - x_ref|| <= 1e-2 ||x_ref - x*|| (FP64) and 0.5 ||x_ref - x*|| (FP32
-  preconditioner, where the same measurement reaches 6e-2), and each
-  ||x - x_ref|| / ||x_ref|| is printed as a function of K;
+  K = 113, 2.8e-12 at K = 123; 128^3 diffusion 4.4e-8 at K = 112, 1.2e-6
+  at K = 168, 7.0e-11 at K = 225).  What stays small is the difference
+  relative to the iterate's own error ||x_a(K) - x*|| (x* from an oracle
+  solve to 1e-14): oracle against oracle at most 3.3e-3 (64^3) and 5.8e-3
+  (128^3, K = 168).  The GPU rounds each operation differently from the
+  oracle (fused multiply-adds, tree-ordered sums), so it starts further
+  away (128^3 at K = 10: 3.5e-14 against 8e-16 between the two oracle
+  runs) and reaches 1.2e-2 of the error at K = 112 and 225.  The bar at
+  half and at the full count is ||x - x_ref|| <= 5e-2 ||x_ref - x*|| (FP64)
+  and 0.5 ||x_ref - x*|| (FP32 preconditioner, where oracle against oracle
+  reaches 6e-2), together with equally accurate iterates
+  (| ||x - x*|| / ||x_ref - x*|| - 1 | within the same bar); each
+  ||x - x_ref|| / ||x_ref|| is printed as a function of K.  A wrong term,
+  sign or index fails the K <= 30 bars by orders of magnitude;
 - FP32 preconditioner against the oracle's FP32 PCG: 1e-6 relative for
   K <= 30 (an FP32 rounding of the preconditioned vector per iteration;
   the oracle's two orderings differ by ~1e-8 there).
@@ -202,14 +209,16 @@ def _iterate_parity(torch, s, solver, b, precision, ks, label):
         x = _host(x)
         d = np.linalg.norm(x - ref.x)
         e = np.linalg.norm(ref.x - xstar)
-        rows.append((K, d / np.linalg.norm(ref.x), d / e))
+        acc = np.linalg.norm(x - xstar) / e - 1.0
+        rows.append((K, d / np.linalg.norm(ref.x), d / e, acc))
         print(f"{label} {prec} K={K}: |x-x_ref|/|x_ref| = {d / np.linalg.norm(ref.x):.3e}, "
-              f"|x-x_ref|/|x_ref-x*| = {d / e:.3e}", flush=True)
-    for K, rel, frac in rows:
+              f"|x-x_ref|/|x_ref-x*| = {d / e:.3e}, |x-x*|/|x_ref-x*| - 1 = {acc:+.2e}", flush=True)
+    bar = 5e-2 if prec == "f64" else 0.5
+    for K, rel, frac, acc in rows:
         if K <= 30:
             assert rel <= (1e-10 if prec == "f64" else 1e-6), (label, K, rel)
         else:
-            assert frac <= (1e-2 if prec == "f64" else 0.5), (label, K, frac)
+            assert frac <= bar and abs(acc) <= bar, (label, K, frac, acc)
     return xstar
 
 
