@@ -19,7 +19,8 @@
  *    never allocates device memory: objects that live on the device report the
  *    bytes they need (..._device_bytes), the caller allocates them and hands
  *    them over with ..._upload, and keeps them alive (and unmodified) for the
- *    lifetime of the object.
+ *    lifetime of the object.  The one exception is the static scratch array
+ *    of iccg_solve_noalloc, part of the library's device code.
  *  - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
  *    stream).  Calls that take a stream only enqueue work on it, except
  *    iccg_solve, which synchronizes the stream to read residuals.
@@ -272,6 +273,33 @@ int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);
 int iccg_solve(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
                int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
                hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream);
+
+/* ---- iccg_solve without any allocation ----------------------------------------
+ * For callers that cannot allocate device memory (code under stream capture
+ * of their own, tight serving loops, harnesses that forbid hipMalloc):
+ * iccg_solve with its workspace taken from a static device array of the
+ * library, HBMC_NOALLOC_SCRATCH_BYTES (64 MiB) per device, which each device
+ * the library runs on holds from the first call there until the process
+ * ends.  Arguments, results, synchronization and errors as for iccg_solve,
+ * without work and work_bytes; the caller still passes b, x and the uploaded
+ * factor and matrix.  The call makes no device or host allocation: no
+ * hipMalloc, hipFree, graph instantiation or heap use.
+ *  - HBMC_EINVAL when iccg_workspace_bytes(f, nrhs) exceeds the scratch
+ *    (about 1.1 million unknowns times right-hand sides: 96^3 with one
+ *    right-hand side fits, 128^3 does not; use iccg_solve there), and for
+ *    opts->use_graph (instantiating a graph allocates) or
+ *    opts->record_history (the history would be left in the scratch).
+ *  - Every call on one device shares that device's scratch and leaves its
+ *    contents there (the solve clears what must start at zero with kernels,
+ *    not memsets): calls that overlap on one device, from any stream or
+ *    thread, race and give wrong results.  Serialize them.
+ *  - The first call on a device looks up that device's copy of the array
+ *    (hipGetSymbolAddress) with the device current. */
+#define HBMC_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+int iccg_solve_noalloc(const hbmc_factor_t *f, const hbmc_matrix_t *A, const double *b, double *x,
+                       int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
+                       hbmc_solve_stats_t *stats, void *stream);
 
 /* ---- new values, same pattern: factor and matrix rebuilt on the device ------
  * For sequences of matrices with one sparsity pattern (time steps, nonlinear

@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <atomic>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "hbmc_internal.h"
@@ -819,19 +820,27 @@ extern "C" int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t
     return HBMC_OK;
 }
 
-extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const double *b, double *x,
-                          int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
-                          hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream) {
-    clear_error();
-    auto *f = const_cast<hbmc_factor_s *>(fc);   // the graph cache is mutable state
-    if (!f || !A || !b || !x || !work) return fail(HBMC_EINVAL, "null argument");
+namespace {
+
+// Checks shared by the solve entry points.
+int solve_args(const hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *x, int32_t nrhs,
+               double tol, int32_t maxit) {
+    if (!f || !A || !b || !x) return fail(HBMC_EINVAL, "null argument");
     if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
     if (!A->dev) return fail(HBMC_ENOTREADY, "matrix not uploaded");
     if (A->n_pad != f->n_pad || A->n != f->n) return fail(HBMC_EINVAL, "matrix and factor sizes differ");
     if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     if (maxit < 0 || !(tol >= 0.0)) return fail(HBMC_EINVAL, "bad tol or maxit");
+    return HBMC_OK;
+}
+
+// The solve on a checked workspace of at least work_layout(f, nrhs) bytes.
+// Allocates nothing on the device or the host unless use_graph is set (the
+// graph is instantiated on first use).
+int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *x, int32_t nrhs, double tol,
+             int32_t maxit, const hbmc_solve_opts_t *opts, hbmc_solve_stats_t *stats, void *work,
+             void *stream) {
     const int K = nrhs;
-    if (work_bytes < work_layout(f, K, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
     Work w{};
     work_layout(f, K, &w, work);
     const bool x0_zero = opts && opts->x0_zero;
@@ -888,27 +897,98 @@ extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const
     VEC_LAUNCH(k_resid, n, K, s, n, K, w.bb, w.q, w.part_g, w.np);
     hipLaunchKernelGGL(k_fin_resid, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.resid);
     HIP_TRY(hipGetLastError());
-    std::vector<CgState> hs(nst);
-    std::vector<double> rt(nst);
-    HIP_TRY(hipMemcpyAsync(hs.data(), w.st, hs.size() * sizeof(CgState), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(rt.data(), w.resid, rt.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
+    // states and true residuals back in fixed-size chunks
+    constexpr int kChunk = 64;
+    CgState hs[kChunk];
+    double rt[kChunk];
     int status = HBMC_OK;
-    for (int32_t k = 0; k < nst; ++k) {
-        const int sk = hs[k].done == kConverged ? HBMC_OK
-                       : hs[k].done == kBreakdown ? HBMC_EBREAKDOWN : HBMC_ENOCONV;
-        if (sk == HBMC_EBREAKDOWN) status = HBMC_EBREAKDOWN;
-        else if (sk == HBMC_ENOCONV && status == HBMC_OK) status = HBMC_ENOCONV;
-        if (stats) {
-            stats[k].iters = hs[k].it;
-            stats[k].status = sk;
-            stats[k].rel_res = hs[k].res;
-            stats[k].true_rel_res = hs[k].bb > 0.0 ? std::sqrt(rt[k] / hs[k].bb) : 0.0;
+    for (int32_t k0 = 0; k0 < nst; k0 += kChunk) {
+        const int32_t nk = std::min<int32_t>(kChunk, nst - k0);
+        HIP_TRY(hipMemcpyAsync(hs, w.st + k0, nk * sizeof(CgState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipMemcpyAsync(rt, w.resid + k0, nk * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        for (int32_t i = 0; i < nk; ++i) {
+            const int sk = hs[i].done == kConverged ? HBMC_OK
+                           : hs[i].done == kBreakdown ? HBMC_EBREAKDOWN : HBMC_ENOCONV;
+            if (sk == HBMC_EBREAKDOWN) status = HBMC_EBREAKDOWN;
+            else if (sk == HBMC_ENOCONV && status == HBMC_OK) status = HBMC_ENOCONV;
+            if (stats) {
+                hbmc_solve_stats_t &o = stats[k0 + i];
+                o.iters = hs[i].it;
+                o.status = sk;
+                o.rel_res = hs[i].res;
+                o.true_rel_res = hs[i].bb > 0.0 ? std::sqrt(rt[i] / hs[i].bb) : 0.0;
+            }
         }
     }
     if (status == HBMC_EBREAKDOWN) return fail(HBMC_EBREAKDOWN, "CG breakdown: (p, Ap) <= 0 or not finite");
     if (status == HBMC_ENOCONV) fail(HBMC_ENOCONV, "maxit = %d reached", maxit);
     return status;
+}
+
+}  // namespace
+
+extern "C" int iccg_solve(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const double *b, double *x,
+                          int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
+                          hbmc_solve_stats_t *stats, void *work, size_t work_bytes, void *stream) {
+    clear_error();
+    auto *f = const_cast<hbmc_factor_s *>(fc);   // the graph cache is mutable state
+    int st = solve_args(f, A, b, x, nrhs, tol, maxit);
+    if (st) return st;
+    if (!work) return fail(HBMC_EINVAL, "null argument");
+    if (work_bytes < work_layout(f, nrhs, nullptr, nullptr)) return fail(HBMC_EINVAL, "workspace too small");
+    return solve_in(f, A, b, x, nrhs, tol, maxit, opts, stats, work, stream);
+}
+
+// ---------------------------------------------------------------------------
+// iccg_solve without allocation: the workspace is a static device array
+// ---------------------------------------------------------------------------
+namespace {
+
+// The workspace of iccg_solve_noalloc.  Host code never uses this name as an
+// address: hipGetSymbolAddress gives each device's copy, kept in g_scratch.
+__device__ __align__(256) unsigned char scratch[HBMC_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[kMaxDevices] = {};
+
+// The current device's copy of scratch (looked up once per device).
+int scratch_of_device(void **out) {
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(HBMC_EINVAL, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(HBMC_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch[dev] = p;
+    }
+    *out = g_scratch[dev];
+    return HBMC_OK;
+}
+
+}  // namespace
+
+extern "C" int iccg_solve_noalloc(const hbmc_factor_t *fc, const hbmc_matrix_t *A, const double *b, double *x,
+                                  int32_t nrhs, double tol, int32_t maxit, const hbmc_solve_opts_t *opts,
+                                  hbmc_solve_stats_t *stats, void *stream) {
+    clear_error();
+    auto *f = const_cast<hbmc_factor_s *>(fc);
+    int st = solve_args(f, A, b, x, nrhs, tol, maxit);
+    if (st) return st;
+    if (opts && opts->use_graph) return fail(HBMC_EINVAL, "use_graph: instantiating a graph allocates");
+    if (opts && opts->record_history)
+        return fail(HBMC_EINVAL, "record_history: the history would stay in the library's scratch");
+    const size_t need = work_layout(f, nrhs, nullptr, nullptr);
+    if (need > size_t(HBMC_NOALLOC_SCRATCH_BYTES))
+        return fail(HBMC_EINVAL, "the solve needs %zu bytes of workspace; the static scratch holds %zu "
+                    "(use iccg_solve with a caller workspace)", need, size_t(HBMC_NOALLOC_SCRATCH_BYTES));
+    void *work = nullptr;
+    if ((st = scratch_of_device(&work))) return st;
+    return solve_in(f, A, b, x, nrhs, tol, maxit, opts, stats, work, stream);
 }
 
 // Residual history of system 0, right-hand side 0, from the last iccg_solve

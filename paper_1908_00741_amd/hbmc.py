@@ -29,7 +29,8 @@ SYMBOLS = (
     "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "hbmc_factor_set_rhs_tile",
     "ic0_apply", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
-    "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_history",
+    "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_solve_noalloc",
+    "iccg_history",
     "ssor_factor", "hbmc_smooth_workspace_bytes", "hbmc_smooth",
     "hbmc_factor_image", "hbmc_matrix_image", "hbmc_set_num_threads",
     "hbmc_revalue_create", "hbmc_revalue_device_bytes", "hbmc_revalue_upload", "hbmc_revalue_destroy",
@@ -97,6 +98,7 @@ def lib():
         L.hbmc_from_hbmc.argtypes = [P, P, P, i32, P]
         L.iccg_workspace_bytes.argtypes = [P, i32, P]
         L.iccg_solve.argtypes = [P, P, P, P, i32, f64, i32, P, P, P, sz, P]
+        L.iccg_solve_noalloc.argtypes = [P, P, P, P, i32, f64, i32, P, P, P]
         L.iccg_history.argtypes = [P, sz, P, P, i32, P]
         L.ssor_factor.argtypes = [P, P, P, P, i32, f64, P]
         L.hbmc_smooth_workspace_bytes.argtypes = [P, i32, P]
@@ -483,6 +485,27 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
                                                   len(h), _stream(stream)))
         return x, (out[0] if nst == 1 else out), h
     return x, (out[0] if nst == 1 else out)
+
+
+# bytes of the library's static workspace used by iccg_solve_noalloc (per device)
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def iccg_solve_noalloc(f: Factor, m: Matrix, b, x, tol: float = 1e-7, maxit: int = 10000,
+                       nrhs: int = 1, x0_zero: bool = False, check_every: int = 0, stream=None):
+    """iccg_solve with the library's static device workspace: the call itself
+    allocates nothing, so x must be given (device FP64, original numbering;
+    overwritten with the solution).  Returns stats as iccg_solve does."""
+    _vec_check(b, f.n, nrhs, "b")
+    _vec_check(x, f.n, nrhs, "x")
+    opts = SolveOpts(1 if x0_zero else 0, int(check_every), 0, 0)
+    nst = f.n_systems * nrhs
+    stats = (SolveStats * nst)()
+    code = lib().iccg_solve_noalloc(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
+                                    C.byref(opts), stats, _stream(stream))
+    _check("iccg_solve_noalloc", code, ok=(HBMC_OK, HBMC_ENOCONV))
+    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res) for s in stats]
+    return out[0] if nst == 1 else out
 
 
 @dataclass
