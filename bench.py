@@ -70,9 +70,10 @@ def main() -> int:
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--ext", default="fp32,fp32_grid,batch,rhs,graph,orderings,smoother,refactor",
+    ap.add_argument("--ext", default="fp32,fp32_grid,batch,rhs,graph,orderings,smoother,refactor,warmstart",
                     help="comma-separated extension comparisons to run after the headline "
-                         "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother, refactor); empty for none")
+                         "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother, refactor, warmstart); "
+                         "empty for none")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the ic0_apply timings of the 1M-point kNN and 96^3 workloads")
@@ -206,6 +207,8 @@ def main() -> int:
                     ext[name] = experiments.batch(dev, log=log)
                 elif name == "rhs":
                     ext[name] = experiments.rhs(dev, log=log)
+                elif name == "warmstart":
+                    ext[name] = experiments.warmstart(dev, log=log)
                 else:
                     ext[name] = {"error": "unknown extension"}
             except Exception as e:   # reported in the JSON line, not fatal

@@ -259,13 +259,25 @@ typedef struct {
     int32_t check_every;   /* iterations between residual readbacks (>= 1)    */
     int32_t use_graph;     /* 1: replay the iterations as a captured hipGraph */
     int32_t record_history;/* 1: keep ||r||/||b|| per iteration (device)      */
+    int32_t x0_scale;      /* 1: start from c x0 (below)                      */
 } hbmc_solve_opts_t;
+
+/* x0_scale (with x0_zero = 0): the given start x0 is replaced by c x0 with
+ * c = (b, x0) / (x0, A x0), the multiple of x0 whose A-norm error
+ * ||c x0 - x*||_A is smallest; that error is never above ||x*||_A, the
+ * error of x = 0 (CG minimizes the A-norm of the error, Section 2's ICCG
+ * being CG on the preconditioned system).  When (b, x0) <= 0 or
+ * (x0, A x0) <= 0, c = 0: the solve starts from 0, the fallback.  Per
+ * system and right-hand side; c is reported in the stats.  Meant for
+ * approximate starts such as a learned guess. */
 
 typedef struct {
     int32_t iters;          /* products A p made before stopping              */
     int32_t status;         /* HBMC_OK, HBMC_ENOCONV or HBMC_EBREAKDOWN       */
     double rel_res;         /* recurrence ||r|| / ||b|| at stop               */
     double true_rel_res;    /* ||b - A x|| / ||b|| at stop                    */
+    double x0_scale;        /* c applied to x0 (1 without x0_scale, 0 when the
+                               start was 0)                                   */
 } hbmc_solve_stats_t;
 
 int iccg_workspace_bytes(const hbmc_factor_t *f, int32_t nrhs, size_t *bytes);

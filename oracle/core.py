@@ -283,6 +283,23 @@ def pcg(Ab, d, fac, b, x0=None, tol: float = 1e-7, maxit: int = 10000,
     return PCGResult(x, it.value, st, hist[: it.value + 1])
 
 
+def scaled_start(A, b, x0):
+    """The start vector c x0 with c = (b, x0) / (x0, A x0), the multiple of
+    x0 nearest the solution x* in the A-norm: ||c x0 - x*||_A^2 =
+    c^2 (x0, A x0) - 2 c (b, x0) + ||x*||_A^2 is least there, and never above
+    ||x*||_A^2, the error of a zero start, which it equals at c = 0.  c = 0
+    (start from zero) when (b, x0) or (x0, A x0) is not > 0.  A safeguard of
+    the learned warm start, which the paper does not have; CG minimizes the
+    A-norm of the error (Section 2's ICCG is CG).  Plain FP64: the oracle's
+    product with A (any numbering) and two inner products.  Returns (c, c x0)."""
+    x0 = np.ascontiguousarray(x0, np.float64)
+    b = np.ascontiguousarray(b, np.float64)
+    bx = float(np.dot(b, x0))
+    xax = float(np.dot(x0, spmv(A, x0)))
+    c = bx / xax if (bx > 0.0 and xax > 0.0) else 0.0
+    return c, c * x0
+
+
 @dataclass
 class System:
     """A problem carried through the oracle: ordering, reordered matrix,

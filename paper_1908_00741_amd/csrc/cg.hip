@@ -314,6 +314,49 @@ __device__ inline void count_done(int32_t *ndone, int32_t *alldone, int total) {
     if (atomicAdd(ndone, 1) + 1 == total) *alldone = 1;
 }
 
+// part partials of (b, x0) and (x0, A x0) (q = A x0), for the scaling of a
+// given start vector
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_init_dots(int64_t n, int K, const double *__restrict__ b,
+                                                      const double *__restrict__ x, const double *__restrict__ q,
+                                                      double *part, int64_t np) {
+    if (NR == 1) K = 1;
+    double bx = 0.0, xq = 0.0;
+#pragma unroll 1
+    for (int mm = 0; mm < rounds(NR); ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) {
+            const int64_t e = r.row * K + r.q;
+            bx += b[e] * x[e];
+            xq += x[e] * q[e];
+        }
+    }
+    store_part<NR>(part, np, K, bx);
+    store_part<NR>(part + int64_t(K) * np, np, K, xq);
+}
+
+// c = (b, x0) / (x0, A x0) per (system, right-hand side), 0 when either is
+// not > 0 (start from 0)
+__global__ void __launch_bounds__(kFin) k_fin_scale(const double *part, int64_t np, int pmul, int K, Sys sys,
+                                                    CgState *st) {
+    const int b = blockIdx.x, s = b / K, q = b % K;
+    const double bx = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
+    const double xq = sys_total(part + (K + q) * np, sys.parts, sys.nc, s, pmul);
+    if (threadIdx.x == 0) st[b].c0 = (bx > 0.0 && xq > 0.0 && isfinite(bx / xq)) ? bx / xq : 0.0;
+}
+
+// x0 *= c, q *= c (q = A x0 stays the product of the scaled start)
+__global__ void __launch_bounds__(kBlock) k_scale_x(int64_t n_pad, int K, const int32_t *__restrict__ part_sys,
+                                                    const CgState *st, double *__restrict__ x,
+                                                    double *__restrict__ q) {
+    const int64_t e = int64_t(blockIdx.x) * kBlock + threadIdx.x;
+    if (e >= n_pad * K) return;
+    const int64_t row = e / K;
+    const double c = st[int64_t(part_sys[row / kPartRows]) * K + (e - row * K)].c0;
+    x[e] *= c;
+    q[e] *= c;
+}
+
 // per (system s, right-hand side q) = blockIdx.x = s * K + q: ||b||^2,
 // ||r0||^2, the state, and whether it is already done
 __global__ void __launch_bounds__(kFin) k_fin_init(const double *part, int64_t np, int pmul, int K, Sys sys,
@@ -844,6 +887,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     Work w{};
     work_layout(f, K, &w, work);
     const bool x0_zero = opts && opts->x0_zero;
+    const bool x0_scale = !x0_zero && opts && opts->x0_scale;
     const bool use_graph = opts && opts->use_graph;
     const bool history = opts && opts->record_history;
     int check = opts && opts->check_every > 0 ? opts->check_every : (use_graph ? 16 : 1);
@@ -862,6 +906,11 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     if (x0_zero) hipLaunchKernelGGL(k_zero, dim3(ge), dim3(kBlock), 0, s, n * K, w.xb);
     else hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, x, w.xb);
     VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
+    if (x0_scale) {
+        VEC_LAUNCH(k_init_dots, n, K, s, n, K, w.bb, w.xb, w.q, w.part_g, w.np);
+        hipLaunchKernelGGL(k_fin_scale, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st);
+        hipLaunchKernelGGL(k_scale_x, dim3(ge), dim3(kBlock), 0, s, n, K, sys.part_sys, w.st, w.xb, w.q);
+    }
     VEC_LAUNCH(k_init_r, n, K, s, n, K, w.bb, w.q, w.r, w.part_g, w.np);
     hipLaunchKernelGGL(k_fin_init, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, tol, maxit,
                        history ? w.hist : nullptr, w.ndone, w.alldone);
@@ -918,6 +967,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
                 o.status = sk;
                 o.rel_res = hs[i].res;
                 o.true_rel_res = hs[i].bb > 0.0 ? std::sqrt(rt[i] / hs[i].bb) : 0.0;
+                o.x0_scale = x0_zero ? 0.0 : (x0_scale ? hs[i].c0 : 1.0);
             }
         }
     }

@@ -185,11 +185,20 @@ size_t add_packed(ImageBuilder &im, const Packed &p, bool f32, PackedOffsets &o)
     o.sbase = im.add(p.sbase);
     o.smask = im.add(p.smask);
     o.sval = f32 ? im.add(cast<float>(p.sval)) : im.add(p.sval);
-    o.ioff = im.add(p.ioff);
-    o.imask = im.add(p.imask);
-    o.ivoff = im.add(p.ivoff);
-    o.icol = im.add(p.icol);
-    o.ival = f32 ? im.add(cast<float>(p.ival)) : im.add(p.ival);
+    // the left-over couplings: indexed slots, or their flat form
+    o = PackedOffsets{o.soff, o.sbase, o.smask, o.sval, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+    if (p.flat) {
+        o.goff = im.add(p.goff);
+        o.lstart = im.add(p.lstart);
+        o.fcol = im.add(p.fcol);
+        o.fval = f32 ? im.add(cast<float>(p.fval)) : im.add(p.fval);
+    } else {
+        o.ioff = im.add(p.ioff);
+        o.imask = im.add(p.imask);
+        o.ivoff = im.add(p.ivoff);
+        o.icol = im.add(p.icol);
+        o.ival = f32 ? im.add(cast<float>(p.ival)) : im.add(p.ival);
+    }
     return o.soff;
 }
 
@@ -245,16 +254,34 @@ int Packed::add_group(const std::vector<CouplingSpan> &lanes, int64_t limit, int
     max_strided = std::max(max_strided, int32_t(cands.size()));
     // the rest, per lane in column order, as indexed slots: slot t holds the
     // t-th left-over coupling of each lane that has one, in lane order
-    thread_local std::vector<int32_t> left;   // left-over entries of each lane, lane by lane
+    thread_local std::vector<int32_t> left_of;   // left-over entries of each lane, lane by lane
     thread_local std::vector<int32_t> lfirst;
-    left.clear();
+    left_of.clear();
     lfirst.assign(nl + 1, 0);
     int32_t len = 0;
     for (int j = 0; j < nl; ++j) {
         for (int32_t i = first[j]; i < first[j + 1]; ++i)
-            if (!used[i]) left.push_back(i - first[j]);
-        lfirst[j + 1] = int32_t(left.size());
+            if (!used[i]) left_of.push_back(i - first[j]);
+        lfirst[j + 1] = int32_t(left_of.size());
         len = std::max(len, lfirst[j + 1] - lfirst[j]);
+    }
+    left += int64_t(left_of.size());
+    if (both) {
+        // the flat form: lane by lane, each lane's in column order
+        const int64_t g0 = int64_t(fcol.size());
+        for (int j = 0; j < kTileLanes; ++j) {
+            const int64_t rel = int64_t(fcol.size()) - g0;
+            if (rel > 0xFFFF) overflow = true;
+            lstart.push_back(uint16_t(rel));
+            if (j >= nl) continue;
+            for (int32_t k = lfirst[j]; k < lfirst[j + 1]; ++k) {
+                const Coupling &c = lanes[j][left_of[k]];
+                fcol.push_back(c.first);
+                fval.push_back(c.second);
+            }
+        }
+        goff.push_back(int64_t(fcol.size()));
+        max_group = std::max(max_group, int32_t(int64_t(fcol.size()) - g0));
     }
     const int64_t base = ioff.back();
     ioff.push_back(int32_t(base + len));
@@ -263,7 +290,7 @@ int Packed::add_group(const std::vector<CouplingSpan> &lanes, int64_t limit, int
         ivoff.push_back(int64_t(icol.size()));
         for (int j = 0; j < nl; ++j) {
             if (lfirst[j] + t >= lfirst[j + 1]) continue;
-            const Coupling &c = lanes[j][left[lfirst[j] + t]];
+            const Coupling &c = lanes[j][left_of[lfirst[j] + t]];
             mask |= uint64_t(1) << j;
             icol.push_back(c.first);
             ival.push_back(c.second);
@@ -283,6 +310,14 @@ void Packed::reserve_for(const std::vector<const Packed *> &parts) {
     }
     soff.reserve(so); sbase.reserve(sb + 1); smask.reserve(sb + 1); sval.reserve(sv + kTileLanes);
     ioff.reserve(io); imask.reserve(is + 1); ivoff.reserve(is + 1); icol.reserve(iv + 1); ival.reserve(iv + 1);
+    if (both) {
+        size_t go = goff.size(), ls = lstart.size(), fc = fcol.size();
+        for (const Packed *p : parts) { go += p->goff.size(); ls += p->lstart.size(); fc += p->fcol.size(); }
+        goff.reserve(go);
+        lstart.reserve(ls);
+        fcol.reserve(fc + 1);
+        fval.reserve(fc + 1);
+    }
 }
 
 void Packed::append(const Packed &o) {
@@ -300,6 +335,16 @@ void Packed::append(const Packed &o) {
     max_strided = std::max(max_strided, o.max_strided);
     max_indexed = std::max(max_indexed, o.max_indexed);
     entries += o.entries;
+    left += o.left;
+    if (both) {
+        const int64_t fb = int64_t(fcol.size());
+        for (size_t i = 1; i < o.goff.size(); ++i) goff.push_back(fb + o.goff[i]);
+        lstart.insert(lstart.end(), o.lstart.begin(), o.lstart.end());
+        fcol.insert(fcol.end(), o.fcol.begin(), o.fcol.end());
+        fval.insert(fval.end(), o.fval.begin(), o.fval.end());
+        max_group = std::max(max_group, o.max_group);
+        overflow = overflow || o.overflow;
+    }
 }
 
 void Packed::finish() {
@@ -310,6 +355,10 @@ void Packed::finish() {
     ivoff.push_back(int64_t(icol.size()));
     icol.push_back(-1);
     ival.push_back(0.0);
+    if (both) {                               // the padding entry of the flat form
+        fcol.push_back(-1);
+        fval.push_back(0.0);
+    }
 }
 
 namespace {
@@ -428,6 +477,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
         std::vector<Chunk> chunks(nchunks);
         parallel_chunks(ntiles, nchunks, [&](int64_t t_lo, int64_t t_hi, int ch) {
             Chunk &k = chunks[ch];
+            k.fext.both = k.bext.both = true;
             k.fint.off.assign(1, 0);
             k.bint.off.assign(1, 0);
             std::vector<CouplingSpan> lanes_f(kTileLanes), lanes_b(kTileLanes), lanes_fi(kTileLanes),
@@ -482,6 +532,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
         });
         f->fint.off.assign(1, 0);
         f->bint.off.assign(1, 0);
+        f->fext.both = f->bext.both = true;
         f->max_int_slots_f = f->max_int_slots_b = f->max_int_step_f = f->max_int_step_b = 0;
         {
             std::vector<const Packed *> pf, pb;
@@ -508,6 +559,16 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
         chunks.clear();
         f->fext.finish();
         f->bext.finish();
+        // the device gets the flat form where the left-over couplings
+        // outweigh the strided slots (unstructured graphs), else the slots
+        {
+            const bool flat = (f->fext.left + f->bext.left) / kTileLanes > f->fext.strided() + f->bext.strided();
+            if (flat && (f->fext.overflow || f->bext.overflow)) {
+                delete f;
+                return fail(HBMC_EINVAL, "a (tile, step) group has more than 65535 couplings to other colors");
+            }
+            f->fext.flat = f->bext.flat = flat;
+        }
         for (Sell *sl : {&f->fint, &f->bint}) {   // the padding slot
             sl->val.resize(sl->val.size() + kTileLanes, 0.0);
             sl->col.resize(sl->col.size() + kTileLanes, -1);

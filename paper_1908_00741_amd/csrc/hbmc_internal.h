@@ -59,6 +59,7 @@ struct Sell {
 // CG state of one system, kept on the device between kernels.
 struct CgState {
     double rho, alpha, beta, sigma, rr, bb, res, tol;
+    double c0;   // scale applied to a given start vector (x0_scale)
     int32_t it, maxit, done, pad;
 };
 // Stop flag values
@@ -135,6 +136,18 @@ struct CouplingRows {
 // j) from the slot's first entry), so that lanes without one cost nothing.
 // Each array ends with one all-padding slot that loads may target instead
 // of branching.
+//
+// Flat form of the left-over couplings (substitution factors build it
+// beside the slots when `both` is set before adding groups, and upload one
+// of the two forms, `flat` saying which): a group's left-over couplings
+// stored lane by lane (lane j's in column order, the order the slots visit
+// them), with the group's first entry (goff) and each lane's first entry
+// relative to it (lstart, 64 per group; lane 63's entries end where the
+// next group's begin).  A lane can then read its own entries in place, or
+// the lanes of a wavefront can share the group's entries evenly whatever
+// the length of each row (row splitting).  Slots suit grids (few left-over
+// couplings, each slot's entries adjacent across lanes); the flat form
+// suits unstructured graphs (mostly left-over couplings of uneven count).
 struct Packed {
     std::vector<int32_t> soff{0};   // [groups + 1] strided slots per group
     std::vector<int32_t> sbase;     // [strided + 1]
@@ -145,8 +158,17 @@ struct Packed {
     std::vector<int64_t> ivoff;     // [indexed + 1] the slot's first entry in icol / ival
     std::vector<int32_t> icol;      // [entries in indexed slots + 1] columns
     std::vector<double> ival;       // [entries in indexed slots + 1] values
-    int32_t max_strided = 0, max_indexed = 0;   // per group
+    int32_t max_strided = 0, max_indexed = 0;   // per group (flat: most left-over couplings of a lane)
     int64_t entries = 0;                        // couplings stored
+    int64_t left = 0;                           // left-over couplings (in indexed slots)
+    bool both = false;                          // build the flat form too
+    bool flat = false;                          // the device image holds the flat form, not the slots
+    std::vector<int64_t> goff{0};               // flat: [groups + 1] first entry of each group
+    std::vector<uint16_t> lstart;               // flat: [groups * kTileLanes] lane starts in the group
+    std::vector<int32_t> fcol;                  // flat: [left + 1] columns (+ padding entry)
+    std::vector<double> fval;                   // flat: [left + 1] values
+    int32_t max_group = 0;                      // flat: most entries of a group
+    bool overflow = false;                      // flat: a group held more entries than lstart can address
     // lanes[j]: couplings of lane j's row (sorted by column), or null.
     // Columns base + j of strided slots stay below limit; at most budget
     // strided slots are made (the rest of the couplings go to indexed slots).
@@ -181,6 +203,7 @@ struct hbmc_order_s {
 // Offsets (bytes, inside a device image) of a Packed layout.
 struct PackedOffsets {
     size_t soff, sbase, smask, sval, ioff, imask, ivoff, icol, ival;
+    size_t goff, lstart, fcol, fval;   // flat form only
 };
 
 // Offsets of one triangular direction.

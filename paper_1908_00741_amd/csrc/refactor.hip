@@ -144,11 +144,16 @@ struct Dir {
     const int32_t *soff, *sbase;
     const uint64_t *smask;
     T *sval;
-    const int32_t *ioff;
+    const int32_t *ioff;      // indexed slots
     const uint64_t *imask;
     const int64_t *ivoff;
     const int32_t *icol;
     T *ival;
+    const int64_t *goff;      // flat form: first entry of each group
+    const uint16_t *lstart;   // first entry of each lane, relative to goff
+    const int32_t *fcol;
+    T *fval;
+    bool flat;
     const int32_t *int_off;
     const int8_t *int_lp;
     T *int_val;
@@ -176,11 +181,18 @@ __global__ void __launch_bounds__(kLanes) k_rv_pack(Rv R, Dir<T> D) {
     };
     for (int32_t s = D.soff[g]; s < D.soff[g + 1]; ++s)
         if ((D.smask[s] >> j) & 1) D.sval[int64_t(s) * kLanes + j] = value(D.sbase[s] + j);
-    for (int32_t s = D.ioff[g]; s < D.ioff[g + 1]; ++s) {
-        const uint64_t mask = D.imask[s];
-        if (!((mask >> j) & 1)) continue;
-        const int64_t e = D.ivoff[s] + __builtin_popcountll(mask & ((uint64_t(1) << j) - 1));
-        D.ival[e] = value(D.icol[e]);
+    if (D.flat) {
+        const int64_t g0 = D.goff[g];
+        const int64_t a = g0 + D.lstart[g * kLanes + j];
+        const int64_t b = j + 1 < kLanes ? g0 + D.lstart[g * kLanes + j + 1] : D.goff[g + 1];
+        for (int64_t e = a; e < b; ++e) D.fval[e] = value(D.fcol[e]);
+    } else {
+        for (int32_t s = D.ioff[g]; s < D.ioff[g + 1]; ++s) {
+            const uint64_t mask = D.imask[s];
+            if (!((mask >> j) & 1)) continue;
+            const int64_t e = D.ivoff[s] + __builtin_popcountll(mask & ((uint64_t(1) << j) - 1));
+            D.ival[e] = value(D.icol[e]);
+        }
     }
     for (int32_t s = D.int_off[g]; s < D.int_off[g + 1]; ++s) {
         const int lp = D.int_lp[int64_t(s) * kLanes + j];
@@ -224,13 +236,14 @@ __global__ void __launch_bounds__(kLanes) k_rv_matrix(Rv R, MatVals M, const dou
 }
 
 template <typename T>
-Dir<T> dir_of(hbmc_factor_s *f, const TriOffsets &o) {
+Dir<T> dir_of(hbmc_factor_s *f, const TriOffsets &o, bool flat) {
     void *b = f->dev;
     const PackedOffsets &x = o.ext;
     return Dir<T>{at<int32_t>(b, x.soff), at<int32_t>(b, x.sbase), at<uint64_t>(b, x.smask), at<T>(b, x.sval),
                   at<int32_t>(b, x.ioff), at<uint64_t>(b, x.imask), at<int64_t>(b, x.ivoff),
-                  at<int32_t>(b, x.icol), at<T>(b, x.ival), at<int32_t>(b, o.int_off), at<int8_t>(b, o.int_lp),
-                  at<T>(b, o.int_val)};
+                  at<int32_t>(b, x.icol), at<T>(b, x.ival),
+                  at<int64_t>(b, x.goff), at<uint16_t>(b, x.lstart), at<int32_t>(b, x.fcol), at<T>(b, x.fval), flat,
+                  at<int32_t>(b, o.int_off), at<int8_t>(b, o.int_lp), at<T>(b, o.int_val)};
 }
 
 template <typename T>
@@ -238,9 +251,9 @@ int pack_factor(hbmc_factor_s *f, const Rv &R, hipStream_t s) {
     const int64_t groups = f->tile_base[f->nc] * f->bs;
     if (groups > 0) {
         hipLaunchKernelGGL((k_rv_pack<T, false>), dim3(unsigned(groups)), dim3(kLanes), 0, s, R,
-                           dir_of<T>(f, f->fwd));
+                           dir_of<T>(f, f->fwd, f->fext.flat));
         hipLaunchKernelGGL((k_rv_pack<T, true>), dim3(unsigned(groups)), dim3(kLanes), 0, s, R,
-                           dir_of<T>(f, f->bwd));
+                           dir_of<T>(f, f->bwd, f->bext.flat));
     }
     hipLaunchKernelGGL(k_rv_dinv<T>, dim3(unsigned((f->n_pad + 255) / 256)), dim3(256), 0, s, R,
                        at<T>(f->dev, f->off_dinv));

@@ -71,19 +71,26 @@ using namespace hbmc;
 constexpr int kLanes = kTileLanes;
 constexpr size_t kMaxLds = 64 * 1024;      // LDS budget of one workgroup (general path)
 
-// Device pointers of a Packed layout (strided and indexed slots per group),
-// each array with a trailing all-padding slot.
+// Device pointers of a factor's Packed layout: strided slots per group,
+// then the left-over couplings either in indexed slots or in flat form
+// (lane by lane per group); every array with a trailing padding slot or
+// entry.
 struct Ext {
     const int32_t *soff;
     const int32_t *sbase;
     const uint64_t *smask;
     const void *sval;
-    const int32_t *ioff;
-    const uint64_t *imask;   // lanes of each indexed slot
-    const int64_t *ivoff;    // first packed entry of each indexed slot
+    const int32_t *ioff;      // indexed slots
+    const uint64_t *imask;    // lanes of each indexed slot
+    const int64_t *ivoff;     // first packed entry of each indexed slot
     const int32_t *icol;
     const void *ival;
-    int64_t spad, ipad;   // index of the padding slots
+    const int64_t *goff;      // flat form: [groups + 1] first entry of each group
+    const uint16_t *lstart;   // flat form: [groups][64] first entry of each chain lane, relative to goff
+    const int32_t *fcol;
+    const void *fval;
+    int64_t spad, ipad, fpad;   // the padding slots and the flat padding entry
+    bool flat;
 };
 
 // Entry of chain lane jc in a packed indexed slot (mask, first entry): its
@@ -92,6 +99,23 @@ struct Ext {
 __device__ inline int64_t packed_entry(uint64_t mask, int64_t first, int jc, bool &on) {
     on = (mask >> jc) & 1;
     return first + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
+}
+
+// Lanes 0..63 of one wavefront: the largest of v.
+__device__ inline int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+// The flat entries of chain lane jc in group g: [first, first + count).
+__device__ inline void lane_range(const Ext &E, int64_t g, int jc, int64_t &first, int &count) {
+    const int64_t g0 = E.goff[g];
+    const int ne = int(E.goff[g + 1] - g0);
+    const int a = E.lstart[g * kLanes + jc];
+    const int b = jc + 1 < kLanes ? int(E.lstart[g * kLanes + jc + 1]) : ne;
+    first = g0 + a;
+    count = b - a;
 }
 
 // One direction: couplings to other colors (ext) and inside the level-1
@@ -132,6 +156,13 @@ __device__ inline double rhs_sum(double v) {
 
 enum { kForward = 0, kBackward = 1, kLast = 2 };
 
+// Row-splitting window of k_rows: chunks of 64 entries per wavefront, so
+// that the bs wavefronts of a workgroup stage at most 32 KB.
+template <int BS, typename T>
+__host__ __device__ constexpr int split_window() {
+    return 32768 / (BS * kLanes * 2 * int(sizeof(T))) < 16 ? 32768 / (BS * kLanes * 2 * int(sizeof(T))) : 16;
+}
+
 // y[idx] among the compile-time candidates lo <= idx < hi, else 0.
 template <int BS, typename T>
 __device__ inline T pick(const T (&y)[BS], int idx, int lo, int hi) {
@@ -157,56 +188,62 @@ struct Lane {
     __device__ int64_t at(int64_t row) const { return row * K + q; }
 };
 
-// acc[l] -= sum of the couplings to other colors of step l, for all steps.
-// Chunks of CH slots: within a chunk every step's slot loads are issued
-// before any of them is used; a slot past a step's count reads the padding
-// slot, whose empty lane mask (strided) or column -1 (indexed) drops the
-// product.  Strided slots read z[base + jc]; the bases and lane masks of the
-// tile's strided slots (at most 64) are fetched by one vector load, one slot
-// per lane, and broadcast with readlane, so no load waits on another.
-// Indexed slots first load the slot's lane mask and first entry, then the
+// acc[l] -= sum of the couplings to other colors of step l, for all steps,
+// each lane over its own couplings in column order: the strided slots, then
+// its flat entries.  Chunks of CH slots (entries): within a chunk every
+// step's loads are issued before any of them is used; a slot past a step's
+// count reads the padding slot, whose empty lane mask drops the product, and
+// an entry past a lane's count reads the padding entry and is dropped.
+// Strided slots read z[base + jc]; the bases and lane masks of the tile's
+// strided slots (at most 64) are fetched by one vector load, one slot per
+// lane, and broadcast with readlane, so no load waits on another.
+template <int BS, int CH, typename T>
+__device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
+                                   const double *__restrict__ z) {
+    const int jc = L.jc;
+    int32_t so[BS + 1];
+#pragma unroll
+    for (int l = 0; l <= BS; ++l) so[l] = E.soff[gt + l];
+    const T *val = static_cast<const T *>(E.sval);
+    const int nst = so[BS] - so[0];
+    const int64_t mslot = so[0] + (j < nst ? j : 0);
+    const int32_t mbase = E.sbase[mslot];
+    const uint64_t mmask = E.smask[mslot];
+    int smax = 0;
+#pragma unroll
+    for (int l = 0; l < BS; ++l) smax = max(smax, so[l + 1] - so[l]);
+    for (int c0 = 0; c0 < smax; c0 += CH) {
+        T v[BS][CH], g[BS][CH];
+        bool on[BS][CH];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const bool has = c0 + k < so[l + 1] - so[l];
+                const int q = has ? so[l] + c0 + k - so[0] : 0;
+                const int32_t base = has ? __builtin_amdgcn_readlane(mbase, q) : 0;
+                const uint64_t mask = has ? readlane64(mmask, q) : 0;
+                const int64_t slot = has ? so[l] + c0 + k : E.spad;
+                on[l][k] = (mask >> jc) & 1;
+                v[l][k] = val[slot * kLanes + jc];
+                g[l][k] = T(z[L.at(base + jc)]);
+            }
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc[l] = on[l][k] ? acc[l] - v[l][k] * g[l][k] : acc[l];
+    }
+}
+
+// Indexed slots: each loads the slot's lane mask and first entry, then the
 // lane's column.
 template <int BS, int CH, typename T>
-__device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
-                                 const double *__restrict__ z) {
+__device__ inline void ext_packed(T (&acc)[BS], const Ext E, int64_t gt, const Lane &L,
+                                  const double *__restrict__ z) {
     const int jc = L.jc;
-    int32_t so[BS + 1], io[BS + 1];
+    int32_t io[BS + 1];
 #pragma unroll
-    for (int l = 0; l <= BS; ++l) {
-        so[l] = E.soff[gt + l];
-        io[l] = E.ioff[gt + l];
-    }
-    {
-        const T *val = static_cast<const T *>(E.sval);
-        const int nst = so[BS] - so[0];
-        const int64_t mslot = so[0] + (j < nst ? j : 0);
-        const int32_t mbase = E.sbase[mslot];
-        const uint64_t mmask = E.smask[mslot];
-        int smax = 0;
-#pragma unroll
-        for (int l = 0; l < BS; ++l) smax = max(smax, so[l + 1] - so[l]);
-        for (int c0 = 0; c0 < smax; c0 += CH) {
-            T v[BS][CH], g[BS][CH];
-            bool on[BS][CH];
-#pragma unroll
-            for (int l = 0; l < BS; ++l)
-#pragma unroll
-                for (int k = 0; k < CH; ++k) {
-                    const bool has = c0 + k < so[l + 1] - so[l];
-                    const int q = has ? so[l] + c0 + k - so[0] : 0;
-                    const int32_t base = has ? __builtin_amdgcn_readlane(mbase, q) : 0;
-                    const uint64_t mask = has ? readlane64(mmask, q) : 0;
-                    const int64_t slot = has ? so[l] + c0 + k : E.spad;
-                    on[l][k] = (mask >> jc) & 1;
-                    v[l][k] = val[slot * kLanes + jc];
-                    g[l][k] = T(z[L.at(base + jc)]);
-                }
-#pragma unroll
-            for (int l = 0; l < BS; ++l)
-#pragma unroll
-                for (int k = 0; k < CH; ++k) acc[l] = on[l][k] ? acc[l] - v[l][k] * g[l][k] : acc[l];
-        }
-    }
+    for (int l = 0; l <= BS; ++l) io[l] = E.ioff[gt + l];
     const T *val = static_cast<const T *>(E.ival);
     int smax = 0;
 #pragma unroll
@@ -235,6 +272,100 @@ __device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, c
 #pragma unroll
             for (int k = 0; k < CH; ++k) acc[l] = col[l][k] >= 0 ? acc[l] - v[l][k] * g[l][k] : acc[l];
     }
+}
+
+// Flat form, each lane over its own entries.
+template <int BS, int CH, typename T>
+__device__ inline void ext_lanes(T (&acc)[BS], const Ext E, int64_t gt, const Lane &L,
+                                 const double *__restrict__ z) {
+    int64_t e0[BS];
+    int cnt[BS];
+    int cmax = 0;
+#pragma unroll
+    for (int l = 0; l < BS; ++l) {
+        lane_range(E, gt + l, L.jc, e0[l], cnt[l]);
+        cmax = max(cmax, cnt[l]);
+    }
+    cmax = wave_max(cmax);
+    const T *val = static_cast<const T *>(E.fval);
+    for (int c0 = 0; c0 < cmax; c0 += CH) {
+        int32_t col[BS][CH];
+        T v[BS][CH];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                const bool has = c0 + k < cnt[l];
+                const int64_t e = has ? e0[l] + c0 + k : E.fpad;
+                const int32_t c = E.fcol[e];
+                col[l][k] = has ? c : -1;
+                v[l][k] = val[e];
+            }
+        T g[BS][CH];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) g[l][k] = T(z[L.at(col[l][k] >= 0 ? col[l][k] : 0)]);
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) acc[l] = col[l][k] >= 0 ? acc[l] - v[l][k] * g[l][k] : acc[l];
+    }
+}
+
+template <int BS, int CH, typename T>
+__device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
+                                 const double *__restrict__ z) {
+    ext_strided<BS, CH, T>(acc, E, gt, j, L, z);
+    if (E.flat) ext_lanes<BS, CH, T>(acc, E, gt, L, z);
+    else ext_packed<BS, CH, T>(acc, E, gt, L, z);
+}
+
+// Row splitting (one right-hand side): the flat entries of group g,
+// however unevenly they fall on the rows, are shared evenly by the 64 lanes
+// (entry w0 + 64 k + j to lane j), which load them with coalesced loads,
+// gather z and stage (value, z) pairs in this wavefront's LDS window
+// (win: 2 * NW * 64 values); each chain lane then adds up its own entries
+// from the window in column order, the order and arithmetic of ext_lanes.
+// Groups longer than the window take several rounds.
+template <int NW, typename T>
+__device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const double *__restrict__ z, T *win) {
+    const int64_t g0 = E.goff[g];
+    const int ne = int(E.goff[g + 1] - g0);
+    if (ne == 0) return acc;
+    const int a = E.lstart[g * kLanes + j];
+    const int b = j + 1 < kLanes ? int(E.lstart[g * kLanes + j + 1]) : ne;
+    const T *val = static_cast<const T *>(E.fval);
+    T *wv = win, *wz = win + NW * kLanes;
+    for (int w0 = 0; w0 < ne; w0 += NW * kLanes) {
+        const int nk = min(NW, (ne - w0 + kLanes - 1) / kLanes);
+        T v[NW], gz[NW];
+        int32_t col[NW];
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (k < nk) {
+                const int64_t e = g0 + min(w0 + k * kLanes + j, ne - 1);
+                col[k] = E.fcol[e];
+                v[k] = val[e];
+            }
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (k < nk) gz[k] = T(z[col[k]]);
+#pragma unroll
+        for (int k = 0; k < NW; ++k)
+            if (k < nk) {
+                wv[k * kLanes + j] = v[k];
+                wz[k * kLanes + j] = gz[k];
+            }
+        // the window is written by other lanes of this wavefront
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int lo = max(a, w0), hi = min(b, w0 + NW * kLanes);
+        for (int e = lo; e < hi; ++e) acc = acc - wv[e - w0] * wz[e - w0];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    return acc;
 }
 
 // Couplings inside the level-1 block for all steps, at most MI per step,
@@ -475,6 +606,8 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
     T *svb = svf + ph.lds_slots * kLanes;                    // [lds_slots][64]
     int32_t *slf = reinterpret_cast<int32_t *>(svb + ph.lds_slots * kLanes);
     int32_t *slb = slf + ph.lds_slots * kLanes;
+    constexpr int NW = split_window<BS, T>();
+    T *win = reinterpret_cast<T *>(slb + ph.lds_slots * kLanes) + l * (2 * NW * kLanes);   // this wave's window
 
     constexpr int RM = MI > 0 ? MI : 1;
     T fv[BS][RM], bv[BS][RM];
@@ -494,7 +627,10 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
         if (MODE != kBackward) stage_steps<T>(ph.f, gt, l, l + 1, j, svf, slf);
         if (MODE != kForward) stage_steps<T>(ph.b, gt, l, l + 1, j, svb, slb);
     }
-    ext_sweep<1, CH, T>(acc1, MODE == kBackward ? ph.b.ext : ph.f.ext, gt + l, j, L, z);
+    const Ext &ext = MODE == kBackward ? ph.b.ext : ph.f.ext;
+    ext_strided<1, CH, T>(acc1, ext, gt + l, j, L, z);
+    if (ext.flat) acc1[0] = ext_split<NW, T>(acc1[0], ext, gt + l, j, z, win);
+    else ext_packed<1, CH, T>(acc1, ext, gt + l, L, z);
     sq[l * kLanes + j] = acc1[0];
     if (CG) {
         srn[l * kLanes + j] = rn1;
@@ -538,7 +674,10 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
                    dev_at<uint64_t>(f->dev, x.smask), dev_at<void>(f->dev, x.sval),
                    dev_at<int32_t>(f->dev, x.ioff), dev_at<uint64_t>(f->dev, x.imask),
                    dev_at<int64_t>(f->dev, x.ivoff), dev_at<int32_t>(f->dev, x.icol),
-                   dev_at<void>(f->dev, x.ival), e.strided(), e.indexed()},
+                   dev_at<void>(f->dev, x.ival),
+                   dev_at<int64_t>(f->dev, x.goff), dev_at<uint16_t>(f->dev, x.lstart),
+                   dev_at<int32_t>(f->dev, x.fcol), dev_at<void>(f->dev, x.fval),
+                   e.strided(), e.indexed(), int64_t(e.fcol.size()) - 1, e.flat},
                dev_at<int32_t>(f->dev, o.int_off), dev_at<void>(f->dev, o.int_val),
                dev_at<int8_t>(f->dev, o.int_lp), i.slots()};
 }
@@ -547,8 +686,9 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
 // workgroup of bs wavefronts per tile (k_rows, one right-hand side only).
 // Automatic choice: k_rows when the colors have few tiles on average (fewer
 // than 1024: a phase would not fill the chip with one wavefront per tile)
-// and most couplings sit in indexed slots (unstructured graphs: each step
-// has many couplings, whose loads k_rows spreads over bs wavefronts).  On
+// and the factor holds its left-over couplings in flat form (unstructured
+// graphs: each step has many couplings, whose loads k_rows spreads over bs
+// wavefronts, and with row splitting evenly over the lanes).  On
 // grids a step has a few strided slots, and k_rows' single chain wavefront
 // after the barrier costs more than it saves (96^3, bs 8: 75.7 against
 // 38.0 us per apply; 1M-point 13-NN graph, bs 2: 300 against 370 us).
@@ -556,9 +696,7 @@ bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
     if (bs > 16 || K != 1 || nr != 1) return false;
     if (f->kernel == HBMC_KERNEL_SWEEP) return false;
     if (f->kernel == HBMC_KERNEL_ROWS) return true;
-    const int64_t strided = f->fext.strided() + f->bext.strided();
-    const int64_t indexed = f->fext.indexed() + f->bext.indexed();
-    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && indexed > strided;
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fext.flat;
 }
 
 template <int BS, typename T, int MI, bool CG, int NR>
@@ -583,14 +721,15 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     const size_t tw = sizeof(T) + sizeof(int32_t);
     size_t lds = 0;
     ph.lds_slots = 0;
+    const size_t split = size_t(BS) * 2 * split_window<BS, T>() * kLanes * sizeof(T);   // k_rows windows
     if (MI == 0) {
         ph.lds_slots = std::max(std::max(f->max_int_slots_f, f->max_int_slots_b), 1);
         const size_t per = size_t(ph.lds_slots) * kLanes * tw;
-        if ((rows ? 2 * per + size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS : WAVES * per) > kMaxLds)
+        if ((rows ? 2 * per + size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + split : WAVES * per) > kMaxLds)
             ph.lds_slots = 0;
     }
     if (rows)
-        lds = size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + 2 * size_t(ph.lds_slots) * kLanes * tw;
+        lds = size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + 2 * size_t(ph.lds_slots) * kLanes * tw + split;
     else
         lds = size_t(WAVES) * ph.lds_slots * kLanes * tw;
     auto run = [&](int c, auto sweep, auto rowk) -> int {

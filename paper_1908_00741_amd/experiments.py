@@ -25,6 +25,12 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
   lane, rows of a lane 1 apart) and hierarchical block multi-color ordering
   of the same problem, FP64: iterations, time and time per iteration (the
   comparison of Section 5's tables, on one GPU);
+- warmstart: the learned warm start on the 96^3 diffusion problem with
+  Gaussian sources, trained from scratch on a short schedule (single-source
+  ICCG solutions combined into targets, Adam on the device); iterations and
+  time to 1e-7 per test source against x0 = 0, the network's inference
+  included, the start scaled by the A-norm-optimal factor (0: fallback to
+  x0 = 0);
 - apply_rate: ic0_apply alone on a named workload, timed with HIP events
   with the caches cold before each call (also the command line used for
   per-workload profiles: ``python -m paper_1908_00741_amd.experiments
@@ -153,6 +159,28 @@ def apply_rate(device, A, bs, w, precision=hbmc.HBMC_F64, kernel=hbmc.HBMC_KERNE
         log(f"[apply {label}] {mode}: {us:.1f} us, {g:.0f} GB/s algorithmic ({g / HBM_PEAK_GBS:.3f} of peak), "
             f"{f.n_colors} colors")
     del f, r, z
+    return out
+
+
+def warmstart(device, N=96, per_diagonal=250, steps=20000, test=50, log=print):
+    """Learned warm start, trained here on a short schedule: per_diagonal
+    single-source solutions per body diagonal, steps Adam steps (batch 256),
+    then test sources (seed 12) solved from x0 = 0 and from the network."""
+    from . import warmstart as wsm
+    t0 = time.perf_counter()
+    ws = wsm.WarmStart(N, device=device)
+    G, S, W, gen = ws.generate_single(per_diagonal)
+    tr = ws.train_combined(G, S, W, steps, 256, 1e-3, log_every=max(1, steps // 4))
+    del G
+    ev = ws.evaluate(inputs.sample_sources(test, 12))
+    out = {"workload": f"diffusion3d {N}^3 lognormal sigma=0.5 seed 10, 4 Gaussian sources, bs 8, w 64, FP64, "
+                       f"tol {ws.tol:g}",
+           "training_solves": gen["solves"], "training_solve_s": gen["seconds"], "steps": steps,
+           "train_s": tr["seconds"], "final_loss": tr["curve"][-1][1] if tr["curve"] else None, **ev,
+           "total_s": round(time.perf_counter() - t0, 1)}
+    log(f"[ext warmstart] {ev['iters_x0_zero']:.1f} -> {ev['iters_warm']:.1f} iterations, "
+        f"{ev['ms_x0_zero']:.2f} -> {ev['ms_warm_incl_inference']:.2f} ms, {ev['speedup']:.3f}x")
+    del ws
     return out
 
 

@@ -52,12 +52,12 @@ class OrderInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("x0_zero", C.c_int32), ("check_every", C.c_int32),
-                ("use_graph", C.c_int32), ("record_history", C.c_int32)]
+                ("use_graph", C.c_int32), ("record_history", C.c_int32), ("x0_scale", C.c_int32)]
 
 
 class SolveStats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("rel_res", C.c_double),
-                ("true_rel_res", C.c_double)]
+                ("true_rel_res", C.c_double), ("x0_scale", C.c_double)]
 
 
 _lib = None
@@ -447,6 +447,7 @@ class Stats:
     status: int
     rel_res: float
     true_rel_res: float
+    x0_scale: float = 1.0
 
 
 def workspace(f: Factor, nrhs: int = 1, device="cuda"):
@@ -458,10 +459,12 @@ def workspace(f: Factor, nrhs: int = 1, device="cuda"):
 
 def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 10000,
                nrhs: int = 1, x0_zero: bool | None = None, check_every: int = 0,
-               use_graph: bool = True, history: bool = False, work=None, stream=None):
+               use_graph: bool = True, history: bool = False, work=None, stream=None,
+               x0_scale: bool = False):
     """Solves A x = b (original numbering, device FP64).  Returns (x, stats),
     or (x, stats, hist) with history=True; stats is a list (system-major,
-    then right-hand side) unless there is one system and one right-hand side."""
+    then right-hand side) unless there is one system and one right-hand side.
+    x0_scale: start from c x with the A-norm-optimal c (0 falls back to x = 0)."""
     import torch
     _vec_check(b, f.n, nrhs, "b")
     if x is None:
@@ -472,13 +475,13 @@ def iccg_solve(f: Factor, m: Matrix, b, x=None, tol: float = 1e-7, maxit: int = 
     if work is None:
         work = workspace(f, nrhs, b.device)
     opts = SolveOpts(1 if x0_zero else 0, int(check_every), 1 if use_graph else 0,
-                     1 if history else 0)
+                     1 if history else 0, 1 if x0_scale else 0)
     nst = f.n_systems * nrhs
     stats = (SolveStats * nst)()
     code = lib().iccg_solve(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
                             C.byref(opts), stats, _dptr(work), work.numel(), _stream(stream))
     _check("iccg_solve", code, ok=(HBMC_OK, HBMC_ENOCONV))
-    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res) for s in stats]
+    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res, s.x0_scale) for s in stats]
     if history:
         h = np.empty(out[0].iters + 1)
         _check("iccg_history", lib().iccg_history(_dptr(work), work.numel(), f.handle, _ptr(h),
@@ -498,13 +501,13 @@ def iccg_solve_noalloc(f: Factor, m: Matrix, b, x, tol: float = 1e-7, maxit: int
     overwritten with the solution).  Returns stats as iccg_solve does."""
     _vec_check(b, f.n, nrhs, "b")
     _vec_check(x, f.n, nrhs, "x")
-    opts = SolveOpts(1 if x0_zero else 0, int(check_every), 0, 0)
+    opts = SolveOpts(1 if x0_zero else 0, int(check_every), 0, 0, 0)
     nst = f.n_systems * nrhs
     stats = (SolveStats * nst)()
     code = lib().iccg_solve_noalloc(f.handle, m.handle, _dptr(b), _dptr(x), nrhs, float(tol), int(maxit),
                                     C.byref(opts), stats, _stream(stream))
     _check("iccg_solve_noalloc", code, ok=(HBMC_OK, HBMC_ENOCONV))
-    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res) for s in stats]
+    out = [Stats(s.iters, s.status, s.rel_res, s.true_rel_res, s.x0_scale) for s in stats]
     return out[0] if nst == 1 else out
 
 

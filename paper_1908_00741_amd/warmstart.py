@@ -6,7 +6,14 @@ Gaussian sources with 12 parameters theta (positions along the cube's body
 diagonals, widths, amplitudes).  A network x0 = s * MLP(theta) is trained on
 solutions that the solver itself produced, then gives CG its start vector;
 CG still stops on its own residual test ||b - A x|| / ||b|| < tol, so the
-accuracy is that of the plain solver, and x0 = 0 remains the fallback.
+accuracy is that of the plain solver.  The solver scales the network's x0
+by c = (b, x0) / (x0, A x0), the multiple of x0 closest to the solution in
+the A-norm (the norm CG minimizes), so the start is never worse than x = 0
+in that norm; when (b, x0) <= 0 the scale is 0 and the solve starts from
+x = 0, the fallback.  (The test ||b - A x0|| >= ||b|| would reject nearly
+every guess of the network: its bfloat16 storage adds high-frequency error
+that raises the residual above ||b|| while the A-norm error, and the
+iteration count, still improve.)
 
 The right-hand sides, the solves, the network's products, loss and Adam
 steps all run in the library's kernels (hbmc.h, hbmc_mlp.h).
@@ -69,7 +76,7 @@ class WarmStart:
             x, st = self.solver.solve(b, self.x, tol=self.tol, x0_zero=True, work=self.work)
         else:
             self.x.copy_(x0)
-            x, st = self.solver.solve(b, self.x, tol=self.tol, x0_zero=False, work=self.work)
+            x, st = self.solver.solve(b, self.x, tol=self.tol, x0_zero=False, work=self.work, x0_scale=True)
         return x, st
 
     def generate(self, thetas, scale_from=64):
@@ -224,9 +231,11 @@ class WarmStart:
             _, s1 = self.solve(th, self.predict(th))
             torch.cuda.synchronize()
             t2 = time.perf_counter()
-            rows.append((s0.iters, s1.iters, t1 - t0, t2 - t1, s0.true_rel_res, s1.true_rel_res))
+            rows.append((s0.iters, s1.iters, t1 - t0, t2 - t1, s0.true_rel_res, s1.true_rel_res, s1.x0_scale))
         r = np.array(rows)
         return {"count": len(rows), "iters_x0_zero": float(r[:, 0].mean()), "iters_warm": float(r[:, 1].mean()),
+                "x0_scale_mean": round(float(r[:, 6].mean()), 4), "x0_scale_min": round(float(r[:, 6].min()), 4),
+                "fallbacks_to_zero": int((r[:, 6] == 0.0).sum()),
                 "ms_x0_zero": round(float(r[:, 2].mean()) * 1e3, 3),
                 "ms_warm_incl_inference": round(float(r[:, 3].mean()) * 1e3, 3),
                 "speedup": round(float(r[:, 2].sum() / r[:, 3].sum()), 3),

@@ -321,6 +321,31 @@ def test_apply_full_size_knn(torch, orc, knn1m, precision):
     assert np.all(z[dummy] == 0.0)
 
 
+def test_solve_scaled_start(torch, orc):
+    """x0_scale: the solver starts from c x0, c = (b, x0) / (x0, A x0),
+    against the oracle's scaled start (c to 1e-12) and its PCG from c x0 at
+    10 iterations (1e-10); a guess pointing away from the solution falls
+    back to x = 0, bit for bit the zero-start solve."""
+    print("case scaled_start", flush=True)
+    A = inputs.diffusion3d(20, 1.0, 2)
+    b = inputs.uniform_rhs(A.n, 3)
+    s = orc.system(A, 8, 64)
+    xs = s.solve(b, tol=1e-14).x
+    rng = np.random.default_rng(4)
+    x0 = 0.8 * xs + 0.1 * np.abs(xs).max() * rng.standard_normal(A.n)
+    c_ref, y_ref = orc.scaled_start(A, b, x0)
+    ref = s.solve(b, x0=y_ref, tol=0.0, maxit=10)
+    solver = hbmc.Solver.setup(A, 8, 64)
+    bd = _dev(torch, b)
+    x, st = solver.solve(bd, _dev(torch, x0), tol=0.0, maxit=10, x0_zero=False, x0_scale=True)
+    assert abs(st.x0_scale - c_ref) <= 1e-12 * abs(c_ref)
+    assert np.linalg.norm(_host(x) - ref.x) <= 1e-10 * np.linalg.norm(ref.x)
+    x1, st1 = solver.solve(bd, _dev(torch, -xs), tol=0.0, maxit=10, x0_zero=False, x0_scale=True)
+    x2, st2 = solver.solve(bd, None, tol=0.0, maxit=10)
+    assert st1.x0_scale == 0.0 and st2.x0_scale == 0.0
+    assert np.array_equal(_host(x1), _host(x2))
+
+
 def test_solve_zero_rhs(torch):
     A = inputs.grid2d_5pt(16)
     solver = hbmc.Solver.setup(A, 4, 8)

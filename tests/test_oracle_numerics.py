@@ -389,3 +389,37 @@ def test_apply_f32_matches_exact_binary32_emulation(orc):
                 acc = f32(acc + f32(f32(Fraction(float(s.fac[pos[(j, i)]]))) * zz[j]))
         zz[i] = f32(y[i] - f32(dinv[i] * acc))
     assert [float(v) for v in zz] == list(z)
+
+
+def test_scaled_start_pins(orc):
+    """The warm start's scaled start c x0, c = (b, x0) / (x0, A x0): the exact
+    solution keeps c = 1; c is the minimum of the A-norm error over multiples
+    of x0 (checked against the error's values, computed with scipy, at
+    neighbouring multiples and against the closed-form minimum over a fine
+    grid); the error is never above that of the zero start; a guess pointing
+    away from the solution falls back to 0; c scales inversely with x0."""
+    A = inputs.diffusion3d(12, 1.0, 2)
+    S = A.to_scipy()
+    b = inputs.uniform_rhs(A.n, 3)
+    xs = spla.spsolve(S.tocsc(), b)
+    c, y = orc.scaled_start(A, b, xs)
+    assert abs(c - 1.0) < 1e-12 and np.allclose(y, xs, rtol=1e-12, atol=0)
+    rng = np.random.default_rng(1)
+    x0 = 0.7 * xs + 0.2 * rng.standard_normal(A.n) * np.abs(xs).max()
+
+    def err(t):
+        e = t * x0 - xs
+        return float(e @ (S @ e))
+
+    c, y = orc.scaled_start(A, b, x0)
+    assert np.array_equal(y, c * x0)
+    grid = np.linspace(0.0, 2.0, 20001)
+    best = grid[np.argmin([err(t) for t in grid])]
+    assert abs(best - c) <= 1e-4
+    for d in (1e-3, -1e-3, 0.1, -0.1):
+        assert err(c) <= err(c + d)
+    assert err(c) <= err(0.0)
+    c0, y0 = orc.scaled_start(A, b, -xs)
+    assert c0 == 0.0 and not np.any(y0)
+    c3, y3 = orc.scaled_start(A, b, 3.0 * x0)
+    assert abs(c3 * 3.0 - c) <= 1e-14 * c and np.allclose(y3, y, rtol=1e-14, atol=0)
