@@ -61,6 +61,7 @@ typedef struct hbmc_order_s hbmc_order_t;
 typedef struct hbmc_factor_s hbmc_factor_t;
 typedef struct hbmc_matrix_s hbmc_matrix_t;
 typedef struct hbmc_revalue_s hbmc_revalue_t;
+typedef struct hbmc_dbuild_s hbmc_dbuild_t;
 
 /* Message of the last error raised on the calling thread ("" if none). */
 const char *hbmc_last_error(void);
@@ -346,6 +347,48 @@ int ic0_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, 
  * IC(0) factor or omega outside (0, 2).  Synchronous. */
 int ssor_refactor(hbmc_factor_t *f, const hbmc_revalue_t *rv, const double *val, double omega, void *stream);
 int hbmc_matrix_revalue(hbmc_matrix_t *m, const hbmc_revalue_t *rv, const double *val, void *stream);
+
+/* ---- the factor and the matrix built on the device ---------------------------
+ * The setup of ic0_factor and hbmc_matrix_create done by GPU kernels from a
+ * CSR matrix in device memory and an ordering from hbmc_order (blocking and
+ * coloring stay on the host; Section 4.4.1 asks for a parallel reordering):
+ * Abar = P A P^T (Section 3, eq. "AB"), its lower pattern, IC(0) (Section
+ * 2, eq. "ILU"; the host's arithmetic in the host's order), and the
+ * sliced-ELL layouts (Section 4.4.2) of the substitutions and of the SpMV.
+ * The device images are byte for byte those of ic0_factor + upload and
+ * hbmc_matrix_create + upload for the same order, matrix and precision.
+ * Single systems only (not hbmc_order_batch orderings); IC(0) only (not the
+ * SSOR splitting).
+ *   1. hbmc_device_build_bytes(order, nnz, &bytes): device workspace for a
+ *      CSR with nnz entries; the caller allocates it (256-byte aligned).
+ *   2. hbmc_device_build(order, rowptr, col, val, nnz, precision, shift,
+ *      work, work_bytes, stream, &b): rowptr (int64[n+1]), col (int32[nnz]),
+ *      val (FP64[nnz]) in device memory, in the conventions of this header
+ *      (checked on the device: sorted in-range columns, symmetric pattern
+ *      and values, positive diagonal; HBMC_EINVAL / HBMC_ENOTSYM /
+ *      HBMC_EDIAG); HBMC_EBREAKDOWN on a pivot not > 0; HBMC_EINVAL when a
+ *      row has more than 64 couplings in one layout group (the host build
+ *      takes any).  Computes Abar, IC(0) and the layouts' sizes in the
+ *      workspace; synchronous.  The order must outlive b.
+ *   3. hbmc_device_build_create(b, &f, &m): the factor and matrix handles;
+ *      hbmc_factor_device_bytes / hbmc_matrix_device_bytes give their image
+ *      sizes.
+ *   4. hbmc_device_build_fill(b, f, m, f_dev, f_bytes, m_dev, m_bytes,
+ *      work, stream): writes both images into caller-allocated device
+ *      buffers (256-byte aligned); f and m are then ready for ic0_apply,
+ *      iccg_solve and the rest, like uploaded handles.  Synchronous.
+ * hbmc_factor_export of such a factor copies d and L from the workspace,
+ * which must still hold them; hbmc_factor_image / hbmc_matrix_image and
+ * the ..._upload calls refuse these handles (their images live on the
+ * device only).  Destroy b with hbmc_device_build_destroy (f and m stay). */
+int hbmc_device_build_bytes(const hbmc_order_t *order, int64_t nnz, size_t *bytes);
+int hbmc_device_build(const hbmc_order_t *order, const int64_t *rowptr, const int32_t *col,
+                      const double *val, int64_t nnz, int32_t precision, double shift, void *work,
+                      size_t work_bytes, void *stream, hbmc_dbuild_t **out);
+int hbmc_device_build_create(const hbmc_dbuild_t *b, hbmc_factor_t **f, hbmc_matrix_t **m);
+int hbmc_device_build_fill(const hbmc_dbuild_t *b, hbmc_factor_t *f, hbmc_matrix_t *m, void *f_dev,
+                           size_t f_bytes, void *m_dev, size_t m_bytes, void *work, void *stream);
+void hbmc_device_build_destroy(hbmc_dbuild_t *b);
 
 /* ---- smoother ----------------------------------------------------------------
  * hbmc_smooth: sweeps steps of  x <- x + c M^-1 (b - Abar x)  (Section 2: the

@@ -812,6 +812,7 @@ void hbmc::release_graphs(hbmc_factor_s *f) {
 extern "C" int hbmc_matrix_upload(hbmc_matrix_t *m, void *dev, size_t bytes, void *stream) {
     clear_error();
     if (!m || !dev) return fail(HBMC_EINVAL, "null argument");
+    if (m->device_built) return fail(HBMC_EINVAL, "a matrix built on the device is already uploaded");
     if (bytes < m->image.bytes.size())
         return fail(HBMC_EINVAL, "device buffer too small (%zu < %zu)", bytes, m->image.bytes.size());
     if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(HBMC_EINVAL, "device buffer not 256-byte aligned");

@@ -568,7 +568,10 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
                 return fail(HBMC_EINVAL, "a (tile, step) group has more than 65535 couplings to other colors");
             }
             f->fext.flat = f->bext.flat = flat;
+            for (auto [e, c] : {std::pair{&f->fext, &f->fcnt}, std::pair{&f->bext, &f->bcnt}})
+                *c = LayoutCounts{e->strided(), e->indexed(), int64_t(e->fcol.size()) - 1, e->left, flat};
         }
+        f->nnz_lower = int64_t(f->lcol.size());
         for (Sell *sl : {&f->fint, &f->bint}) {   // the padding slot
             sl->val.resize(sl->val.size() + kTileLanes, 0.0);
             sl->col.resize(sl->col.size() + kTileLanes, -1);
@@ -630,6 +633,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
             t.int_off = im.add(i.off);
             t.int_lp = im.add(i.col);
             t.int_val = precision == HBMC_F64 ? im.add(i.val) : im.add(cast<float>(i.val));
+            t.int_slots = i.slots();
         };
         f->off_dinv = precision == HBMC_F64 ? im.add(dinv) : im.add(cast<float>(dinv));
         f->off_perm = im.add(f->perm);
@@ -663,7 +667,8 @@ extern "C" int ssor_factor(const hbmc_order_t *o, const int64_t *rowptr, const i
 extern "C" int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lower_rowptr,
                                   int32_t *lower_col, double *lower_val, int64_t *lower_nnz) {
     if (!f) return fail(HBMC_EINVAL, "null handle");
-    if (lower_nnz) *lower_nnz = int64_t(f->lcol.size());
+    if (lower_nnz) *lower_nnz = f->nnz_lower;
+    if (f->device_built) return device_export(f, d, lower_rowptr, lower_col, lower_val);
     if (d) std::copy(f->d.begin(), f->d.end(), d);
     if (lower_rowptr) std::copy(f->lrp.begin(), f->lrp.end(), lower_rowptr);
     if (lower_col) std::copy(f->lcol.begin(), f->lcol.end(), lower_col);
@@ -673,6 +678,7 @@ extern "C" int hbmc_factor_export(const hbmc_factor_t *f, double *d, int64_t *lo
 
 extern "C" int hbmc_factor_image(const hbmc_factor_t *f, void *host, size_t bytes) {
     if (!f || !host) return fail(HBMC_EINVAL, "null argument");
+    if (f->device_built) return fail(HBMC_EINVAL, "a factor built on the device has no host image");
     if (bytes < f->image.bytes.size())
         return fail(HBMC_EINVAL, "buffer too small (%zu < %zu)", bytes, f->image.bytes.size());
     std::memcpy(host, f->image.bytes.data(), f->image.bytes.size());
@@ -681,6 +687,7 @@ extern "C" int hbmc_factor_image(const hbmc_factor_t *f, void *host, size_t byte
 
 extern "C" int hbmc_matrix_image(const hbmc_matrix_t *m, void *host, size_t bytes) {
     if (!m || !host) return fail(HBMC_EINVAL, "null argument");
+    if (m->device_built) return fail(HBMC_EINVAL, "a matrix built on the device has no host image");
     if (bytes < m->image.bytes.size())
         return fail(HBMC_EINVAL, "buffer too small (%zu < %zu)", bytes, m->image.bytes.size());
     std::memcpy(host, m->image.bytes.data(), m->image.bytes.size());
@@ -689,7 +696,7 @@ extern "C" int hbmc_matrix_image(const hbmc_matrix_t *m, void *host, size_t byte
 
 extern "C" int hbmc_factor_device_bytes(const hbmc_factor_t *f, size_t *bytes) {
     if (!f || !bytes) return fail(HBMC_EINVAL, "null argument");
-    *bytes = f->image.bytes.size();
+    *bytes = f->device_built ? f->dev_image_bytes : f->image.bytes.size();
     return HBMC_OK;
 }
 
@@ -772,7 +779,7 @@ extern "C" int hbmc_matrix_create(const hbmc_order_t *o, const int64_t *rowptr, 
 
 extern "C" int hbmc_matrix_device_bytes(const hbmc_matrix_t *m, size_t *bytes) {
     if (!m || !bytes) return fail(HBMC_EINVAL, "null argument");
-    *bytes = m->image.bytes.size();
+    *bytes = m->image_bytes();
     return HBMC_OK;
 }
 

@@ -88,6 +88,9 @@ int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *str
                  const int32_t *done, const ApplyCg *cg, int K, bool fwd_only = false);
 // Right-hand sides per wavefront (NR) used for K right-hand sides.
 int rhs_tile(const ::hbmc_factor_s *f, int K);
+// hbmc_factor_export of a factor built on the device (copies from the
+// build workspace; synchronous).
+int device_export(const ::hbmc_factor_s *f, double *d, int64_t *lrp, int32_t *lcol, double *lval);
 // Destroys the hipGraph executables cached by iccg_solve for this factor.
 void release_graphs(::hbmc_factor_s *f);
 // Unique id for each upload of a device image (keys the graph cache).
@@ -190,6 +193,8 @@ struct ImageBuilder {
 
 }  // namespace hbmc
 
+struct hbmc_dbuild_s;
+
 struct hbmc_order_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, nsys = 1;
     int64_t n_pad = 0, nblocks = 0;
@@ -206,10 +211,22 @@ struct PackedOffsets {
     size_t goff, lstart, fcol, fval;   // flat form only
 };
 
+// What the launchers need to know of one direction's coupling layout
+// (host builds take it from their Packed arrays, device builds from the
+// counts computed on the device).
+struct LayoutCounts {
+    int64_t strided = 0;   // strided slots: the padding slot's index
+    int64_t indexed = 0;   // indexed slots: the padding slot's index
+    int64_t fpad = 0;      // flat form: the padding entry's index
+    int64_t left = 0;      // left-over couplings
+    bool flat = false;     // the image holds the flat form
+};
+
 // Offsets of one triangular direction.
 struct TriOffsets {
     PackedOffsets ext;                  // per (tile, step): couplings to other colors
     size_t int_off, int_val, int_lp;    // per (tile, step): couplings inside the level-1 block
+    int64_t int_slots;                  // in-block slots (the padding slot's index)
 };
 
 struct hbmc_factor_s {
@@ -235,6 +252,13 @@ struct hbmc_factor_s {
     // substitution layout
     hbmc::Packed fext, bext;   // forward: L to earlier colors; backward: U to later colors
     hbmc::Sell fint, bint;   // inside level-1 blocks; col = source step (0..bs-1)
+    LayoutCounts fcnt, bcnt;   // of fext, bext
+    int64_t nnz_lower = 0;     // entries of L
+    // built on the device (hbmc_device_build): no host image; the image's
+    // size, and where d and L stay in the build workspace (for export)
+    bool device_built = false;
+    size_t dev_image_bytes = 0;
+    const void *dev_d = nullptr, *dev_lrp = nullptr, *dev_lcol = nullptr, *dev_lval = nullptr;
     int32_t max_int_slots_f = 0, max_int_slots_b = 0;   // per tile, summed over steps
     int32_t max_int_step_f = 0, max_int_step_b = 0;     // per (tile, step)
     // device image
@@ -287,4 +311,7 @@ struct hbmc_matrix_s {
     void *dev = nullptr;
     size_t dev_bytes = 0;
     uint64_t uid = 0;
+    bool device_built = false;   // built on the device: no host image
+    size_t dev_image_bytes = 0;
+    size_t image_bytes() const { return device_built ? dev_image_bytes : image.bytes.size(); }
 };

@@ -49,6 +49,7 @@ int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void 
 extern "C" int hbmc_factor_upload(hbmc_factor_t *f, void *dev, size_t bytes, void *stream) {
     clear_error();
     if (!f || !dev) return fail(HBMC_EINVAL, "null argument");
+    if (f->device_built) return fail(HBMC_EINVAL, "a factor built on the device is already uploaded");
     if (bytes < f->image.bytes.size())
         return fail(HBMC_EINVAL, "device buffer too small (%zu < %zu)", bytes, f->image.bytes.size());
     if (reinterpret_cast<uintptr_t>(dev) % 256) return fail(HBMC_EINVAL, "device buffer not 256-byte aligned");

@@ -668,7 +668,7 @@ const P *dev_at(const void *base, size_t off) {
     return reinterpret_cast<const P *>(static_cast<const uint8_t *>(base) + off);
 }
 
-Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const Sell &i) {
+Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const LayoutCounts &e) {
     const PackedOffsets &x = o.ext;
     return Tri{Ext{dev_at<int32_t>(f->dev, x.soff), dev_at<int32_t>(f->dev, x.sbase),
                    dev_at<uint64_t>(f->dev, x.smask), dev_at<void>(f->dev, x.sval),
@@ -677,9 +677,9 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const Packed &e, const
                    dev_at<void>(f->dev, x.ival),
                    dev_at<int64_t>(f->dev, x.goff), dev_at<uint16_t>(f->dev, x.lstart),
                    dev_at<int32_t>(f->dev, x.fcol), dev_at<void>(f->dev, x.fval),
-                   e.strided(), e.indexed(), int64_t(e.fcol.size()) - 1, e.flat},
+                   e.strided, e.indexed, e.fpad, e.flat},
                dev_at<int32_t>(f->dev, o.int_off), dev_at<void>(f->dev, o.int_val),
-               dev_at<int8_t>(f->dev, o.int_lp), i.slots()};
+               dev_at<int8_t>(f->dev, o.int_lp), o.int_slots};
 }
 
 // Which kernel runs the phases: one wavefront per tile (k_sweep) or one
@@ -696,7 +696,7 @@ bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
     if (bs > 16 || K != 1 || nr != 1) return false;
     if (f->kernel == HBMC_KERNEL_SWEEP) return false;
     if (f->kernel == HBMC_KERNEL_ROWS) return true;
-    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fext.flat;
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fcnt.flat;
 }
 
 template <int BS, typename T, int MI, bool CG, int NR>
@@ -713,8 +713,8 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     ph.K = K;
     ph.G = (K + NR - 1) / NR;
     ph.ptiles = f->tile_base[f->nc] * NR;
-    ph.f = tri_of(f, f->fwd, f->fext, f->fint);
-    ph.b = tri_of(f, f->bwd, f->bext, f->bint);
+    ph.f = tri_of(f, f->fwd, f->fcnt);
+    ph.b = tri_of(f, f->bwd, f->bcnt);
     ph.dinv = dev_at<void>(f->dev, f->off_dinv);
     ph.done = done;
     ph.cg = cg;

@@ -460,9 +460,18 @@ def _main():
     ap.add_argument("--kernel", choices=["auto", "sweep", "rows"], default="auto")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--modes", default="cold,warm")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="first run dst = 2 * src on 256 MiB tensors, a kernel that reads and writes exactly "
+                         "256 MiB, for scaling hardware byte counters")
     a = ap.parse_args()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(0)
+    if a.calibrate:
+        src = torch.ones(1 << 25, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     A = WORKLOADS[a.workload]()
     prec = hbmc.HBMC_F64 if a.precision == "f64" else hbmc.HBMC_F32
     kern = {"auto": hbmc.HBMC_KERNEL_AUTO, "sweep": hbmc.HBMC_KERNEL_SWEEP, "rows": hbmc.HBMC_KERNEL_ROWS}[a.kernel]

@@ -35,6 +35,8 @@ SYMBOLS = (
     "hbmc_factor_image", "hbmc_matrix_image", "hbmc_set_num_threads",
     "hbmc_revalue_create", "hbmc_revalue_device_bytes", "hbmc_revalue_upload", "hbmc_revalue_destroy",
     "ic0_refactor", "ssor_refactor", "hbmc_matrix_revalue",
+    "hbmc_device_build_bytes", "hbmc_device_build", "hbmc_device_build_create", "hbmc_device_build_fill",
+    "hbmc_device_build_destroy",
 )
 
 
@@ -114,6 +116,12 @@ def lib():
         L.ic0_refactor.argtypes = [P, P, P, f64, P]
         L.ssor_refactor.argtypes = [P, P, P, f64, P]
         L.hbmc_matrix_revalue.argtypes = [P, P, P, P]
+        L.hbmc_device_build_bytes.argtypes = [P, i64, P]
+        L.hbmc_device_build.argtypes = [P, P, P, P, i64, i32, f64, P, sz, P, P]
+        L.hbmc_device_build_create.argtypes = [P, P, P]
+        L.hbmc_device_build_fill.argtypes = [P, P, P, P, sz, P, sz, P, P]
+        L.hbmc_device_build_destroy.argtypes = [P]
+        L.hbmc_device_build_destroy.restype = None
         _lib = L
     return _lib
 
@@ -375,6 +383,55 @@ def hbmc_matrix_create(order: Order, A) -> Matrix:
     _check("hbmc_matrix_create", lib().hbmc_matrix_create(order.handle, _ptr(rp), _ptr(ci), _ptr(v),
                                                           C.byref(h)))
     return Matrix(h, order)
+
+
+@dataclass
+class DeviceBuild:
+    """Factor and matrix built by hbmc_device_build from a CSR in device
+    memory (the device images are those of the host build, byte for byte);
+    work holds d and L for Factor.export."""
+    factor: Factor
+    matrix: Matrix
+    work: object
+    seconds: dict
+
+
+def device_build(order: Order, A=None, precision: int = HBMC_F64, shift: float = 0.0, device="cuda",
+                 csr_dev=None, stream=None) -> DeviceBuild:
+    """IC(0) factor and matrix of A under order, set up on the device.  A is
+    a host CSR (copied to the device first, timed apart) or csr_dev =
+    (rowptr, col, val) device tensors (int64, int32, float64)."""
+    import time
+    import torch
+    t0 = time.perf_counter()
+    if csr_dev is None:
+        rp, ci, v = _csr_arrays(A)
+        csr_dev = (torch.from_numpy(rp).to(device), torch.from_numpy(ci).to(device), torch.from_numpy(v).to(device))
+        torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rp_d, ci_d, v_d = csr_dev
+    nnz = int(ci_d.numel())
+    b = C.c_size_t(0)
+    _check("hbmc_device_build_bytes", lib().hbmc_device_build_bytes(order.handle, nnz, C.byref(b)))
+    work = torch.empty(max(b.value, 256), dtype=torch.uint8, device=device)
+    h = C.c_void_p()
+    _check("hbmc_device_build", lib().hbmc_device_build(order.handle, _dptr(rp_d), _dptr(ci_d), _dptr(v_d), nnz,
+                                                        int(precision), float(shift), _dptr(work), work.numel(),
+                                                        _stream(stream), C.byref(h)))
+    try:
+        fh, mh = C.c_void_p(), C.c_void_p()
+        _check("hbmc_device_build_create", lib().hbmc_device_build_create(h, C.byref(fh), C.byref(mh)))
+        f, m = Factor(fh, order, precision), Matrix(mh, order)
+        fdev = torch.empty(max(f.device_bytes(), 256), dtype=torch.uint8, device=device)
+        mdev = torch.empty(max(m.device_bytes(), 256), dtype=torch.uint8, device=device)
+        _check("hbmc_device_build_fill", lib().hbmc_device_build_fill(h, fh, mh, _dptr(fdev), fdev.numel(),
+                                                                      _dptr(mdev), mdev.numel(), _dptr(work),
+                                                                      _stream(stream)))
+        f.dev, m.dev = fdev, mdev
+    finally:
+        lib().hbmc_device_build_destroy(h)
+    t2 = time.perf_counter()
+    return DeviceBuild(f, m, work, {"csr_upload": t1 - t0, "build": t2 - t1})
 
 
 def _vec_check(t, n, nrhs, name):
