@@ -29,6 +29,7 @@
 #include <mutex>
 #include <vector>
 
+#include "fold.h"
 #include "hbmc_internal.h"
 
 using namespace hbmc;
@@ -306,12 +307,6 @@ __global__ void __launch_bounds__(kBlock) k_init_r(int64_t n, int K, const doubl
     }
     store_part<NR>(part, np, K, sb);
     store_part<NR>(part + int64_t(K) * np, np, K, sr);
-}
-
-// one stopped (system, right-hand side) more; the last one raises the
-// all-stopped flag
-__device__ inline void count_done(int32_t *ndone, int32_t *alldone, int total) {
-    if (atomicAdd(ndone, 1) + 1 == total) *alldone = 1;
 }
 
 // part partials of (b, x0) and (x0, A x0) (q = A x0), for the scaling of a
@@ -609,8 +604,10 @@ __global__ void __launch_bounds__(kBlock) k_zero(int64_t n, double *__restrict__
     if (i < n) v[i] = 0.0;
 }
 
-__global__ void k_zero_int(int32_t *a, int n) {
-    if (int(threadIdx.x) < n) a[threadIdx.x] = 0;
+// the solve's counters and flags zero; the words that carry alpha unpublished
+__global__ void k_init_flags(int32_t *ints, uint64_t *words) {
+    if (threadIdx.x < 4) ints[threadIdx.x] = 0;
+    for (int i = int(threadIdx.x); i < kFoldWords; i += int(blockDim.x)) words[i] = kNotYet;
 }
 
 template <class P>
@@ -653,6 +650,8 @@ struct Work {
     double *bb, *xb, *r, *z, *p[2], *q, *part_g, *part_rr, *part_rz, *resid, *hist;
     CgState *st;
     int32_t *ndone, *alldone;
+    int32_t *err;      // a wait for alpha inside a kernel ran past its time limit
+    uint64_t *awords;  // [kFoldWords] alpha published inside a kernel (both parities, replicated)
     int64_t np;        // part partial slots per right-hand side (parts * pmul)
     int32_t pmul;      // sub-blocks per part of the vector kernels
     int64_t ptiles;    // tile partial slots per right-hand side
@@ -676,7 +675,7 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
     const size_t sts = up(size_t(f->nsys) * K * sizeof(CgState));
     const size_t res = up(size_t(f->nsys) * K * sizeof(double));
     const size_t hist = size_t(kHistLen) * sizeof(double);
-    const size_t total = hist + 7 * vec + pg + 2 * tp + sts + 256 + res;
+    const size_t total = hist + 7 * vec + pg + 2 * tp + sts + 256 + kFoldWords * sizeof(uint64_t) + res;
     if (w && base) {
         auto *b = static_cast<uint8_t *>(base);
         w->hist = reinterpret_cast<double *>(b);   // first: its place does not depend on K
@@ -689,7 +688,11 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
         w->part_rz = reinterpret_cast<double *>(b + a); a += tp;
         w->st = reinterpret_cast<CgState *>(b + a); a += sts;
         w->ndone = reinterpret_cast<int32_t *>(b + a);
-        w->alldone = w->ndone + 1; a += 256;
+        w->alldone = w->ndone + 1;
+        w->err = w->ndone + 2;
+        a += 256;
+        w->awords = reinterpret_cast<uint64_t *>(b + a);
+        a += kFoldWords * sizeof(uint64_t);
         w->resid = reinterpret_cast<double *>(b + a);
         w->hist_len = kHistLen;
         w->pmul = sub_blocks(vec_nr(K));
@@ -737,10 +740,27 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
         VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);
         VEC_LAUNCH(k_spmv_dot, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     }
-    hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, w.ndone,
-                       w.alldone);
-    HIP_TRY(hipGetLastError());
-    const ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz};
+    ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz,
+               nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, nullptr};
+    if (K == 1 && f->nsys == 1 && !use_rows(f, f->bs, 1, 1)) {
+        // one system, one right-hand side, one wavefront per tile: alpha is
+        // computed by the first phase of the preconditioning step (fold.h)
+        // instead of a kernel of its own (128^3, bs 8: 6.7 us less per
+        // iteration).  Not with one workgroup per tile, where it measured
+        // slower (1M-point 13-NN graph: 134.1 against 137.3 ms per solve).
+        cg.stw = w.st;
+        cg.fpart = w.part_g;
+        cg.fnp = w.np;
+        cg.fwords = w.awords;
+        cg.fparity = parity;
+        cg.ferr = w.err;
+        cg.ndone = w.ndone;
+        cg.alldone = w.alldone;
+    } else {
+        hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, w.ndone,
+                           w.alldone);
+        HIP_TRY(hipGetLastError());
+    }
     int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg, K);
     if (st) return st;
     hipLaunchKernelGGL(k_fin_rr_beta, dim3(nst), dim3(kFin), 0, s, w.part_rr, w.part_rz, w.ptiles, w.nr, K,
@@ -779,11 +799,11 @@ int get_graph(hbmc_factor_s *f, const hbmc_matrix_s *A, const Mat &m, const Work
     for (int k = 0; k < iters && st == HBMC_OK; ++k) st = enqueue_iteration(f, m, w, cs, history, k & 1);
     hipGraph_t graph = nullptr;
     hipError_t e = hipStreamEndCapture(cs, &graph);
-    if (st) { if (graph) hipGraphDestroy(graph); return st; }
+    if (st) { if (graph) (void)hipGraphDestroy(graph); return st; }
     if (e != hipSuccess) return fail(HBMC_EHIP, "hipStreamEndCapture: %s", hipGetErrorString(e));
     hipGraphExec_t exec = nullptr;
     e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    hipGraphDestroy(graph);
+    (void)hipGraphDestroy(graph);
     if (e != hipSuccess) return fail(HBMC_EHIP, "hipGraphInstantiate: %s", hipGetErrorString(e));
     f->graphs.push_back({A->uid, work, key, w.K, w.nr, exec});
     *out = exec;
@@ -802,7 +822,7 @@ int check_ready(const hbmc_factor_s *f, int32_t nrhs) {
 uint64_t hbmc::next_uid() { return g_uid.fetch_add(1); }
 
 void hbmc::release_graphs(hbmc_factor_s *f) {
-    for (auto &gph : f->graphs) hipGraphExecDestroy(static_cast<hipGraphExec_t>(gph.exec));
+    for (auto &gph : f->graphs) (void)hipGraphExecDestroy(static_cast<hipGraphExec_t>(gph.exec));
     f->graphs.clear();
 }
 
@@ -902,7 +922,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     const int32_t *iperm = at<int32_t>(f->dev, f->off_iperm);
     const int32_t *perm = at<int32_t>(f->dev, f->off_perm);
 
-    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, w.ndone, 2);
+    hipLaunchKernelGGL(k_init_flags, dim3(1), dim3(256), 0, s, w.ndone, w.awords);
     hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, b, w.bb);
     if (x0_zero) hipLaunchKernelGGL(k_zero, dim3(ge), dim3(kBlock), 0, s, n * K, w.xb);
     else hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, x, w.xb);
@@ -916,7 +936,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     hipLaunchKernelGGL(k_fin_init, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, tol, maxit,
                        history ? w.hist : nullptr, w.ndone, w.alldone);
     HIP_TRY(hipGetLastError());
-    int32_t hd[2] = {0, 0};
+    int32_t hd[3] = {0, 0, 0};   // stopped count, all-stopped flag, wait time-out
     HIP_TRY(hipMemcpyAsync(hd, w.ndone, sizeof hd, hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
 
@@ -936,6 +956,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
                     if ((st = enqueue_iteration(f, m, w, s, history, parity))) return st;
             HIP_TRY(hipMemcpyAsync(hd, w.ndone, sizeof hd, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
+            if (hd[2]) return fail(HBMC_EHIP, "a wait for alpha inside a kernel timed out");
         }
     }
     // pairs with b = 0 get x = 0; the solution back to the caller's

@@ -78,6 +78,15 @@ struct ApplyCg {
     const int32_t *tile_sys;    // [tiles] system of each tile
     double *part_rr;            // [K][tiles * NR]
     double *part_rz;            // [K][tiles * NR]
+    // one system, one right-hand side: alpha computed in the first phase
+    // (workgroup 0 adds the product's partials fpart[0 .. fnp)), published
+    // in fwords (replicated, by iteration parity fparity)
+    CgState *stw;
+    const double *fpart;
+    int64_t fnp;
+    uint64_t *fwords;
+    int32_t fparity;
+    int32_t *ferr, *ndone, *alldone;
 };
 // Enqueues z = M^-1 r for K right-hand sides ([n_pad][K]) on stream (a
 // hipStream_t).  When done is not null the kernels return at once while
@@ -88,6 +97,9 @@ int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *str
                  const int32_t *done, const ApplyCg *cg, int K, bool fwd_only = false);
 // Right-hand sides per wavefront (NR) used for K right-hand sides.
 int rhs_tile(const ::hbmc_factor_s *f, int K);
+// Whether the phases run as one workgroup per tile (k_rows) rather than one
+// wavefront per tile (k_sweep), for bs, K right-hand sides and tile NR.
+bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr);
 // hbmc_factor_export of a factor built on the device (copies from the
 // build workspace; synchronous).
 int device_export(const ::hbmc_factor_s *f, double *d, int64_t *lrp, int32_t *lcol, double *lval);

@@ -28,6 +28,23 @@ int hbmc::rhs_tile(const hbmc_factor_s *f, int K) {
     return K < 8 ? 4 : 8;
 }
 
+// Which kernel runs the phases: one wavefront per tile (k_sweep) or one
+// workgroup of bs wavefronts per tile (k_rows, one right-hand side only).
+// Automatic choice: k_rows when the colors have few tiles on average (fewer
+// than 1024: a phase would not fill the chip with one wavefront per tile)
+// and the factor holds its left-over couplings in flat form (unstructured
+// graphs: each step has many couplings, whose loads k_rows spreads over bs
+// wavefronts, and with row splitting evenly over the lanes).  On
+// grids a step has a few strided slots, and k_rows' single chain wavefront
+// after the barrier costs more than it saves (96^3, bs 8: 75.7 against
+// 38.0 us per apply; 1M-point 13-NN graph, bs 2: 300 against 370 us).
+bool hbmc::use_rows(const hbmc_factor_s *f, int bs, int K, int nr) {
+    if (bs > 16 || K != 1 || nr != 1) return false;
+    if (f->kernel == HBMC_KERNEL_SWEEP) return false;
+    if (f->kernel == HBMC_KERNEL_ROWS) return true;
+    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fcnt.flat;
+}
+
 int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void *stream,
                        const int32_t *done, const ApplyCg *cg, int K, bool fo) {
     auto s = static_cast<hipStream_t>(stream);

@@ -33,6 +33,7 @@
 #include <cmath>
 #include <vector>
 
+#include "fold.h"
 #include "hbmc_internal.h"
 
 namespace hbmc {
@@ -143,6 +144,7 @@ struct Phase {
     const void *dinv;
     const int32_t *done;  // if set and *done != 0 the phase does nothing
     ApplyCg cg;
+    bool fold;            // CG, first phase, k_sweep: alpha computed here (fold.h)
 };
 
 // Sum over the lanes j' of the wavefront with j' = j mod NR (the lanes of
@@ -513,6 +515,7 @@ template <int BS, typename T, int MODE, int MI, int CH, int WAVES, bool CG, int 
 __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double *__restrict__ r,
                                                           double *__restrict__ z) {
     if (ph.done && *ph.done) return;
+    if (CG && ph.fold && blockIdx.x == 0) fold_alpha(ph.cg);   // every thread, before any return
     // the wavefront index is uniform: say so, so that everything indexed by
     // the tile (slot offsets, strided bases and masks) uses scalar loads
     const int wave = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);
@@ -552,12 +555,42 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
     T acc[BS], dv[BS];
     double rn[BS];   // CG: the updated residual of the lane's rows
     double rr = 0.0;
-    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
+    if constexpr (CG && MODE != kBackward) {
+        // x += alpha p, r -= alpha q on the lane's rows: their loads first,
+        // then (first phase of a folded iteration) the wait for alpha
+        double pv[BS], xv[BS], rv[BS], qv[BS];
 #pragma unroll
-    for (int l = 0; l < BS; ++l) {
-        const int64_t row = rb + int64_t(l) * w;
-        if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
-        acc[l] = row_rhs<T, MODE, CG>(ph, r, z, L.at(row), valid, alpha, rn[l], rr);
+        for (int l = 0; l < BS; ++l) {
+            const int64_t row = rb + int64_t(l) * w, e = L.at(row);
+            dv[l] = static_cast<const T *>(ph.dinv)[row];
+            pv[l] = ph.cg.p[e];
+            xv[l] = ph.cg.x[e];
+            rv[l] = ph.cg.r[e];
+            qv[l] = ph.cg.q[e];
+        }
+        double alpha;
+        if (ph.fold) {
+            const uint64_t v = fold_wait(ph.cg.fwords, ph.cg.fparity, ph.cg.ferr);
+            if (v == kStopped) return;
+            alpha = __longlong_as_double(int64_t(v));
+        } else {
+            alpha = cs->alpha;
+        }
+#pragma unroll
+        for (int l = 0; l < BS; ++l) {
+            const int64_t e = L.at(rb + int64_t(l) * w);
+            const double xn = xv[l] + alpha * pv[l];
+            rn[l] = rv[l] - alpha * qv[l];
+            if (valid) { ph.cg.x[e] = xn; ph.cg.r[e] = rn[l]; rr += rn[l] * rn[l]; }
+            acc[l] = T(rn[l]);
+        }
+    } else {
+#pragma unroll
+        for (int l = 0; l < BS; ++l) {
+            const int64_t row = rb + int64_t(l) * w;
+            if (MODE != kBackward) dv[l] = static_cast<const T *>(ph.dinv)[row];
+            acc[l] = row_rhs<T, MODE, CG>(ph, r, z, L.at(row), valid, 0.0, rn[l], rr);
+        }
     }
     if (CG && MODE != kBackward) {
         rr = rhs_sum<NR>(rr);
@@ -682,23 +715,6 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const LayoutCounts &e)
                dev_at<int8_t>(f->dev, o.int_lp), o.int_slots};
 }
 
-// Which kernel runs the phases: one wavefront per tile (k_sweep) or one
-// workgroup of bs wavefronts per tile (k_rows, one right-hand side only).
-// Automatic choice: k_rows when the colors have few tiles on average (fewer
-// than 1024: a phase would not fill the chip with one wavefront per tile)
-// and the factor holds its left-over couplings in flat form (unstructured
-// graphs: each step has many couplings, whose loads k_rows spreads over bs
-// wavefronts, and with row splitting evenly over the lanes).  On
-// grids a step has a few strided slots, and k_rows' single chain wavefront
-// after the barrier costs more than it saves (96^3, bs 8: 75.7 against
-// 38.0 us per apply; 1M-point 13-NN graph, bs 2: 300 against 370 us).
-bool use_rows(const ::hbmc_factor_s *f, int bs, int K, int nr) {
-    if (bs > 16 || K != 1 || nr != 1) return false;
-    if (f->kernel == HBMC_KERNEL_SWEEP) return false;
-    if (f->kernel == HBMC_KERNEL_ROWS) return true;
-    return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fcnt.flat;
-}
-
 template <int BS, typename T, int MI, bool CG, int NR>
 int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
                   const int32_t *done, const ApplyCg &cg, int K, bool fwd_only) {
@@ -706,7 +722,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     constexpr int WAVES = MI > 0 ? 4 : 1;                 // k_sweep: wavefronts per workgroup
     constexpr int CHR = 16;                               // k_rows: slots per chunk
     if (NR == 1 && K != 1) return fail(HBMC_EINVAL, "right-hand-side tile 1 runs one right-hand side");
-    const bool rows = use_rows(f, BS, K, NR);
+    const bool rows = hbmc::use_rows(f, BS, K, NR);
     Phase ph{};
     ph.w = f->w;
     ph.lw = __builtin_ctz(unsigned(f->w));
@@ -718,6 +734,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     ph.dinv = dev_at<void>(f->dev, f->off_dinv);
     ph.done = done;
     ph.cg = cg;
+    bool first_phase = CG && cg.stw != nullptr;   // the next launch computes alpha
     const size_t tw = sizeof(T) + sizeof(int32_t);
     size_t lds = 0;
     ph.lds_slots = 0;
@@ -739,6 +756,8 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
         ph.ntile = f->tile_base[c + 1] - f->tile_base[c];
         ph.nlane = (ph.row1 - ph.row0) / BS;
         if (ph.ntile == 0) return HBMC_OK;
+        ph.fold = first_phase;
+        first_phase = false;
         if (rows) {
             hipLaunchKernelGGL(rowk, dim3(unsigned(ph.ntile)), dim3(BS * kLanes), lds, s, ph, r, z);
         } else {

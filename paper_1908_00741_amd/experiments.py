@@ -452,7 +452,9 @@ def _main():
     import sys
     import torch
     ap = argparse.ArgumentParser(description="ic0_apply alone on one workload, caches cold before each call")
-    ap.add_argument("what", choices=["apply"])
+    ap.add_argument("what", choices=["apply", "solve"],
+                    help="apply: ic0_apply timed cold and warm; solve: ICCG to 1e-7 (b ~ U[-1, 1], seed 6)")
+    ap.add_argument("--solves", type=int, default=2, help="solve: timed solves after one untimed")
     ap.add_argument("workload", choices=sorted(WORKLOADS))
     ap.add_argument("--bs", type=int, default=8)
     ap.add_argument("--w", type=int, default=64)
@@ -476,6 +478,19 @@ def _main():
     prec = hbmc.HBMC_F64 if a.precision == "f64" else hbmc.HBMC_F32
     kern = {"auto": hbmc.HBMC_KERNEL_AUTO, "sweep": hbmc.HBMC_KERNEL_SWEEP, "rows": hbmc.HBMC_KERNEL_ROWS}[a.kernel]
     log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
+    if a.what == "solve":
+        o = hbmc.hbmc_order(A, a.bs, a.w)
+        solver = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).set_kernel(kern).upload(dev),
+                             hbmc.hbmc_matrix_create(o, A).upload(dev))
+        b = torch.from_numpy(inputs.uniform_rhs(A.n, 6)).to(dev)
+        work = hbmc.workspace(solver.factor, 1, dev)
+        t, (x, st) = _timed(lambda: solver.solve(b, tol=1e-7, work=work), reps=a.solves)
+        out = {"workload": a.workload, "bs": a.bs, "w": a.w, "precision": a.precision, "kernel": a.kernel,
+               "ms_to_1e-7": round(t * 1e3, 3), "iterations": st.iters, "true_rel_res": st.true_rel_res,
+               "ms_per_iteration": round(t * 1e3 / max(st.iters, 1), 4)}
+        log(f"[solve {a.workload}] {out['ms_to_1e-7']} ms, {st.iters} iterations")
+        print(json.dumps(out), flush=True)
+        return
     out = apply_rate(dev, A, a.bs, a.w, prec, kern, a.reps, modes=tuple(a.modes.split(",")), log=log,
                      label=f"{a.workload} bs {a.bs} w {a.w} {a.precision} {a.kernel}")
     out.update(workload=a.workload, kernel=a.kernel)
