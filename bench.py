@@ -36,24 +36,32 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-PROFILE = os.path.join(ROOT, "profiles", "ic0_apply_diffusion128.md")
-PROFILED_SOURCES = ["paper_1908_00741_amd/csrc/sweep.h",
-                    "paper_1908_00741_amd/csrc/sweep_bs8.hip",
-                    "paper_1908_00741_amd/csrc/factor.cpp",
-                    "paper_1908_00741_amd/csrc/hbmc_internal.h"]
+# committed rocprofv3 byte-counter summaries per workload, and the kernel
+# sources each was taken with (the summary records a hash of them)
+PROFILES = {
+    "diffusion128": ("ic0_apply_diffusion128.md", ["paper_1908_00741_amd/csrc/sweep.h",
+                                                   "paper_1908_00741_amd/csrc/sweep_bs8.hip",
+                                                   "paper_1908_00741_amd/csrc/factor.cpp",
+                                                   "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
+    "knn1m": ("ic0_apply_knn1m.md", ["paper_1908_00741_amd/csrc/sweep.h",
+                                     "paper_1908_00741_amd/csrc/sweep_bs2.hip",
+                                     "paper_1908_00741_amd/csrc/factor.cpp",
+                                     "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
+}
 
 
-def measured_traffic():
-    """HBM bytes per ic0_apply from the committed rocprofv3 FETCH_SIZE /
-    WRITE_SIZE summary, or None when the kernel sources changed since it was
-    taken (the summary records a hash of them)."""
+def measured_traffic(workload="diffusion128"):
+    """HBM bytes per FP64 ic0_apply from the committed rocprofv3 FETCH_SIZE /
+    WRITE_SIZE summary of the workload, or None when the kernel sources
+    changed since it was taken."""
     import hashlib
+    name, sources = PROFILES[workload]
     try:
-        text = open(PROFILE).read()
+        text = open(os.path.join(ROOT, "profiles", name)).read()
     except OSError:
         return None
     h = hashlib.sha256()
-    for f in PROFILED_SOURCES:
+    for f in sources:
         h.update(open(os.path.join(ROOT, f), "rb").read())
     fields = dict(line.split(": ", 1) for line in text.splitlines()
                   if line.startswith(("traffic_bytes_per_apply: ", "source_sha256_16: ")))
@@ -187,6 +195,11 @@ def main() -> int:
                 ("diffusion96_bs8_w64_f64", experiments.WORKLOADS["diffusion96"](), None, 8, 64, hbmc.HBMC_F64)):
             apply_cfg[name] = experiments.apply_rate(dev, Ac, cbs, cw, prec, reps=args.apply_reps, timer=timer,
                                                      order=oc, log=log, label=name)
+            if name == "knn1m_bs2_w32_f64":
+                tk = measured_traffic("knn1m")
+                us = apply_cfg[name]["median_us_cold"]
+                apply_cfg[name]["traffic"] = tk
+                apply_cfg[name]["measured_gbs"] = None if tk is None else round(tk / (us * 1e-6) / 1e9, 1)
             torch.cuda.empty_cache()
         del Ak, ok
         torch.cuda.empty_cache()

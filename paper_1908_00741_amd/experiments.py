@@ -34,7 +34,8 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
 - apply_rate: ic0_apply alone on a named workload, timed with HIP events
   with the caches cold before each call (also the command line used for
   per-workload profiles: ``python -m paper_1908_00741_amd.experiments
-  apply knn1m --bs 2 --w 32``).
+  apply knn1m --bs 2 --w 32``; ``solve`` in place of ``apply`` runs ICCG
+  to 1e-7 on the workload instead).
 
 Setup (ordering, factorization, upload) is outside every timed region.
 """
@@ -120,6 +121,7 @@ class ColdTimer:
 
 
 WORKLOADS = {
+    "grid64": lambda: inputs.grid2d_5pt(64),
     "diffusion128": lambda: inputs.diffusion3d(128, 1.0, 2),
     "diffusion96": lambda: inputs.diffusion3d(96, 0.5, 10),
     "knn1m": lambda: inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3),
