@@ -47,6 +47,7 @@ def lib():
         P = C.c_void_p
         L.orc_check.argtypes = [i32, P, P, P]
         L.orc_blocking.argtypes = [i32, P, P, i32, P, P]
+        L.orc_rcm.argtypes = [i32, P, P, P]
         L.orc_coloring.argtypes = [i32, P, P, i32, P, i32, P, P, P]
         L.orc_hbmc_perm.argtypes = [i32, i32, i32, P, i32, P, i32, P, P, P]
         L.orc_permute.argtypes = [i32, P, P, P, P, i64, P, P, P]
@@ -128,6 +129,56 @@ def order(A, bs: int, w: int) -> Ordering:
         raise OracleError("orc_hbmc_perm", st)
     return Ordering(n, bs, w, members, nblocks, block_of, color, nc.value, perm, cstart,
                     int(npad.value))
+
+
+def rcm(A) -> np.ndarray:
+    """Reverse Cuthill-McKee numbering (the locality pre-pass, outside the
+    paper): entry k is the unknown numbered k."""
+    rp, ci, _ = _csr(A)
+    out = np.empty(A.n, np.int32)
+    st = lib().orc_rcm(A.n, _p(rp), _p(ci), _p(out))
+    if st:
+        raise OracleError("orc_rcm", st)
+    return out
+
+
+@dataclass
+class _Renumbered:
+    n: int
+    rowptr: np.ndarray
+    col: np.ndarray
+    val: np.ndarray
+
+
+def renumber(A, order: np.ndarray):
+    """P A P^T with row k of the result = row order[k] of A (rows sorted)."""
+    inv = np.empty(A.n, np.int64)
+    inv[order] = np.arange(A.n)
+    rp = np.asarray(A.rowptr, np.int64)
+    ci = np.asarray(A.col, np.int64)
+    v = np.asarray(A.val, np.float64)
+    rows, cols, vals = [], [], []
+    new_rp = np.zeros(A.n + 1, np.int64)
+    for k in range(A.n):
+        u = int(order[k])
+        c = inv[ci[rp[u]:rp[u + 1]]]
+        srt = np.argsort(c, kind="stable")
+        cols.append(c[srt])
+        vals.append(v[rp[u]:rp[u + 1]][srt])
+        new_rp[k + 1] = new_rp[k] + len(c)
+    return _Renumbered(A.n, new_rp, np.concatenate(cols).astype(np.int32), np.concatenate(vals))
+
+
+def order_rcm(A, bs: int, w: int) -> Ordering:
+    """The HBMC ordering of A renumbered by rcm(A), with perm mapping A's own
+    unknowns to HBMC positions (the other fields refer to the renumbered
+    system)."""
+    r = rcm(A)
+    o = order(renumber(A, r), bs, w)
+    inv = np.empty(A.n, np.int64)
+    inv[r] = np.arange(A.n)
+    o.perm = np.ascontiguousarray(o.perm[inv], np.int32)
+    return o
 
 
 @dataclass
@@ -324,11 +375,11 @@ class System:
         return PCGResult(self.from_hbmc(res.x), res.iters, res.status, res.hist)
 
 
-def system(A, bs: int, w: int, shift: float = 0.0) -> System:
+def system(A, bs: int, w: int, shift: float = 0.0, rcm: bool = False) -> System:
     st = check(A)
     if st:
         raise OracleError("orc_check", st)
-    o = order(A, bs, w)
+    o = order_rcm(A, bs, w) if rcm else order(A, bs, w)
     Ab = permute(A, o.perm, o.n_pad)
     d, fac = ic0(Ab, shift)
     return System(A, o, Ab, d, fac)

@@ -25,6 +25,10 @@
  *     multiplied in as in the forward-substitution listing (Fig. 6);
  *   - PCG stops when ||r||_2 / ||b||_2 < tol for the recurrence residual
  *     (Section 5.1), checked after every update of r.
+ *   - the optional locality pre-pass (not in the paper: its blocking takes
+ *     seeds in the input numbering): reverse Cuthill-McKee, each component
+ *     started at its unvisited unknown of least off-diagonal degree (the
+ *     smallest index among equals), neighbours queued by (degree, index).
  *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared -o liboracle.so hbmc_oracle.c
  * (no FMA contraction, so every product and sum rounds separately).
@@ -176,6 +180,59 @@ done:
     free(frontier.a);
     free(assigned);
     return status;
+}
+
+/* ------------------------------------------------------------------------
+ * Reverse Cuthill-McKee numbering (the locality pre-pass; not a step of the
+ * paper's method).  deg(i) = number of j != i with a_ij != 0.  Repeat until
+ * every unknown is numbered: start a breadth-first sweep at the unnumbered
+ * unknown of least degree (smallest index among equals); when an unknown
+ * leaves the queue, its unnumbered neighbours are numbered next, by
+ * increasing (degree, index).  The resulting sequence is reversed.
+ * Output: order[k] = the unknown numbered k.
+ * ---------------------------------------------------------------------- */
+int orc_rcm(int32_t n, const int64_t *rp, const int32_t *ci, int32_t *order)
+{
+    if (n < 1) return ORC_EINVAL;
+    int32_t *deg = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    char *numbered = (char *)calloc((size_t)n, 1);
+    int32_t *cm = (int32_t *)malloc((size_t)n * sizeof(int32_t));
+    if (!deg || !numbered || !cm) { free(deg); free(numbered); free(cm); return ORC_ENOMEM; }
+    for (int32_t i = 0; i < n; i++) {
+        deg[i] = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+            if (ci[p] != i) deg[i]++;
+    }
+    int32_t count = 0, head = 0;
+    while (count < n) {
+        int32_t s = -1;
+        for (int32_t i = 0; i < n; i++)
+            if (!numbered[i] && (s < 0 || deg[i] < deg[s])) s = i;
+        numbered[s] = 1;
+        cm[count++] = s;
+        while (head < count) {
+            int32_t u = cm[head++];
+            int32_t first = count;
+            for (int64_t p = rp[u]; p < rp[u + 1]; p++) {
+                int32_t v = ci[p];
+                if (numbered[v]) continue;
+                /* insert v into cm[first .. count) kept sorted by (deg, index) */
+                int32_t k = count++;
+                while (k > first && (deg[cm[k - 1]] > deg[v] ||
+                                     (deg[cm[k - 1]] == deg[v] && cm[k - 1] > v))) {
+                    cm[k] = cm[k - 1];
+                    k--;
+                }
+                cm[k] = v;
+                numbered[v] = 1;
+            }
+        }
+    }
+    for (int32_t k = 0; k < n; k++) order[k] = cm[n - 1 - k];
+    free(deg);
+    free(numbered);
+    free(cm);
+    return ORC_OK;
 }
 
 /* ------------------------------------------------------------------------

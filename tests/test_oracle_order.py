@@ -207,3 +207,109 @@ def test_check_rejects(orc):
     assert orc.check(inputs.CSR(A.n, A.rowptr, A.col, v)) == orc.ENOTSYM
     v = A.val.copy(); v[0] = 0.0                        # zero diagonal
     assert orc.check(inputs.CSR(A.n, A.rowptr, A.col, v)) == orc.EDIAG
+
+
+# ---------------------------------------------------------------------------
+# Reverse Cuthill-McKee (the locality pre-pass, outside the paper): exact
+# results derived by hand, and the characterization of a Cuthill-McKee
+# sequence under the stated rule on larger graphs.
+# ---------------------------------------------------------------------------
+
+def _graph(n, edges):
+    rows = [i for i in range(n)] + [a for a, b in edges] + [b for a, b in edges]
+    cols = [i for i in range(n)] + [b for a, b in edges] + [a for a, b in edges]
+    vals = [4.0] * n + [-1.0] * (2 * len(edges))
+    return inputs._from_coo(n, rows, cols, vals)
+
+
+def test_rcm_path_shuffled(orc):
+    """A path whose unknowns are labelled at random: degree 1 at the two
+    ends, so the sweep starts at the end with the smaller label and walks to
+    the other; reversed, the numbering runs from the other end back."""
+    n = 50
+    lab = np.random.default_rng(3).permutation(n)          # lab[t]: unknown at place t of the path
+    A = _graph(n, [(int(lab[t]), int(lab[t + 1])) for t in range(n - 1)])
+    walk = list(lab) if lab[0] < lab[-1] else list(lab[::-1])
+    assert list(orc.rcm(A)) == walk[::-1]
+
+
+def test_rcm_star_and_components(orc):
+    """A star (centre 7 of degree 11, leaves of degree 1): start at leaf 0,
+    then the centre, then the other leaves by index.  Components: the
+    isolated unknown 3 (degree 0) starts first, then the path 0-1-2 from
+    its end 0, then 4-5."""
+    A = _graph(12, [(7, j) for j in range(12) if j != 7])
+    cm = [0, 7] + [j for j in range(1, 12) if j != 7]
+    assert list(orc.rcm(A)) == cm[::-1]
+    B = _graph(6, [(0, 1), (1, 2), (4, 5)])
+    assert list(orc.rcm(B)) == [3, 0, 1, 2, 4, 5][::-1]
+
+
+def _cm_characterization(A, order):
+    """Checks that reversed(order) is the Cuthill-McKee sequence of the
+    stated rule: a permutation; each component starts at the unnumbered
+    unknown of least (degree, index); every other unknown's parent (its
+    earliest-numbered neighbour) comes before it; parents are non-decreasing
+    along the sequence, and the children of one parent run by (degree,
+    index)."""
+    n = A.n
+    cm = np.asarray(order)[::-1]
+    assert sorted(cm.tolist()) == list(range(n))
+    pos = np.empty(n, np.int64)
+    pos[cm] = np.arange(n)
+    rp, ci = A.rowptr, A.col
+    deg = np.array([int(np.sum(ci[rp[i]:rp[i + 1]] != i)) for i in range(n)])
+    numbered = np.zeros(n, bool)
+    last_parent = -1
+    prev_key = None
+    for k in range(n):
+        v = int(cm[k])
+        nb = [int(c) for c in ci[rp[v]:rp[v + 1]] if c != v]
+        earlier = [pos[c] for c in nb if pos[c] < k]
+        if not earlier:    # a component start
+            rest = np.flatnonzero(~numbered)
+            best = min(rest, key=lambda u: (deg[u], u))
+            assert v == best, (k, v, best)
+            last_parent, prev_key = -1, None
+        else:
+            par = min(earlier)
+            assert par >= last_parent, k
+            key = (deg[v], v)
+            if par == last_parent:
+                assert key > prev_key, k
+            last_parent, prev_key = par, key
+        numbered[v] = True
+
+
+@pytest.mark.parametrize("make", [lambda: inputs.random_spd(400, 0.01, 5), lambda: inputs.knn_laplacian(2000, 13, 4, 5),
+                                  lambda: inputs.grid2d_5pt(23, 17)], ids=["random", "knn", "grid"])
+def test_rcm_characterization(orc, make):
+    A = make()
+    _cm_characterization(A, orc.rcm(A))
+
+
+def test_rcm_restores_grid_locality(orc):
+    """A 40 x 40 grid whose numbering is shuffled: bandwidth back to at most
+    the grid's width + 1 (a Cuthill-McKee sweep from a corner runs along
+    anti-diagonals), from about the whole matrix."""
+    G = inputs.grid2d_5pt(40)
+    p = np.random.default_rng(9).permutation(G.n)
+    A = orc.renumber(G, p)
+    r = orc.rcm(A)
+    pos = np.empty(A.n, np.int64)
+    pos[r] = np.arange(A.n)
+    rows = np.repeat(np.arange(A.n), np.diff(A.rowptr))
+    assert np.abs(rows - A.col).max() > 1000
+    assert np.abs(pos[rows] - pos[A.col]).max() <= 41
+
+
+def test_order_rcm_composition(orc):
+    """order_rcm's permutation is the plain ordering of the renumbered system
+    read back in the input's numbering, a bijection onto the non-dummy HBMC
+    positions."""
+    A = inputs.knn_laplacian(3000, 13, 4, 5)
+    r = orc.rcm(A)
+    o = orc.order_rcm(A, 2, 32)
+    ref = orc.order(orc.renumber(A, r), 2, 32)
+    assert np.array_equal(o.perm[r], ref.perm)
+    assert len(set(o.perm.tolist())) == A.n and o.perm.max() < o.n_pad
