@@ -78,9 +78,10 @@ def main() -> int:
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--ext", default="fp32,fp32_grid,batch,rhs,graph,orderings,smoother,refactor,warmstart",
+    ap.add_argument("--ext", default="fp32,locality,fp32_grid,batch,rhs,graph,orderings,smoother,refactor,warmstart",
                     help="comma-separated extension comparisons to run after the headline "
-                         "(fp32, fp32_grid, batch, rhs, graph, orderings, smoother, refactor, warmstart); "
+                         "(fp32, locality, fp32_grid, batch, rhs, graph, orderings, smoother, refactor, "
+                         "warmstart); "
                          "empty for none")
     ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--no-configs", action="store_true",
@@ -236,6 +237,8 @@ def main() -> int:
                     ext[name] = experiments.graph(solver, b, tol=1e-7, log=log)
                 elif name == "fp32":
                     ext[name] = experiments.fp32(dev, log=log)
+                elif name == "locality":
+                    ext[name] = experiments.locality(dev, reps=args.apply_reps, log=log)
                 elif name == "fp32_grid":
                     ext[name] = experiments.fp32_grid(dev, log=log)
                 elif name == "orderings":

@@ -89,6 +89,29 @@ const char *hbmc_last_error(void);
 int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
                int32_t w, hbmc_order_t **out);
 
+/* hbmc_rcm: reverse Cuthill-McKee numbering of the pattern (a locality
+ * pre-pass outside the paper, whose blocking takes its seeds in the input's
+ * numbering and so inherits its locality).  order[k] receives the unknown
+ * numbered k (n entries, caller-owned).  Rule: the degree of an unknown is
+ * its count of off-diagonal entries; each connected component starts at
+ * its unvisited unknown of least degree (smallest index among equals);
+ * every unknown taken from the BFS queue appends its unvisited neighbours
+ * by (degree, index); the Cuthill-McKee sequence is reversed.  Errors as
+ * hbmc_order's pattern checks.  Deterministic.
+ *
+ * hbmc_order_rcm: hbmc_order applied to the pattern renumbered by
+ * hbmc_rcm (blocking, coloring, padding and secondary reordering exactly as
+ * hbmc_order would do them on P A P^T, P from hbmc_rcm), returned in the
+ * input's numbering: the handle's permutation maps the caller's unknowns to
+ * HBMC positions, so factors, matrices, solves and device builds take the
+ * caller's CSR, right-hand sides and solutions unchanged.  For inputs whose
+ * numbering has no spatial locality (a shuffled graph) the gathers of the
+ * substitutions and the SpMV then fall in fewer cache lines.  Arguments,
+ * errors and ownership as hbmc_order. */
+int hbmc_rcm(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t *order);
+int hbmc_order_rcm(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs,
+                   int32_t w, hbmc_order_t **out);
+
 typedef struct {
     int64_t n;          /* unknowns of the original system                */
     int64_t n_pad;      /* unknowns after padding (HBMC vector length)     */

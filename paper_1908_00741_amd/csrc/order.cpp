@@ -299,6 +299,96 @@ extern "C" int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, 
     return order_systems(1, sys_ptr, n, rowptr, col, bs, w, false, out);
 }
 
+// Reverse Cuthill-McKee numbering of a symmetric pattern: order[k] is the
+// unknown numbered k.  The degree of an unknown counts its off-diagonal
+// entries.  Each connected component starts at its unvisited unknown of
+// least degree (the smallest index among equals; components in the order of
+// those starts); every unknown taken from the queue appends its unvisited
+// neighbours by (degree, index); the whole Cuthill-McKee sequence is then
+// reversed.
+static void rcm_order(int32_t n, const int64_t *rp, const int32_t *ci, std::vector<int32_t> &order) {
+    std::vector<int32_t> deg(n), by_deg(n);
+    for (int32_t i = 0; i < n; ++i) {
+        int32_t d = 0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; ++p) d += ci[p] != i;
+        deg[i] = d;
+    }
+    std::iota(by_deg.begin(), by_deg.end(), 0);
+    std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
+    std::vector<char> seen(n, 0);
+    order.clear();
+    order.reserve(n);
+    std::vector<int32_t> nb;
+    size_t head = 0, next_start = 0;
+    while (int32_t(order.size()) < n) {
+        while (seen[by_deg[next_start]]) ++next_start;
+        const int32_t s = by_deg[next_start];
+        seen[s] = 1;
+        order.push_back(s);
+        for (; head < order.size(); ++head) {
+            const int32_t u = order[head];
+            nb.clear();
+            for (int64_t p = rp[u]; p < rp[u + 1]; ++p)
+                if (!seen[ci[p]]) { seen[ci[p]] = 1; nb.push_back(ci[p]); }
+            std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; });
+            order.insert(order.end(), nb.begin(), nb.end());
+        }
+    }
+    std::reverse(order.begin(), order.end());
+}
+
+extern "C" int hbmc_rcm(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t *order) {
+    clear_error();
+    if (!order) return fail(HBMC_EINVAL, "order is NULL");
+    int st = check_csr(n, rowptr, col, nullptr);
+    if (st) return st;
+    try {
+        std::vector<int32_t> o;
+        rcm_order(n, rowptr, col, o);
+        std::memcpy(order, o.data(), size_t(n) * sizeof(int32_t));
+        return HBMC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HBMC_ENOMEM, "out of host memory in hbmc_rcm");
+    }
+}
+
+extern "C" int hbmc_order_rcm(int32_t n, const int64_t *rowptr, const int32_t *col, int32_t bs, int32_t w,
+                              hbmc_order_t **out) {
+    clear_error();
+    if (!out) return fail(HBMC_EINVAL, "out is NULL");
+    *out = nullptr;
+    int st = check_csr(n, rowptr, col, nullptr);
+    if (st) return st;
+    try {
+        // the pattern renumbered: row k of it is row order[k] of the input
+        std::vector<int32_t> ord, inv(n);
+        rcm_order(n, rowptr, col, ord);
+        for (int32_t k = 0; k < n; ++k) inv[ord[k]] = k;
+        std::vector<int64_t> rp(int64_t(n) + 1, 0);
+        std::vector<int32_t> ci(size_t(rowptr[n]));
+        for (int32_t k = 0; k < n; ++k) {
+            const int32_t u = ord[k];
+            int64_t at = rp[k];
+            for (int64_t p = rowptr[u]; p < rowptr[u + 1]; ++p) ci[size_t(at++)] = inv[col[p]];
+            std::sort(ci.begin() + rp[k], ci.begin() + at);
+            rp[k + 1] = at;
+        }
+        const int64_t sys_ptr[2] = {0, n};
+        hbmc_order_t *h = nullptr;
+        if ((st = order_systems(1, sys_ptr, n, rp.data(), ci.data(), bs, w, false, &h))) return st;
+        // back to the input's numbering
+        std::vector<int32_t> perm(n);
+        for (int32_t u = 0; u < n; ++u) perm[u] = h->perm[inv[u]];
+        h->perm.swap(perm);
+        for (auto &v : h->iperm)
+            if (v >= 0) v = ord[v];
+        *out = h;
+        return HBMC_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(HBMC_ENOMEM, "out of host memory in hbmc_order_rcm");
+    }
+}
+
 extern "C" int hbmc_order_batch(int32_t nsys, const int64_t *sys_ptr, int32_t n, const int64_t *rowptr,
                                 const int32_t *col, int32_t bs, int32_t w, hbmc_order_t **out) {
     return order_systems(nsys, sys_ptr, n, rowptr, col, bs, w, true, out);

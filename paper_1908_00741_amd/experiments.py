@@ -31,6 +31,10 @@ solve stops at ||r|| / ||b|| < tol and reports ||b - A x|| / ||b||).
   time to 1e-7 per test source against x0 = 0, the network's inference
   included, the start scaled by the A-norm-optimal factor (0: fallback to
   x0 = 0);
+- locality: the 13-NN Laplacian of 1M points (its numbering shuffled) in
+  the input's numbering and after the reverse Cuthill-McKee renumbering
+  (hbmc_order_rcm, a pre-pass outside the paper): ordering time, colors,
+  cold ic0_apply and ICCG to 1e-7 with the FP64 and FP32 preconditioners;
 - apply_rate: ic0_apply alone on a named workload, timed with HIP events
   with the caches cold before each call (also the command line used for
   per-workload profiles: ``python -m paper_1908_00741_amd.experiments
@@ -207,6 +211,40 @@ def fp32(device, npts=1_000_000, bs=2, w=32, tol=1e-7, log=print):
         log(f"[ext fp32] {name}: {t * 1e3:.2f} ms, {st.iters} its, true res {st.true_rel_res:.2e}")
     res["speedup"] = round(res["f64"]["ms"] / res["f32"]["ms"], 3)
     res["rel_diff_x_f32_vs_f64"] = float(np.linalg.norm(xs["f32"] - xs["f64"]) / np.linalg.norm(xs["f64"]))
+    return res
+
+
+def locality(device, npts=1_000_000, bs=2, w=32, tol=1e-7, reps=20, log=print):
+    """The kNN problem in the input's (shuffled) numbering and renumbered by
+    reverse Cuthill-McKee before the ordering: the paper's blocking seeds in
+    the input numbering, so its layouts inherit that numbering's locality,
+    and the gathers of the substitutions and the SpMV follow it."""
+    import time
+    import torch
+    A = inputs.knn_laplacian(npts, 13, 4, 5, shift=1e-3)
+    b = torch.from_numpy(inputs.uniform_rhs(A.n, 3)).to(device)
+    res = {"workload": f"13-NN Laplacian of {npts} uniform points (numbering shuffled), 1/dist weights, "
+                       f"shift 1e-3, b~U[-1,1], HBMC bs={bs} w={w}, tol {tol:g}"}
+    for numbering in ("input", "rcm"):
+        t0 = time.perf_counter()
+        o = hbmc.hbmc_order(A, bs, w, rcm=numbering == "rcm")
+        t_order = time.perf_counter() - t0
+        m = hbmc.hbmc_matrix_create(o, A).upload(device)
+        r = {"order_s": round(t_order, 3), "n_colors": o.n_colors}
+        for name, prec in (("f64", hbmc.HBMC_F64), ("f32", hbmc.HBMC_F32)):
+            ap = apply_rate(device, A, bs, w, prec, reps=reps, order=o, log=log,
+                            label=f"locality {numbering} {name}")
+            sv = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).upload(device), m)
+            t, (x, st) = _timed(lambda: sv.solve(b, tol=tol))
+            r[name] = {"apply_us_cold": ap["median_us_cold"], "apply_frac": ap["frac"], "solve_ms": round(t * 1e3, 3),
+                       **_stats(st)}
+            log(f"[ext locality] {numbering} {name}: apply {ap['median_us_cold']:.1f} us, solve {t * 1e3:.2f} ms, "
+                f"{st.iters} its, true res {st.true_rel_res:.2e}")
+        res[numbering] = r
+        del m
+        torch.cuda.empty_cache()
+    res["speedup_f64"] = round(res["input"]["f64"]["solve_ms"] / res["rcm"]["f64"]["solve_ms"], 3)
+    res["speedup_f32_over_input_f64"] = round(res["input"]["f64"]["solve_ms"] / res["rcm"]["f32"]["solve_ms"], 3)
     return res
 
 
@@ -462,6 +500,7 @@ def _main():
     ap.add_argument("--w", type=int, default=64)
     ap.add_argument("--precision", choices=["f64", "f32"], default="f64")
     ap.add_argument("--kernel", choices=["auto", "sweep", "rows"], default="auto")
+    ap.add_argument("--rcm", action="store_true", help="order after the reverse Cuthill-McKee renumbering")
     ap.add_argument("--reps", type=int, default=20)
     ap.add_argument("--modes", default="cold,warm")
     ap.add_argument("--calibrate", action="store_true",
@@ -481,21 +520,23 @@ def _main():
     kern = {"auto": hbmc.HBMC_KERNEL_AUTO, "sweep": hbmc.HBMC_KERNEL_SWEEP, "rows": hbmc.HBMC_KERNEL_ROWS}[a.kernel]
     log = lambda *x: print(*x, file=sys.stderr, flush=True)  # noqa: E731
     if a.what == "solve":
-        o = hbmc.hbmc_order(A, a.bs, a.w)
+        o = hbmc.hbmc_order(A, a.bs, a.w, rcm=a.rcm)
         solver = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).set_kernel(kern).upload(dev),
                              hbmc.hbmc_matrix_create(o, A).upload(dev))
         b = torch.from_numpy(inputs.uniform_rhs(A.n, 6)).to(dev)
         work = hbmc.workspace(solver.factor, 1, dev)
         t, (x, st) = _timed(lambda: solver.solve(b, tol=1e-7, work=work), reps=a.solves)
         out = {"workload": a.workload, "bs": a.bs, "w": a.w, "precision": a.precision, "kernel": a.kernel,
+               "rcm": a.rcm,
                "ms_to_1e-7": round(t * 1e3, 3), "iterations": st.iters, "true_rel_res": st.true_rel_res,
                "ms_per_iteration": round(t * 1e3 / max(st.iters, 1), 4)}
         log(f"[solve {a.workload}] {out['ms_to_1e-7']} ms, {st.iters} iterations")
         print(json.dumps(out), flush=True)
         return
     out = apply_rate(dev, A, a.bs, a.w, prec, kern, a.reps, modes=tuple(a.modes.split(",")), log=log,
-                     label=f"{a.workload} bs {a.bs} w {a.w} {a.precision} {a.kernel}")
-    out.update(workload=a.workload, kernel=a.kernel)
+                     order=hbmc.hbmc_order(A, a.bs, a.w, rcm=True) if a.rcm else None,
+                     label=f"{a.workload} bs {a.bs} w {a.w} {a.precision} {a.kernel}{' rcm' if a.rcm else ''}")
+    out.update(workload=a.workload, kernel=a.kernel, rcm=a.rcm)
     print(json.dumps(out), flush=True)
 
 

@@ -24,7 +24,8 @@ HBMC_SMOOTH_SYMMETRIC, HBMC_SMOOTH_FORWARD = 0, 1
 
 # every symbol include/hbmc.h declares
 SYMBOLS = (
-    "hbmc_last_error", "hbmc_order", "hbmc_order_batch", "hbmc_order_info", "hbmc_order_perm",
+    "hbmc_last_error", "hbmc_order", "hbmc_order_rcm", "hbmc_rcm", "hbmc_order_batch", "hbmc_order_info",
+    "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
     "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "hbmc_factor_set_rhs_tile",
     "ic0_apply", "hbmc_matrix_create",
@@ -76,6 +77,8 @@ def lib():
         P, i32, i64, f64, sz = C.c_void_p, C.c_int32, C.c_int64, C.c_double, C.c_size_t
         L.hbmc_last_error.restype = C.c_char_p
         L.hbmc_order.argtypes = [i32, P, P, i32, i32, P]
+        L.hbmc_order_rcm.argtypes = [i32, P, P, i32, i32, P]
+        L.hbmc_rcm.argtypes = [i32, P, P, P]
         L.hbmc_order_batch.argtypes = [i32, P, i32, P, P, i32, i32, P]
         L.hbmc_order_info.argtypes = [P, P]
         L.hbmc_order_perm.argtypes = [P, P, P]
@@ -179,11 +182,22 @@ class Order:
             self._h = None
 
 
-def hbmc_order(A, bs: int, w: int) -> Order:
+def hbmc_order(A, bs: int, w: int, rcm: bool = False) -> Order:
+    """HBMC ordering of A's pattern; with rcm, of the pattern renumbered by
+    reverse Cuthill-McKee first (hbmc_order_rcm), in A's numbering."""
     rp, ci, _ = _csr_arrays(A)
     h = C.c_void_p()
-    _check("hbmc_order", lib().hbmc_order(A.n, _ptr(rp), _ptr(ci), bs, w, C.byref(h)))
+    name = "hbmc_order_rcm" if rcm else "hbmc_order"
+    _check(name, getattr(lib(), name)(A.n, _ptr(rp), _ptr(ci), bs, w, C.byref(h)))
     return Order(h, A)
+
+
+def hbmc_rcm(A) -> np.ndarray:
+    """Reverse Cuthill-McKee numbering: entry k is the unknown numbered k."""
+    rp, ci, _ = _csr_arrays(A)
+    out = np.empty(A.n, np.int32)
+    _check("hbmc_rcm", lib().hbmc_rcm(A.n, _ptr(rp), _ptr(ci), _ptr(out)))
+    return out
 
 
 def hbmc_order_batch(A, sys_ptr, bs: int, w: int) -> Order:

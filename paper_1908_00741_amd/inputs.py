@@ -135,11 +135,12 @@ def poisson3d(N: int) -> CSR:
 # unstructured: symmetric k-nearest-neighbour graph Laplacian
 # --------------------------------------------------------------------------
 
-def knn_laplacian(npts: int, k: int = 13, seed_points: int = 4, seed_perm: int = 5,
+def knn_laplacian(npts: int, k: int = 13, seed_points: int = 4, seed_perm: int | None = 5,
                   shift: float = 1e-3, points=None) -> CSR:
     """Graph Laplacian of the union-symmetrized k-NN graph of ``npts`` points
     uniform in the unit cube, with edge weights 1/distance, plus ``shift`` on
-    the diagonal; the numbering is shuffled with a seeded permutation.
+    the diagonal; the numbering is shuffled with a seeded permutation
+    (``seed_perm=None``: the points' own order).
 
     A = diag(sum_j w_ij) - W + shift*I.  It is a symmetric M-matrix and
     strictly diagonally dominant, hence SPD.
@@ -161,7 +162,8 @@ def knn_laplacian(npts: int, k: int = 13, seed_points: int = 4, seed_perm: int =
     deg = np.zeros(npts)
     np.add.at(deg, lo, w)
     np.add.at(deg, hi, w)
-    perm = np.random.default_rng(seed_perm).permutation(npts)  # old -> new
+    perm = (np.arange(npts) if seed_perm is None
+            else np.random.default_rng(seed_perm).permutation(npts))  # old -> new
     rows = np.concatenate([perm[lo], perm[hi], perm])
     cols = np.concatenate([perm[hi], perm[lo], perm])
     vals = np.concatenate([-w, -w, deg + shift])

@@ -51,13 +51,16 @@ def _to_dtype(torch, a, dtype):
 @pytest.mark.parametrize("layout", [mlp.MLP_NN, mlp.MLP_TN, mlp.MLP_NT], ids=["NN", "TN", "NT"])
 @pytest.mark.parametrize("M,N,K,split,pad", [(70, 130, 45, 1, 0), (64, 64, 32, 1, 0), (64, 64, 64, 1, 0),
                                              (5, 300, 1000, 3, 0), (128, 33, 12, 1, 0), (128, 192, 256, 3, 0),
-                                             (192, 128, 128, 1, 8), (128, 64, 64, 1, 3)])
+                                             (192, 128, 128, 1, 8), (128, 64, 64, 1, 3),
+                                             (128, 128, 448, 2, 0), (64, 128, 640, 1, 0), (64, 64, 1280, 3, 8)])
 def test_gemm(torch, dtype, layout, M, N, K, split, pad):
     """Whole 64 x 64 tiles with K a multiple of 64 (the K slice) and rows
     16-byte aligned take the BF16 kernel's 16-byte staging (with a split
     over K whose last range is empty, and with rows padded by pad
     elements); a pad of 3 breaks the alignment and K = 32 a whole slice, so
-    those take the element-wise staging."""
+    those take the element-wise staging.  K ranges of 4, 3, 7 and 10 slices
+    cover the loads that run four slices ahead (fewer slices than that,
+    a number that is not a multiple of it, a last range cut short)."""
     print(f"gemm dtype {dtype} layout {layout} {M}x{N}x{K} split {split} pad {pad}", flush=True)
     rng = np.random.default_rng(M + N + K)
     A = _bf16_exact(rng, (M, K))

@@ -293,6 +293,31 @@ def test_solve_full_count_knn(torch, orc, knn100k, precision, kernel):
           f"|x-x*|/|x*| = {np.linalg.norm(xh - xstar) / np.linalg.norm(xstar):.3e}", flush=True)
 
 
+def test_solve_rcm_knn(torch, orc, knn100k):
+    """The 100k-point kNN system ordered after the reverse Cuthill-McKee
+    renumbering (hbmc_order_rcm), FP64, bs 2, w 32: iterates up to the
+    count of the oracle run on the same renumbered ordering, the converged
+    count, and the solution back in the caller's numbering: its true
+    residual there, and its distance to the oracle's FP64 solution of the
+    shuffled system (printed, with the iteration counts of both orderings)."""
+    A, b, s0 = knn100k
+    print("case knn100k rcm", flush=True)
+    s = orc.system(A, 2, 32, rcm=True)
+    o = hbmc.hbmc_order(A, 2, 32, rcm=True)
+    solver = hbmc.Solver(o, hbmc.ic0_factor(o, A).upload(), hbmc.hbmc_matrix_create(o, A).upload())
+    K = s.solve(b, tol=1e-7).iters
+    _iterate_parity(torch, s, solver, b, hbmc.HBMC_F64, [10, 30, K // 2, K], "knn100k_rcm")
+    x, st = solver.solve(_dev(torch, b), tol=1e-7)
+    assert st.status == hbmc.HBMC_OK and abs(st.iters - K) <= 1 and st.true_rel_res < 1.5e-7
+    xh = _host(x)
+    true = np.linalg.norm(b - A.to_scipy() @ xh) / np.linalg.norm(b)   # in the caller's numbering
+    assert true < 1.5e-7
+    x0 = s0.solve(b, tol=1e-7)
+    err = np.linalg.norm(xh - x0.x) / np.linalg.norm(x0.x)
+    print(f"knn100k rcm: {st.iters} its (oracle {K}; shuffled numbering {x0.iters}), true residual {true:.2e}, "
+          f"|x - x_shuffled|/|x_shuffled| = {err:.2e}", flush=True)
+
+
 @pytest.fixture(scope="module")
 def knn1m(orc):
     A = inputs.knn_laplacian(1_000_000, 13, 4, 5, shift=1e-3)

@@ -106,6 +106,39 @@ def test_order_bit_exact(orc, name, make, bs, w):
     assert np.array_equal(perm, ref.perm)
 
 
+@pytest.mark.parametrize("name,make,bs,w", CASES, ids=[c[0] for c in CASES])
+def test_rcm_order_bit_exact(orc, name, make, bs, w):
+    """The reverse Cuthill-McKee numbering and the ordering of the renumbered
+    system (hbmc_rcm, hbmc_order_rcm) against the oracle's: same numbering,
+    same permutation in the input's numbering, same color starts."""
+    A = make()
+    assert np.array_equal(hbmc.hbmc_rcm(A), orc.rcm(A))
+    o = hbmc.hbmc_order(A, bs, w, rcm=True)
+    ref = orc.order_rcm(A, bs, w)
+    perm, cs = o.perm()
+    assert (o.n_colors, o.n_pad, o.n_blocks) == (ref.ncolors, ref.n_pad, ref.nblocks)
+    assert np.array_equal(cs, ref.color_start) and np.array_equal(perm, ref.perm)
+
+
+def test_rcm_order_bit_exact_knn_100k(orc):
+    """The unstructured workload at 100,000 points (bs 2, w 32): the
+    renumbered ordering bit-exact, with fewer colors than the shuffled
+    numbering's and the factor built on it against the oracle's."""
+    A = inputs.knn_laplacian(100_000, 13, 4, 5, shift=1e-3)
+    o = hbmc.hbmc_order(A, 2, 32, rcm=True)
+    ref = orc.order_rcm(A, 2, 32)
+    perm, cs = o.perm()
+    assert np.array_equal(perm, ref.perm) and np.array_equal(cs, ref.color_start)
+    assert o.n_colors <= hbmc.hbmc_order(A, 2, 32).n_colors
+    d, rp, ci, v = hbmc.ic0_factor(o, A).export()
+    Ab = orc.permute(A, ref.perm, ref.n_pad)
+    dref, fac = orc.ic0(Ab)
+    Lref = sp.tril(sp.csr_matrix((fac, Ab.col, Ab.rowptr), shape=(Ab.n, Ab.n)), k=-1).tocsr()
+    Lref.sort_indices()
+    assert np.array_equal(rp, Lref.indptr) and np.array_equal(ci, Lref.indices)
+    assert np.allclose(v, Lref.data, rtol=1e-14, atol=0) and np.allclose(d, dref, rtol=1e-14, atol=0)
+
+
 @pytest.mark.parametrize("N,sigma,seed", [(128, 1.0, 2), (96, 0.5, 10)])
 def test_order_bit_exact_full_size_grids(orc, N, sigma, seed):
     """The 128^3 (sigma 1) and 96^3 (sigma 0.5) diffusion workloads at full size."""
