@@ -222,8 +222,10 @@ __device__ inline int64_t part_of_block() { return logical_block() / sub_blocks(
 // One row of y = A x for one right-hand side, x(i) given by an accessor of
 // element indices; all 64 lanes of the wavefront must be active.  The
 // group's strided-slot bases and masks (at most 64) come in with one vector
-// load, one slot per lane, and are broadcast with readlane.
-template <class X>
+// load, one slot per lane, and are broadcast with readlane.  CHUNKED: the
+// packed slots are read in chunks (below), for matrices that hold most of
+// their couplings there (those whose product gathers p alone).
+template <bool CHUNKED = true, class X>
 __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) {
     const int64_t g = r.g;
     const int lane = int(threadIdx.x & 63);
@@ -241,16 +243,48 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) 
         const double xv = x((base + jc) * int64_t(K) + r.q);
         acc = on ? acc + v * xv : acc;
     }
+    if constexpr (!CHUNKED) {
 #pragma unroll 4
-    for (int64_t s = m.ioff[g]; s < m.ioff[g + 1]; ++s) {
-        // packed slot: lane jc's entry is its rank among the slot's lanes
-        const uint64_t mask = m.imask[s];
-        const bool on = (mask >> jc) & 1;
-        const int64_t e = m.ivoff[s] + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
-        const int32_t c = on ? m.icol[e] : -1;
-        const double v = m.ival[e];
-        const double xv = x((c >= 0 ? c : 0) * int64_t(K) + r.q);
-        acc = c >= 0 ? acc + v * xv : acc;
+        for (int64_t s = m.ioff[g]; s < m.ioff[g + 1]; ++s) {
+            // packed slot: lane jc's entry is its rank among the slot's lanes
+            const uint64_t mask = m.imask[s];
+            const bool on = (mask >> jc) & 1;
+            const int64_t e = m.ivoff[s] + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
+            const int32_t c = on ? m.icol[e] : -1;
+            const double v = m.ival[e];
+            const double xv = x((c >= 0 ? c : 0) * int64_t(K) + r.q);
+            acc = c >= 0 ? acc + v * xv : acc;
+        }
+        return acc;
+    }
+    // packed slots kC at a time: the slots' masks and offsets, then their
+    // columns and values, then the gathers, each step issued for the whole
+    // chunk (lane jc's entry is its rank among the slot's lanes), so that a
+    // row of an unstructured matrix waits for three round trips per chunk,
+    // not per slot (1M-point 13-NN product 146 against 140 us).  Past the
+    // last slot a chunk repeats that slot's loads (in range) and adds
+    // nothing.  The product of the grids (strided slots, p formed on the
+    // fly) keeps one slot at a time: the chunks' registers cost it
+    // occupancy, and chunking its strided slots too measured slower (128^3
+    // product 48 against 69 us).
+    constexpr int kC = 8;
+    const int64_t i0 = m.ioff[g], i1 = m.ioff[g + 1];
+    for (int64_t s0i = i0; s0i < i1; s0i += kC) {
+        int32_t c[kC];
+        double v[kC], xv[kC];
+#pragma unroll
+        for (int kk = 0; kk < kC; ++kk) {
+            const int64_t s = min(s0i + kk, i1 - 1);
+            const uint64_t mask = m.imask[s];
+            const bool on = s0i + kk < i1 && ((mask >> jc) & 1);
+            const int64_t e = m.ivoff[s] + (on ? __builtin_popcountll(mask & ((uint64_t(1) << jc) - 1)) : 0);
+            c[kk] = on ? m.icol[e] : -1;
+            v[kk] = m.ival[e];
+        }
+#pragma unroll
+        for (int kk = 0; kk < kC; ++kk) xv[kk] = x((c[kk] >= 0 ? c[kk] : 0) * int64_t(K) + r.q);
+#pragma unroll
+        for (int kk = 0; kk < kC; ++kk) acc = c[kk] >= 0 ? acc + v[kk] * xv[kk] : acc;
     }
     return acc;
 }
@@ -424,7 +458,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on || !__any(live)) continue;
         const double pi = pv(r.e);
-        const double qi = spmv_row_with(m, pv, r, K);
+        const double qi = spmv_row_with<false>(m, pv, r, K);
         if (r.valid && live) {
             const int64_t e = r.row * K + r.q;
             p_new[e] = pi;
