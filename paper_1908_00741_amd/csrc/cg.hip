@@ -235,13 +235,25 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) 
     const int64_t ms = s0 + (lane < ns ? lane : 0);
     const int32_t mbase = m.sbase[ms];
     const uint64_t mmask = m.smask[ms];
-#pragma unroll 4
-    for (int k = 0; k < ns; ++k) {
-        const int32_t base = __builtin_amdgcn_readlane(mbase, k);
-        const bool on = (readlane64(mmask, k) >> jc) & 1;
-        const double v = m.sval[(s0 + k) * int64_t(kLanes) + jc];
-        const double xv = x((base + jc) * int64_t(K) + r.q);
-        acc = on ? acc + v * xv : acc;
+    // strided slots kS at a time, all loads of a chunk issued before its
+    // products are added in slot order (past the last slot a chunk repeats
+    // that slot's loads and adds nothing).  128^3 product: 48.0 us one slot
+    // at a time, 46.5 us two, 51.5 us four (the repeated loads and the
+    // registers cost more than the overlap gains)
+    constexpr int kS = 2;
+    for (int k0 = 0; k0 < ns; k0 += kS) {
+        double v[kS], xv[kS];
+        bool on[kS];
+#pragma unroll
+        for (int kk = 0; kk < kS; ++kk) {
+            const int k = min(k0 + kk, ns - 1);
+            const int32_t base = __builtin_amdgcn_readlane(mbase, k);
+            on[kk] = k0 + kk < ns && ((readlane64(mmask, k) >> jc) & 1);
+            v[kk] = m.sval[(s0 + k) * int64_t(kLanes) + jc];
+            xv[kk] = x((base + jc) * int64_t(K) + r.q);
+        }
+#pragma unroll
+        for (int kk = 0; kk < kS; ++kk) acc = on[kk] ? acc + v[kk] * xv[kk] : acc;
     }
     if constexpr (!CHUNKED) {
 #pragma unroll 4
@@ -264,9 +276,9 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) 
     // not per slot (1M-point 13-NN product 146 against 140 us).  Past the
     // last slot a chunk repeats that slot's loads (in range) and adds
     // nothing.  The product of the grids (strided slots, p formed on the
-    // fly) keeps one slot at a time: the chunks' registers cost it
-    // occupancy, and chunking its strided slots too measured slower (128^3
-    // product 48 against 69 us).
+    // fly) reads its packed slots one at a time: the chunks' registers cost
+    // it occupancy (128^3 product 69 against 48 us with chunks of eight
+    // for both kinds of slot).
     constexpr int kC = 8;
     const int64_t i0 = m.ioff[g], i1 = m.ioff[g + 1];
     for (int64_t s0i = i0; s0i < i1; s0i += kC) {
