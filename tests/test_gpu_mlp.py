@@ -104,12 +104,14 @@ def test_linear_fwd(torch, dtype, M, N, K):
 
 
 @pytest.mark.parametrize("dtype", [mlp.MLP_BF16, mlp.MLP_F32], ids=["bf16", "f32"])
-@pytest.mark.parametrize("M,N,K", [(70, 333, 45), (128, 192, 128), (64, 64, 64)])
+@pytest.mark.parametrize("M,N,K", [(70, 333, 45), (128, 192, 128), (64, 64, 64), (256, 320, 256), (192, 128, 192),
+                                   (320, 128, 64)])
 def test_linear_fwd_mse(torch, dtype, M, N, K):
     """Output layer with the loss: dY = scale (X W + b - T) in the compute
     type, the loss partial of each 64 x 64 output tile and the bias-gradient
     partial of each 64-row tile, against FP64 on inputs that bfloat16 holds
-    exactly (whole tiles take the 16-byte epilogue of the BF16 kernel)."""
+    exactly (whole BF16 tiles take the 16-byte epilogue of the tiled
+    kernel; one to five row tiles)."""
     print(f"linear_fwd_mse dtype {dtype} {M}x{N}x{K}", flush=True)
     rng = np.random.default_rng(M + 3 * N + 7 * K)
     X = _bf16_exact(rng, (M, K))
