@@ -224,8 +224,8 @@ __device__ inline int64_t part_of_block() { return logical_block() / sub_blocks(
 // group's strided-slot bases and masks (at most 64) come in with one vector
 // load, one slot per lane, and are broadcast with readlane.  CHUNKED: the
 // packed slots are read in chunks (below), for matrices that hold most of
-// their couplings there (those whose product gathers p alone).
-template <bool CHUNKED = true, class X>
+// their couplings there (fuse_p false).
+template <bool CHUNKED, class X>
 __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) {
     const int64_t g = r.g;
     const int lane = int(threadIdx.x & 63);
@@ -301,7 +301,8 @@ __device__ inline double spmv_row_with(const Mat &m, X x, const Elem &r, int K) 
     return acc;
 }
 
-template <int NR>
+// CH: the matrix holds most couplings in packed slots (spmv_row_with)
+template <int NR, bool CH>
 __global__ void __launch_bounds__(kBlock) k_spmv(Mat m, int K, const double *__restrict__ x,
                                                  double *__restrict__ y) {
     if (NR == 1) K = 1;
@@ -309,7 +310,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv(Mat m, int K, const double *__r
     for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on) continue;
-        const double v = spmv_row_with(m, [=](int64_t i) { return x[i]; }, r, K);
+        const double v = spmv_row_with<CH>(m, [=](int64_t i) { return x[i]; }, r, K);
         if (r.valid) y[r.row * K + r.q] = v;
     }
 }
@@ -505,7 +506,7 @@ __global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, 
 }
 
 // q = A p for p formed by k_update_p; part partials of (p, q)
-template <int NR>
+template <int NR, bool CH>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, const double *__restrict__ p,
                                                      double *__restrict__ q, double *part, int64_t np,
                                                      const CgState *st, const int32_t *alldone) {
@@ -519,7 +520,7 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, cons
     for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on || !__any(live)) continue;
-        const double qi = spmv_row_with(m, pv, r, K);
+        const double qi = spmv_row_with<CH>(m, pv, r, K);
         if (r.valid && live) {
             const int64_t e = r.row * K + r.q;
             q[e] = qi;
@@ -597,7 +598,7 @@ __global__ void __launch_bounds__(kFin) k_fin_resid(const double *part, int64_t 
 }
 
 // r = b - A x (the residual of a smoothing step)
-template <int NR>
+template <int NR, bool CH>
 __global__ void __launch_bounds__(kBlock) k_smooth_r(Mat m, int K, const double *__restrict__ b,
                                                      const double *__restrict__ x, double *__restrict__ r) {
     if (NR == 1) K = 1;
@@ -605,7 +606,7 @@ __global__ void __launch_bounds__(kBlock) k_smooth_r(Mat m, int K, const double 
     for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem e = elem<NR>(m.n, K, mm);
         if (!e.wave_on) continue;
-        const double ax = spmv_row_with(m, [=](int64_t i) { return x[i]; }, e, K);
+        const double ax = spmv_row_with<CH>(m, [=](int64_t i) { return x[i]; }, e, K);
         if (e.valid) r[e.row * K + e.q] = b[e.row * K + e.q] - ax;
     }
 }
@@ -767,6 +768,31 @@ size_t work_layout(const hbmc_factor_s *f, int K, Work *w, void *base) {
         }                                                                                         \
     } while (0)
 
+// VEC_LAUNCH for the product kernels, with the packed-slot form chosen by
+// the matrix (chunks for matrices held mostly in packed slots, the others
+// one slot at a time: the chunks' registers would cost them occupancy).
+#define VEC_LAUNCH_MAT(kernel, mat, n_pad, K, s, ...)                                              \
+    do {                                                                                          \
+        const int nr_ = vec_nr(K);                                                                \
+        const bool ch_ = !(mat).fuse_p;                                                           \
+        const unsigned px_ = unsigned(((n_pad) + kPartRows - 1) / kPartRows * sub_blocks(nr_));   \
+        const dim3 g_(px_, unsigned(((K) + nr_ - 1) / nr_));                                      \
+        switch (nr_) {                                                                            \
+            case 1: if (ch_) hipLaunchKernelGGL((kernel<1, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);     \
+                    else hipLaunchKernelGGL((kernel<1, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+            case 4: if (ch_) hipLaunchKernelGGL((kernel<4, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);     \
+                    else hipLaunchKernelGGL((kernel<4, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+            case 8: if (ch_) hipLaunchKernelGGL((kernel<8, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);     \
+                    else hipLaunchKernelGGL((kernel<8, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;  \
+            case 16: if (ch_) hipLaunchKernelGGL((kernel<16, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);   \
+                     else hipLaunchKernelGGL((kernel<16, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;\
+            case 32: if (ch_) hipLaunchKernelGGL((kernel<32, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);   \
+                     else hipLaunchKernelGGL((kernel<32, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;\
+            default: if (ch_) hipLaunchKernelGGL((kernel<64, true>), g_, dim3(kBlock), 0, s, __VA_ARGS__);   \
+                     else hipLaunchKernelGGL((kernel<64, false>), g_, dim3(kBlock), 0, s, __VA_ARGS__); break;\
+        }                                                                                         \
+    } while (0)
+
 inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock - 1) / kBlock)); }
 
 // One CG iteration (everything after the first preconditioning step); the
@@ -784,7 +810,7 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
         VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     } else {
         VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);
-        VEC_LAUNCH(k_spmv_dot, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+        VEC_LAUNCH_MAT(k_spmv_dot, m, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     }
     ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz,
                nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, nullptr};
@@ -897,7 +923,8 @@ extern "C" int hbmc_spmv(const hbmc_matrix_t *m, const double *x, double *y, int
     if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     if (x == y) return fail(HBMC_EINVAL, "y must not alias x");
     const int K = nrhs;
-    VEC_LAUNCH(k_spmv, m->n_pad, K, static_cast<hipStream_t>(stream), mat_of(m), K, x, y);
+    const Mat mm = mat_of(m);
+    VEC_LAUNCH_MAT(k_spmv, mm, m->n_pad, K, static_cast<hipStream_t>(stream), mm, K, x, y);
     HIP_TRY(hipGetLastError());
     return HBMC_OK;
 }
@@ -972,7 +999,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, b, w.bb);
     if (x0_zero) hipLaunchKernelGGL(k_zero, dim3(ge), dim3(kBlock), 0, s, n * K, w.xb);
     else hipLaunchKernelGGL(k_to_hbmc, dim3(ge), dim3(kBlock), 0, s, n, K, iperm, x, w.xb);
-    VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
+    VEC_LAUNCH_MAT(k_spmv, m, n, K, s, m, K, w.xb, w.q);
     if (x0_scale) {
         VEC_LAUNCH(k_init_dots, n, K, s, n, K, w.bb, w.xb, w.q, w.part_g, w.np);
         hipLaunchKernelGGL(k_fin_scale, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st);
@@ -1010,7 +1037,7 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     hipLaunchKernelGGL(k_zero_b0, dim3(ge), dim3(kBlock), 0, s, n, K, sys.part_sys, w.st, w.xb);
     hipLaunchKernelGGL(k_from_hbmc, dim3(grid_elems(int64_t(f->n) * K)), dim3(kBlock), 0, s, int64_t(f->n), K,
                        perm, w.xb, x);
-    VEC_LAUNCH(k_spmv, n, K, s, m, K, w.xb, w.q);
+    VEC_LAUNCH_MAT(k_spmv, m, n, K, s, m, K, w.xb, w.q);
     VEC_LAUNCH(k_resid, n, K, s, n, K, w.bb, w.q, w.part_g, w.np);
     hipLaunchKernelGGL(k_fin_resid, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.resid);
     HIP_TRY(hipGetLastError());
@@ -1169,7 +1196,7 @@ extern "C" int hbmc_smooth(const hbmc_factor_t *f, const hbmc_matrix_t *A, const
     const double c = fwd ? 1.0 : f->smooth_scale;
     const int64_t ne = f->n_pad * K;
     for (int32_t k = 0; k < sweeps; ++k) {
-        VEC_LAUNCH(k_smooth_r, f->n_pad, K, s, m, K, b, x, r);
+        VEC_LAUNCH_MAT(k_smooth_r, m, f->n_pad, K, s, m, K, b, x, r);
         HIP_TRY(hipGetLastError());
         if ((st = apply_launch(f, r, z, s, nullptr, nullptr, K, fwd))) return st;
         hipLaunchKernelGGL(k_axpy, dim3(grid_elems(ne)), dim3(kBlock), 0, s, ne, c, z, x);
