@@ -446,15 +446,17 @@ __global__ void __launch_bounds__(kFin) k_fin_rho(const double *part, int64_t np
                                                   CgState *st) {
     const int b = blockIdx.x, s = b / K, q = b % K;
     const double t = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
-    if (threadIdx.x == 0) { st[b].rho = t; st[b].beta = 0.0; }
+    if (threadIdx.x == 0) { st[b].rho = t; st[b].beta = 0.0; st[b].alpha = 0.0; }
 }
 
 // p = z + beta p_old (formed on the fly, also at the columns the row
-// couples to), written to p_new; q = A p; part partials of (p, q)
+// couples to), written to p_new; q = A p; part partials of (p, q); and the
+// previous iteration's x += alpha p_old at the row (lagged: this kernel
+// reads p_old there anyway; k_finish_x adds the last one)
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, const double *__restrict__ z,
                                                        const double *__restrict__ p_old,
-                                                       double *__restrict__ p_new,
+                                                       double *__restrict__ p_new, double *__restrict__ x,
                                                        double *__restrict__ q, double *part, int64_t np,
                                                        const CgState *st, const int32_t *alldone) {
     if (*alldone) return;
@@ -463,17 +465,19 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
     const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
     const bool live = q0 < K && !c.done;          // a part lies in one system
     if (NR == 1 && !live) return;                  // workgroup-uniform with one right-hand side
-    const double beta = c.beta;
+    const double beta = c.beta, alpha = c.alpha;
     auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
     double pq = 0.0;
 #pragma unroll 1
     for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(m.n, K, mm);
         if (!r.wave_on || !__any(live)) continue;
-        const double pi = pv(r.e);
+        const double po = p_old[r.e], xo = x[r.e];
+        const double pi = z[r.e] + beta * po;
         const double qi = spmv_row_with<false>(m, pv, r, K);
         if (r.valid && live) {
             const int64_t e = r.row * K + r.q;
+            x[e] = xo + alpha * po;
             p_new[e] = pi;
             q[e] = qi;
             pq += pi * qi;
@@ -489,18 +493,43 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
 template <int NR>
 __global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, const double *__restrict__ z,
                                                      const double *__restrict__ p_old, double *__restrict__ p_new,
-                                                     const CgState *st, const int32_t *alldone) {
+                                                     double *__restrict__ x, const CgState *st,
+                                                     const int32_t *alldone) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
     const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
     if (q0 >= K || c.done) return;
-    const double beta = c.beta;
+    const double beta = c.beta, alpha = c.alpha;
 #pragma unroll 1
     for (int mm = 0; mm < rounds(NR); ++mm) {
         const Elem r = elem<NR>(n, K, mm);
         if (r.valid) {
             const int64_t e = r.row * K + r.q;
-            p_new[e] = z[e] + beta * p_old[e];
+            const double po = p_old[e];
+            x[e] = x[e] + alpha * po;   // the previous iteration's step (lagged)
+            p_new[e] = z[e] + beta * po;
+        }
+    }
+}
+
+// After the loop: the step x += alpha p of each stopped system's last
+// iteration, which no direction update applied (none after a breakdown in
+// alpha, which leaves alpha = 0).  The direction of iteration k is p[k % 2].
+template <int NR>
+__global__ void __launch_bounds__(kBlock) k_finish_x(int64_t n, int K, Sys sys, const double *__restrict__ p0,
+                                                     const double *__restrict__ p1, double *__restrict__ x,
+                                                     const CgState *st) {
+    const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
+    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
+    if (q0 >= K || c.it < 1 || c.alpha == 0.0) return;
+    const double alpha = c.alpha;
+    const double *p = (c.it & 1) ? p1 : p0;
+#pragma unroll 1
+    for (int mm = 0; mm < rounds(NR); ++mm) {
+        const Elem r = elem<NR>(n, K, mm);
+        if (r.valid) {
+            const int64_t e = r.row * K + r.q;
+            x[e] = x[e] + alpha * p[e];
         }
     }
 }
@@ -541,6 +570,7 @@ __global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t 
     c.sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         c.done = kBreakdown;
+        c.alpha = 0.0;   // no x update pending
         c.it += 1;
         count_done(ndone, alldone, sys.nsys * K);
         return;
@@ -797,9 +827,9 @@ inline int grid_elems(int64_t n) { return int(std::max<int64_t>(1, (n + kBlock -
 
 // One CG iteration (everything after the first preconditioning step); the
 // direction is read from p[parity] and written to p[1 - parity].
-//   q = A p, p = z + beta p_old (two kernels for several right-hand sides or a mostly indexed matrix)  |  alpha = rho / (p, q)  |
-//   x += alpha p, r -= alpha q, z = M^-1 r, partials of ||r||^2 and (r, z)  |
-//   stopping test, beta
+//   q = A p, p = z + beta p_old, the previous iteration's x += alpha p_old (two kernels for several
+//   right-hand sides or a mostly indexed matrix)  |  alpha = rho / (p, q)  |
+//   r -= alpha q, z = M^-1 r, partials of ||r||^2 and (r, z)  |  stopping test, beta
 int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipStream_t s,
                       bool history, int parity) {
     const Sys sys = sys_of(f);
@@ -807,12 +837,13 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
     const unsigned nst = unsigned(f->nsys) * K;
     double *p_old = w.p[parity], *p_new = w.p[1 - parity];
     if (K == 1 && m.fuse_p) {
-        VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
+        VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.xb, w.q, w.part_g, w.np, w.st,
+                   w.alldone);
     } else {
-        VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.st, w.alldone);
+        VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.xb, w.st, w.alldone);
         VEC_LAUNCH_MAT(k_spmv_dot, m, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     }
-    ApplyCg cg{w.xb, p_new, w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz,
+    ApplyCg cg{w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz,
                nullptr, nullptr, 0, nullptr, 0, nullptr, nullptr, nullptr};
     if (K == 1 && f->nsys == 1 && !use_rows(f, f->bs, 1, 1)) {
         // one system, one right-hand side, one wavefront per tile: alpha is
@@ -1032,8 +1063,9 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
             if (hd[2]) return fail(HBMC_EHIP, "a wait for alpha inside a kernel timed out");
         }
     }
-    // pairs with b = 0 get x = 0; the solution back to the caller's
-    // numbering; the true residuals
+    // the last step of each system; pairs with b = 0 get x = 0; the
+    // solution back to the caller's numbering; the true residuals
+    VEC_LAUNCH(k_finish_x, n, K, s, n, K, sys, w.p[0], w.p[1], w.xb, w.st);
     hipLaunchKernelGGL(k_zero_b0, dim3(ge), dim3(kBlock), 0, s, n, K, sys.part_sys, w.st, w.xb);
     hipLaunchKernelGGL(k_from_hbmc, dim3(grid_elems(int64_t(f->n) * K)), dim3(kBlock), 0, s, int64_t(f->n), K,
                        perm, w.xb, x);

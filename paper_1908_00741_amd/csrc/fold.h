@@ -2,7 +2,7 @@
 // preconditioning step (one system, one right-hand side), in place of a
 // kernel of its own: workgroup 0 of that phase adds up the product's
 // partials and publishes alpha; every workgroup first loads the rows it
-// updates (x += alpha p, r -= alpha q), then waits for the publication.
+// updates (r -= alpha q), then waits for the publication.
 // Workgroup 0 is dispatched first and waits on nobody before publishing, so
 // the wait always ends; it is also bounded in time.
 //
@@ -120,6 +120,7 @@ __device__ inline void fold_alpha(const ApplyCg &cg) {
         const double alpha = c.rho / sigma;
         if (!(sigma > 0.0) || !isfinite(sigma) || !isfinite(alpha)) {
             c.it += 1;
+            c.alpha = 0.0;   // no x update pending
             c.done = kBreakdown;
             count_done(cg.ndone, cg.alldone, 1);
         } else {

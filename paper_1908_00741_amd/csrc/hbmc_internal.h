@@ -66,12 +66,12 @@ struct CgState {
 enum { kRunning = 0, kConverged = 1, kBreakdown = 2, kMaxIt = 3 };
 
 // CG work folded into the preconditioning step (iccg_solve only): the
-// forward sweep of a color first applies x += alpha p, r -= alpha q to the
-// rows it reads and adds up ||r||^2; the sweeps that finish z add up (r, z).
-// Partial sums per (right-hand side, tile, sub-tile): [K][tiles * NR].
+// forward sweep of a color first applies r -= alpha q to the rows it reads
+// and adds up ||r||^2; the sweeps that finish z add up (r, z).  (x += alpha
+// p waits for the next iteration's direction update, which streams p
+// anyway.)  Partial sums per (right-hand side, tile, sub-tile):
+// [K][tiles * NR].
 struct ApplyCg {
-    double *x;
-    const double *p;
     const double *q;
     double *r;
     const CgState *st;          // [systems][K]: alpha, and done (stopped ones are skipped)

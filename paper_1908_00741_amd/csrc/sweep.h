@@ -488,15 +488,13 @@ __device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], 
 }
 
 // Loads the right-hand side of one row (r, or y for a backward phase); with
-// CG in a forward phase first applies x += alpha p, r -= alpha q to it.
+// CG in a forward phase first applies r -= alpha q to it.
 template <typename T, int MODE, bool CG>
 __device__ inline T row_rhs(const Phase &ph, const double *__restrict__ r, const double *__restrict__ z,
                             int64_t e, bool valid, double alpha, double &rn, double &rr) {
     if (CG && MODE != kBackward) {
-        const double pv = ph.cg.p[e];
-        const double xn = ph.cg.x[e] + alpha * pv;
         rn = ph.cg.r[e] - alpha * ph.cg.q[e];
-        if (valid) { ph.cg.x[e] = xn; ph.cg.r[e] = rn; rr += rn * rn; }
+        if (valid) { ph.cg.r[e] = rn; rr += rn * rn; }
         return T(rn);
     }
     if (CG) rn = ph.cg.r[e];   // backward: r of these rows is final
@@ -556,15 +554,13 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
     double rn[BS];   // CG: the updated residual of the lane's rows
     double rr = 0.0;
     if constexpr (CG && MODE != kBackward) {
-        // x += alpha p, r -= alpha q on the lane's rows: their loads first,
-        // then (first phase of a folded iteration) the wait for alpha
-        double pv[BS], xv[BS], rv[BS], qv[BS];
+        // r -= alpha q on the lane's rows: their loads first, then (first
+        // phase of a folded iteration) the wait for alpha
+        double rv[BS], qv[BS];
 #pragma unroll
         for (int l = 0; l < BS; ++l) {
             const int64_t row = rb + int64_t(l) * w, e = L.at(row);
             dv[l] = static_cast<const T *>(ph.dinv)[row];
-            pv[l] = ph.cg.p[e];
-            xv[l] = ph.cg.x[e];
             rv[l] = ph.cg.r[e];
             qv[l] = ph.cg.q[e];
         }
@@ -579,9 +575,8 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
 #pragma unroll
         for (int l = 0; l < BS; ++l) {
             const int64_t e = L.at(rb + int64_t(l) * w);
-            const double xn = xv[l] + alpha * pv[l];
             rn[l] = rv[l] - alpha * qv[l];
-            if (valid) { ph.cg.x[e] = xn; ph.cg.r[e] = rn[l]; rr += rn[l] * rn[l]; }
+            if (valid) { ph.cg.r[e] = rn[l]; rr += rn[l] * rn[l]; }
             acc[l] = T(rn[l]);
         }
     } else {
