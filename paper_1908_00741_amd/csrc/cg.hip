@@ -30,6 +30,7 @@
 #include <vector>
 
 #include "fold.h"
+#include "xcd.h"
 #include "hbmc_internal.h"
 
 using namespace hbmc;
@@ -176,12 +177,7 @@ __host__ __device__ constexpr int sub_blocks(int NR) { return NR <= 4 ? 1 : NR /
 // chip's 8 XCDs (each with its own L2) in turn; renumbering them so that XCD
 // x gets a contiguous range of the row order keeps rows whose neighbours
 // overlap (the gathers of the SpMV) in the same L2.
-constexpr int kXcds = 8;
-__device__ inline int64_t logical_block() {
-    const int64_t nb = gridDim.x, b = blockIdx.x;
-    const int64_t x = b % kXcds, i = b / kXcds, q = nb / kXcds, r = nb % kXcds;
-    return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
-}
+__device__ inline int64_t logical_block() { return xcd_block(blockIdx.x, gridDim.x); }
 __host__ __device__ constexpr int rounds(int NR) { return NR / sub_blocks(NR); }
 
 struct Elem {

@@ -209,6 +209,7 @@ struct hbmc_dbuild_s;
 
 struct hbmc_order_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, nsys = 1;
+    bool local = false;                // ordered after the locality renumbering (hbmc_order_rcm)
     int64_t n_pad = 0, nblocks = 0;
     std::vector<int64_t> sys_ptr;      // [nsys + 1] original rows of each system
     std::vector<int64_t> seg;          // [nc * (nsys + 1)] HBMC rows of (color, system)
@@ -244,6 +245,7 @@ struct TriOffsets {
 struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int32_t kernel = HBMC_KERNEL_AUTO;
+    bool xcd_tiles = false;            // the row kernel takes tiles in XCD-contiguous order
     int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;
     int64_t n_pad = 0;

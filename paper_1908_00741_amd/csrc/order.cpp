@@ -382,6 +382,7 @@ extern "C" int hbmc_order_rcm(int32_t n, const int64_t *rowptr, const int32_t *c
         h->perm.swap(perm);
         for (auto &v : h->iperm)
             if (v >= 0) v = ord[v];
+        h->local = true;
         *out = h;
         return HBMC_OK;
     } catch (const std::bad_alloc &) {
