@@ -593,10 +593,13 @@ class Solver:
     @staticmethod
     def setup(A, bs: int, w: int, precision: int = HBMC_F64, shift: float = 0.0,
               device="cuda", kernel: int = HBMC_KERNEL_AUTO, sys_ptr=None,
-              omega: float | None = None) -> "Solver":
+              omega: float | None = None, rcm: bool = False) -> "Solver":
         """IC(0) factor, or the SSOR splitting with relaxation omega when
-        omega is given."""
-        o = hbmc_order(A, bs, w) if sys_ptr is None else hbmc_order_batch(A, sys_ptr, bs, w)
+        omega is given; with rcm, the ordering of the pattern renumbered by
+        reverse Cuthill-McKee (one system)."""
+        if sys_ptr is not None and rcm:
+            raise ValueError("the renumbered ordering takes one system")
+        o = hbmc_order(A, bs, w, rcm=rcm) if sys_ptr is None else hbmc_order_batch(A, sys_ptr, bs, w)
         f = ic0_factor(o, A, precision, shift) if omega is None else ssor_factor(o, A, precision, omega)
         f = f.set_kernel(kernel).upload(device)
         m = hbmc_matrix_create(o, A).upload(device)
