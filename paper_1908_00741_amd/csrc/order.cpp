@@ -308,30 +308,35 @@ extern "C" int hbmc_order(int32_t n, const int64_t *rowptr, const int32_t *col, 
 // reversed.
 static void rcm_order(int32_t n, const int64_t *rp, const int32_t *ci, std::vector<int32_t> &order) {
     std::vector<int32_t> deg(n), by_deg(n);
-    for (int32_t i = 0; i < n; ++i) {
+    parallel_for(n, 1 << 16, [&](int64_t i) {
         int32_t d = 0;
         for (int64_t p = rp[i]; p < rp[i + 1]; ++p) d += ci[p] != i;
         deg[i] = d;
-    }
+    });
     std::iota(by_deg.begin(), by_deg.end(), 0);
     std::stable_sort(by_deg.begin(), by_deg.end(), [&](int32_t a, int32_t b) { return deg[a] < deg[b]; });
     std::vector<char> seen(n, 0);
-    order.clear();
-    order.reserve(n);
-    std::vector<int32_t> nb;
-    size_t head = 0, next_start = 0;
-    while (int32_t(order.size()) < n) {
+    order.assign(size_t(n), 0);
+    int64_t len = 0, head = 0, next_start = 0;
+    // (degree, index) order of the neighbours an unknown appends: rows are
+    // short, so an insertion sort in place in the sequence
+    auto before = [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; };
+    while (len < n) {
         while (seen[by_deg[next_start]]) ++next_start;
         const int32_t s = by_deg[next_start];
         seen[s] = 1;
-        order.push_back(s);
-        for (; head < order.size(); ++head) {
+        order[len++] = s;
+        for (; head < len; ++head) {
             const int32_t u = order[head];
-            nb.clear();
-            for (int64_t p = rp[u]; p < rp[u + 1]; ++p)
-                if (!seen[ci[p]]) { seen[ci[p]] = 1; nb.push_back(ci[p]); }
-            std::sort(nb.begin(), nb.end(), [&](int32_t a, int32_t b) { return deg[a] != deg[b] ? deg[a] < deg[b] : a < b; });
-            order.insert(order.end(), nb.begin(), nb.end());
+            const int64_t first = len;
+            for (int64_t p = rp[u]; p < rp[u + 1]; ++p) {
+                const int32_t v = ci[p];
+                if (seen[v]) continue;
+                seen[v] = 1;
+                int64_t k = len++;
+                while (k > first && before(v, order[k - 1])) { order[k] = order[k - 1]; --k; }
+                order[k] = v;
+            }
         }
     }
     std::reverse(order.begin(), order.end());
@@ -363,25 +368,26 @@ extern "C" int hbmc_order_rcm(int32_t n, const int64_t *rowptr, const int32_t *c
         // the pattern renumbered: row k of it is row order[k] of the input
         std::vector<int32_t> ord, inv(n);
         rcm_order(n, rowptr, col, ord);
-        for (int32_t k = 0; k < n; ++k) inv[ord[k]] = k;
+        parallel_for(n, 1 << 16, [&](int64_t k) { inv[ord[k]] = int32_t(k); });
         std::vector<int64_t> rp(int64_t(n) + 1, 0);
         std::vector<int32_t> ci(size_t(rowptr[n]));
-        for (int32_t k = 0; k < n; ++k) {
+        for (int32_t k = 0; k < n; ++k) rp[k + 1] = rp[k] + (rowptr[ord[k] + 1] - rowptr[ord[k]]);
+        parallel_for(n, 1 << 14, [&](int64_t k) {
             const int32_t u = ord[k];
             int64_t at = rp[k];
             for (int64_t p = rowptr[u]; p < rowptr[u + 1]; ++p) ci[size_t(at++)] = inv[col[p]];
             std::sort(ci.begin() + rp[k], ci.begin() + at);
-            rp[k + 1] = at;
-        }
+        });
         const int64_t sys_ptr[2] = {0, n};
         hbmc_order_t *h = nullptr;
         if ((st = order_systems(1, sys_ptr, n, rp.data(), ci.data(), bs, w, false, &h))) return st;
         // back to the input's numbering
         std::vector<int32_t> perm(n);
-        for (int32_t u = 0; u < n; ++u) perm[u] = h->perm[inv[u]];
+        parallel_for(n, 1 << 16, [&](int64_t u) { perm[u] = h->perm[inv[u]]; });
         h->perm.swap(perm);
-        for (auto &v : h->iperm)
-            if (v >= 0) v = ord[v];
+        parallel_for(int64_t(h->iperm.size()), 1 << 16, [&](int64_t x) {
+            if (h->iperm[x] >= 0) h->iperm[x] = ord[h->iperm[x]];
+        });
         h->local = true;
         *out = h;
         return HBMC_OK;
