@@ -47,6 +47,10 @@ PROFILES = {
                                      "paper_1908_00741_amd/csrc/sweep_bs2.hip",
                                      "paper_1908_00741_amd/csrc/factor.cpp",
                                      "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
+    "knn1m_rcm": ("ic0_apply_knn1m_rcm.md", ["paper_1908_00741_amd/csrc/sweep.h",
+                                             "paper_1908_00741_amd/csrc/sweep_bs2.hip",
+                                             "paper_1908_00741_amd/csrc/factor.cpp",
+                                             "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
 }
 
 
@@ -239,6 +243,10 @@ def main() -> int:
                     ext[name] = experiments.fp32(dev, log=log)
                 elif name == "locality":
                     ext[name] = experiments.locality(dev, reps=args.apply_reps, log=log)
+                    r64 = ext[name]["rcm"]["f64"]
+                    tk = measured_traffic("knn1m_rcm")
+                    r64["apply_traffic"] = tk
+                    r64["apply_measured_gbs"] = None if tk is None else round(tk / (r64["apply_us_cold"] * 1e-6) / 1e9, 1)
                 elif name == "fp32_grid":
                     ext[name] = experiments.fp32_grid(dev, log=log)
                 elif name == "orderings":
