@@ -147,6 +147,7 @@ struct Phase {
     ApplyCg cg;
     bool fold;            // CG, first phase, k_sweep: alpha computed here (fold.h)
     bool xcd;             // k_rows: tiles in XCD-contiguous order
+    bool one_sys;         // CG: one system (its states are st[0 .. K), no tile lookup)
 };
 
 // Sum over the lanes j' of the wavefront with j' = j mod NR (the lanes of
@@ -532,8 +533,12 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
     const int q0 = grp * NR + j % NR;
     const bool qv = q0 < K;
     const Lane L{sub * (kLanes / NR) + j / NR, qv ? q0 : K - 1, K};
-    const CgState *cs = CG ? &ph.cg.st[int64_t(ph.cg.tile_sys[ph.tile0 + tile]) * K + L.q] : nullptr;
-    const bool live = qv && !(CG && cs->done);
+    // The state of the lane's (system, right-hand side).  With one system
+    // and one right-hand side its stop is the all-stopped flag checked above,
+    // so nothing waits for the state here (alpha is read where it is used).
+    const CgState *cs = CG ? &ph.cg.st[(ph.one_sys ? 0 : int64_t(ph.cg.tile_sys[ph.tile0 + tile]) * K) + L.q]
+                           : nullptr;
+    const bool live = qv && !(CG && !(ONE && ph.one_sys) && cs->done);
     if (CG && !__any(live)) return;              // every right-hand side of this wave has stopped
     const int64_t lam = tile * kLanes + L.jc;    // chain lane in the color
     const bool valid = lam < ph.nlane && live;
@@ -623,8 +628,10 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
     // hardware order is faster (solve 131.9 against 134.7 ms), and the
     // wavefront-per-tile kernel keeps it too (128^3 apply 51.5 against 53.2 us)
     const int64_t tile = ph.xcd ? xcd_block(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
-    const CgState *cs = CG ? &ph.cg.st[ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
-    if (CG && cs->done) return;                  // the whole workgroup: one tile
+    // the tile's system state; with one system its stop is the all-stopped
+    // flag checked above, and nothing waits for the state here
+    const CgState *cs = CG ? &ph.cg.st[ph.one_sys ? 0 : ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
+    if (CG && !ph.one_sys && cs->done) return;   // the whole workgroup: one tile
     const Lane L{j, 0, 1};
     const int64_t lam = tile * kLanes + j;
     const bool valid = lam < ph.nlane;
@@ -738,6 +745,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     ph.done = done;
     ph.cg = cg;
     ph.xcd = f->xcd_tiles;
+    ph.one_sys = f->nsys == 1;
     bool first_phase = CG && cg.stw != nullptr;   // the next launch computes alpha
     const size_t tw = sizeof(T) + sizeof(int32_t);
     size_t lds = 0;
