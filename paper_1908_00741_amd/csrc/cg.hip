@@ -215,6 +215,13 @@ __device__ inline Elem elem(int64_t n, int K, int m) {
 template <int NR>
 __device__ inline int64_t part_of_block() { return logical_block() / sub_blocks(NR); }
 
+// The CG state of the workgroup's part for right-hand side q: with one
+// system no table lookup (the state is st[q]).
+template <int NR>
+__device__ inline const CgState &state_of(const Sys &sys, const CgState *st, int K, int q) {
+    return st[(sys.nsys == 1 ? 0 : int64_t(sys.part_sys[part_of_block<NR>()]) * K) + q];
+}
+
 // One row of y = A x for one right-hand side, x(i) given by an accessor of
 // element indices; all 64 lanes of the wavefront must be active.  The
 // group's strided-slot bases and masks (at most 64) come in with one vector
@@ -458,8 +465,10 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
     if (*alldone) return;
     if (NR == 1) K = 1;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
-    const bool live = q0 < K && !c.done;          // a part lies in one system
+    const CgState &c = state_of<NR>(sys, st, K, q0 < K ? q0 : K - 1);
+    // a part lies in one system; with one system and one right-hand side its
+    // stop is the all-stopped flag above, and the loads need not wait for it
+    const bool live = q0 < K && ((NR == 1 && sys.nsys == 1) || !c.done);
     if (NR == 1 && !live) return;                  // workgroup-uniform with one right-hand side
     const double beta = c.beta, alpha = c.alpha;
     auto pv = [=](int64_t i) { return z[i] + beta * p_old[i]; };
@@ -493,8 +502,8 @@ __global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, 
                                                      const int32_t *alldone) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
-    if (q0 >= K || c.done) return;
+    const CgState &c = state_of<NR>(sys, st, K, q0 < K ? q0 : K - 1);
+    if (q0 >= K || (!(K == 1 && sys.nsys == 1) && c.done)) return;   // (one system and K = 1: the flag above)
     const double beta = c.beta, alpha = c.alpha;
 #pragma unroll 1
     for (int mm = 0; mm < rounds(NR); ++mm) {
@@ -516,7 +525,7 @@ __global__ void __launch_bounds__(kBlock) k_finish_x(int64_t n, int K, Sys sys, 
                                                      const double *__restrict__ p1, double *__restrict__ x,
                                                      const CgState *st) {
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
+    const CgState &c = state_of<NR>(sys, st, K, q0 < K ? q0 : K - 1);
     if (q0 >= K || c.it < 1 || c.alpha == 0.0) return;
     const double alpha = c.alpha;
     const double *p = (c.it & 1) ? p1 : p0;
@@ -537,8 +546,8 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, cons
                                                      const CgState *st, const int32_t *alldone) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
-    const CgState &c = st[int64_t(sys.part_sys[part_of_block<NR>()]) * K + (q0 < K ? q0 : K - 1)];
-    const bool live = q0 < K && !c.done;
+    const CgState &c = state_of<NR>(sys, st, K, q0 < K ? q0 : K - 1);
+    const bool live = q0 < K && ((K == 1 && sys.nsys == 1) || !c.done);
     auto pv = [=](int64_t i) { return p[i]; };
     double pq = 0.0;
 #pragma unroll 1
