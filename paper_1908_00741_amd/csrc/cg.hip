@@ -81,8 +81,19 @@ struct Sys {
 // that the latency of the partials' loads is paid once per kLoads, not once
 // per partial.
 constexpr int kLoads = 16;
-__device__ inline double sys_total(const double *part, const int32_t *ranges, int nc, int s, int tmul) {
+__device__ inline double sys_total(const double *part, const int32_t *ranges, int nc, int s, int tmul,
+                                   int64_t all = -1) {
     double acc = 0.0;
+    if (all >= 0) {   // one system: its partials are all of them, no range table to wait for
+        for (int64_t i0 = threadIdx.x; i0 < all; i0 += int64_t(kFin) * kLoads) {
+            double v[kLoads];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) v[k] = i0 + k * kFin < all ? part[i0 + k * kFin] : 0.0;
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) acc += v[k];
+        }
+        return block_sum(acc);
+    }
     for (int c = 0; c < nc;) {
         // ranges of consecutive colors that meet are summed as one (a single
         // system's partials are one range over all colors)
@@ -104,8 +115,26 @@ __device__ inline double sys_total(const double *part, const int32_t *ranges, in
 // both in flight together); each total is added in the same order as by
 // sys_total, so the results are the same bits.  Valid in thread 0.
 __device__ inline void sys_total2(const double *pa, const double *pb, const int32_t *ranges, int nc, int s,
-                                  int tmul, double &ta, double &tb) {
+                                  int tmul, double &ta, double &tb, int64_t all = -1) {
     double acc_a = 0.0, acc_b = 0.0;
+    if (all >= 0) {   // one system (as sys_total)
+        for (int64_t i0 = threadIdx.x; i0 < all; i0 += int64_t(kFin) * kLoads) {
+            double va[kLoads], vb[kLoads];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) {
+                const bool in = i0 + k * kFin < all;
+                va[k] = in ? pa[i0 + k * kFin] : 0.0;
+                vb[k] = in ? pb[i0 + k * kFin] : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) acc_a += va[k];
+#pragma unroll
+            for (int k = 0; k < kLoads; ++k) acc_b += vb[k];
+        }
+        ta = block_sum(acc_a);
+        tb = block_sum(acc_b);
+        return;
+    }
     for (int c = 0; c < nc;) {
         const int a = ranges[(s * nc + c) * 2] * tmul;
         int b = ranges[(s * nc + c) * 2 + 1] * tmul;
@@ -569,9 +598,10 @@ __global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t 
                                                     CgState *st, int32_t *ndone, int32_t *alldone) {
     const int b = blockIdx.x, s = b / K, q = b % K;
     CgState &c = st[b];
-    if (c.done) return;
-    const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, pmul);
-    if (threadIdx.x) return;
+    // the stop flag is read beside the partials, not before them
+    const int32_t done = c.done;
+    const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, pmul, sys.nsys == 1 ? np : -1);
+    if (threadIdx.x || done) return;
     c.sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
         c.done = kBreakdown;
@@ -593,10 +623,11 @@ __global__ void __launch_bounds__(kFin) k_fin_rr_beta(const double *part_rr, con
                                                       int32_t *ndone, int32_t *alldone) {
     const int b = blockIdx.x, s = b / K, q = b % K;
     CgState &c = st[b];
-    if (c.done) return;
+    const int32_t done = c.done;   // read beside the partials, not before them
     double rr, rz;
-    sys_total2(part_rr + q * ptiles, part_rz + q * ptiles, sys.tiles, sys.nc, s, tmul, rr, rz);
-    if (threadIdx.x) return;
+    sys_total2(part_rr + q * ptiles, part_rz + q * ptiles, sys.tiles, sys.nc, s, tmul, rr, rz,
+               sys.nsys == 1 ? ptiles : -1);
+    if (threadIdx.x || done) return;
     c.rr = rr;
     c.it += 1;
     c.res = sqrt(rr / c.bb);
