@@ -215,6 +215,23 @@ int hbmc_set_num_threads(int32_t threads);
 #define HBMC_KERNEL_ROWS 2
 int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel);
 
+/* Synchronization between the colors of the ROWS kernel (same results,
+ * different speed; Section 4.4.3 synchronizes once per color):
+ * HBMC_SYNC_LAUNCH -- one kernel launch per color phase, the launch
+ *   boundary being the synchronization;
+ * HBMC_SYNC_AUTO (default) -- where it applies (ROWS kernel, one system,
+ *   one right-hand side, at most 64 colors, and the solve, or
+ *   ic0_apply_ws), all phases in one launch: every forward value and every
+ *   result starts as a reserved bit pattern (a signalling NaN, which
+ *   arithmetic never yields), and a tile that reads a value of another
+ *   color waits until its owner has stored it.  Workgroups run in launch
+ *   order, which holds the phases in their sequential order, so the waits
+ *   end; each is also bounded in time (then NaN results and an error word).
+ *   Elsewhere as LAUNCH. */
+#define HBMC_SYNC_AUTO 0
+#define HBMC_SYNC_LAUNCH 1
+int hbmc_factor_set_sync(hbmc_factor_t *f, int32_t sync);
+
 /* Right-hand-side tile for nrhs > 1 (same results up to the order of the
  * partial sums, different speed): nr right-hand sides per wavefront, which
  * then covers 64/nr level-1-block lanes, nr lanes per lane of the factor
@@ -243,6 +260,20 @@ void hbmc_factor_destroy(hbmc_factor_t *f);
  */
 int ic0_apply(const hbmc_factor_t *f, const double *r, double *z, int32_t nrhs,
               void *stream);
+
+/* ic0_apply with a device workspace, which lets the ROWS kernel run all
+ * color phases in one launch (hbmc_factor_set_sync); same results.
+ * ws: device memory of at least ic0_apply_ws_bytes bytes, 256-byte
+ * aligned, owned by the caller; it holds the forward values (y) between
+ * the phases and, in its first 4 bytes, an error word that each call
+ * clears and that a wait past its time limit makes nonzero (z then holds
+ * NaN; read it after the stream has finished the call).  Calls that share
+ * ws must not overlap.  Where the one-launch form does not apply (or ws is
+ * NULL) this is ic0_apply and ws is not touched.  Errors: as ic0_apply;
+ * HBMC_EINVAL for a workspace too small or misaligned. */
+int ic0_apply_ws_bytes(const hbmc_factor_t *f, size_t *bytes);
+int ic0_apply_ws(const hbmc_factor_t *f, const double *r, double *z, int32_t nrhs, void *ws,
+                 size_t ws_bytes, void *stream);
 
 /* ---- coefficient matrix ----------------------------------------------------
  * The reordered matrix Abar = P A P^T (Section 3, eq. "AB") in a sliced ELL

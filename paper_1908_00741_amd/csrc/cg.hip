@@ -29,6 +29,7 @@
 #include <mutex>
 #include <vector>
 
+#include "flow.h"
 #include "fold.h"
 #include "xcd.h"
 #include "hbmc_internal.h"
@@ -524,11 +525,15 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot_p(Mat m, int K, Sys sys, co
 // the product below gathers p alone at the columns a row couples to (with
 // [n][K] vectors the gathered rows are K times longer and miss the caches;
 // forming p on the fly would gather z and p_old both).
+// With empty (one system, one right-hand side, the substitution in one
+// launch), z and p_old, dead once read, are marked kFlowEmpty for the next
+// preconditioning step, which computes into them (p_old holding its
+// forward values).
 template <int NR>
-__global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, const double *__restrict__ z,
-                                                     const double *__restrict__ p_old, double *__restrict__ p_new,
+__global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, double *__restrict__ z,
+                                                     double *__restrict__ p_old, double *__restrict__ p_new,
                                                      double *__restrict__ x, const CgState *st,
-                                                     const int32_t *alldone) {
+                                                     const int32_t *alldone, bool empty) {
     if (*alldone) return;
     const int q0 = int(blockIdx.y) * NR + int(threadIdx.x & 63) % NR;
     const CgState &c = state_of<NR>(sys, st, K, q0 < K ? q0 : K - 1);
@@ -542,6 +547,10 @@ __global__ void __launch_bounds__(kBlock) k_update_p(int64_t n, int K, Sys sys, 
             const double po = p_old[e];
             x[e] = x[e] + alpha * po;   // the previous iteration's step (lagged)
             p_new[e] = z[e] + beta * po;
+            if (empty) {
+                reinterpret_cast<uint64_t *>(z)[e] = kFlowEmpty;
+                reinterpret_cast<uint64_t *>(p_old)[e] = kFlowEmpty;
+            }
         }
     }
 }
@@ -763,7 +772,7 @@ struct Work {
     double *bb, *xb, *r, *z, *p[2], *q, *part_g, *part_rr, *part_rz, *resid, *hist;
     CgState *st;
     int32_t *ndone, *alldone;
-    int32_t *err;      // a wait for alpha inside a kernel ran past its time limit
+    int32_t *err;      // a wait inside a kernel ran past its time limit (1: alpha, 2: substitution)
     uint64_t *awords;  // [kFoldWords] alpha published inside a kernel (both parities, replicated)
     int64_t np;        // part partial slots per right-hand side (parts * pmul)
     int32_t pmul;      // sub-blocks per part of the vector kernels
@@ -872,11 +881,18 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
     const int K = w.K;
     const unsigned nst = unsigned(f->nsys) * K;
     double *p_old = w.p[parity], *p_new = w.p[1 - parity];
-    if (K == 1 && m.fuse_p) {
+    // The row kernel's phases in one launch (flow.h): p_old, dead once the
+    // direction update has read it (the lagged x update included), holds
+    // the forward values.  The update marks it and z empty where it streams
+    // them anyway; after the product that forms p itself a kernel does.
+    const bool flow = flow_ok(f, K);
+    const bool fused = K == 1 && m.fuse_p;
+    const Flow fl{p_old, w.err, fused, false};
+    if (fused) {
         VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.xb, w.q, w.part_g, w.np, w.st,
                    w.alldone);
     } else {
-        VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.xb, w.st, w.alldone);
+        VEC_LAUNCH(k_update_p, f->n_pad, K, s, f->n_pad, K, sys, w.z, p_old, p_new, w.xb, w.st, w.alldone, flow);
         VEC_LAUNCH_MAT(k_spmv_dot, m, f->n_pad, K, s, m, K, sys, p_new, w.q, w.part_g, w.np, w.st, w.alldone);
     }
     ApplyCg cg{w.q, w.r, w.st, at<int32_t>(f->dev, f->off_tile_sys), w.part_rr, w.part_rz,
@@ -900,7 +916,7 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
                            w.alldone);
         HIP_TRY(hipGetLastError());
     }
-    int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg, K);
+    int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg, K, false, flow ? &fl : nullptr);
     if (st) return st;
     hipLaunchKernelGGL(k_fin_rr_beta, dim3(nst), dim3(kFin), 0, s, w.part_rr, w.part_rz, w.ptiles, w.nr, K,
                        sys, w.st, history ? w.hist : nullptr, w.hist_len, w.ndone, w.alldone);
@@ -1081,7 +1097,10 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
     HIP_TRY(hipStreamSynchronize(s));
 
     if (hd[0] < nst) {
-        int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr, K);
+        // the first direction is written after this step, the second in
+        // the first iteration: p[1] is free to hold the forward values
+        const Flow fl{w.p[1], w.err, true, false};
+        int st = apply_launch(f, w.r, w.z, s, nullptr, nullptr, K, false, &fl);
         if (st) return st;
         VEC_LAUNCH(k_init_p, n, K, s, n, K, w.r, w.z, w.p[0], w.part_g, w.np);
         hipLaunchKernelGGL(k_fin_rho, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st);
@@ -1096,7 +1115,9 @@ int solve_in(hbmc_factor_s *f, const hbmc_matrix_t *A, const double *b, double *
                     if ((st = enqueue_iteration(f, m, w, s, history, parity))) return st;
             HIP_TRY(hipMemcpyAsync(hd, w.ndone, sizeof hd, hipMemcpyDeviceToHost, s));
             HIP_TRY(hipStreamSynchronize(s));
-            if (hd[2]) return fail(HBMC_EHIP, "a wait for alpha inside a kernel timed out");
+            if (hd[2])
+                return fail(HBMC_EHIP, "a wait inside a kernel timed out (%s)",
+                            hd[2] & 2 ? "a value of the substitution" : "alpha");
         }
     }
     // the last step of each system; pairs with b = 0 get x = 0; the

@@ -88,13 +88,29 @@ struct ApplyCg {
     int32_t fparity;
     int32_t *ferr, *ndone, *alldone;
 };
+// All phases of the row kernel in one launch (flow.h): y ([n_pad]) holds
+// the forward values, err is set by a wait past its time limit.  With
+// fill the launcher first marks y and z empty (and with reset_err clears
+// *err); else the caller has (the CG direction update does).
+constexpr int kFlowMaxColors = 64;
+struct Flow {
+    double *y;
+    int32_t *err;
+    bool fill;
+    bool reset_err;
+};
+// Whether the one-launch form applies to z = M^-1 r for K right-hand sides.
+bool flow_ok(const ::hbmc_factor_s *f, int K, bool fwd_only = false);
+
 // Enqueues z = M^-1 r for K right-hand sides ([n_pad][K]) on stream (a
 // hipStream_t).  When done is not null the kernels return at once while
 // *done != 0 (used inside captured CG loops).  With cg, r is taken from
 // cg->r after the update.  With fwd_only (and no cg), only the forward
-// substitution runs: z = (D + L)^-1 r.
+// substitution runs: z = (D + L)^-1 r.  With flow (and flow_ok) all phases
+// run in one launch.
 int apply_launch(const ::hbmc_factor_s *f, const double *r, double *z, void *stream,
-                 const int32_t *done, const ApplyCg *cg, int K, bool fwd_only = false);
+                 const int32_t *done, const ApplyCg *cg, int K, bool fwd_only = false,
+                 const Flow *flow = nullptr);
 // Right-hand sides per wavefront (NR) used for K right-hand sides.
 int rhs_tile(const ::hbmc_factor_s *f, int K);
 // Whether the phases run as one workgroup per tile (k_rows) rather than one
@@ -245,6 +261,7 @@ struct TriOffsets {
 struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int32_t kernel = HBMC_KERNEL_AUTO;
+    int32_t sync = HBMC_SYNC_AUTO;
     bool xcd_tiles = false;            // the row kernel takes tiles in XCD-contiguous order
     int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;

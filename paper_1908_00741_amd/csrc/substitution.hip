@@ -45,17 +45,46 @@ bool hbmc::use_rows(const hbmc_factor_s *f, int bs, int K, int nr) {
     return f->tile_base[f->nc] < 1024 * int64_t(f->nc) && f->fcnt.flat;
 }
 
+// The one-launch form of the row kernel (flow.h): one system, one
+// right-hand side, both substitutions, colors within the kernel's table.
+bool hbmc::flow_ok(const hbmc_factor_s *f, int K, bool fo) {
+    return f->sync == HBMC_SYNC_AUTO && !fo && K == 1 && f->nsys == 1 && f->nc >= 1 &&
+           f->nc <= kFlowMaxColors && use_rows(f, f->bs, 1, 1);
+}
+
+namespace {
+// Marks y and z empty for the one-launch form (rows [0, n)) unless *done;
+// with err, clears it.
+__global__ void __launch_bounds__(256) k_flow_fill(int64_t n, double *y, double *z, int32_t *err,
+                                                   const int32_t *done) {
+    if (done && *done) return;
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (err && i == 0) *err = 0;
+    if (i < n) {
+        reinterpret_cast<uint64_t *>(y)[i] = kFlowEmpty;
+        reinterpret_cast<uint64_t *>(z)[i] = kFlowEmpty;
+    }
+}
+}  // namespace
+
 int hbmc::apply_launch(const hbmc_factor_s *f, const double *r, double *z, void *stream,
-                       const int32_t *done, const ApplyCg *cg, int K, bool fo) {
+                       const int32_t *done, const ApplyCg *cg, int K, bool fo, const Flow *flow) {
     auto s = static_cast<hipStream_t>(stream);
     const int nr = rhs_tile(f, K);
+    const Flow *fl = flow && flow_ok(f, K, fo) ? flow : nullptr;
+    if (fl && fl->fill) {
+        const int64_t n = f->n_pad;
+        hipLaunchKernelGGL(k_flow_fill, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, fl->y, z,
+                           fl->reset_err ? fl->err : nullptr, done);
+        HIP_TRY(hipGetLastError());
+    }
     switch (f->bs) {
-        case 1: return launch_bs1(f, r, z, s, done, cg, K, nr, fo);
-        case 2: return launch_bs2(f, r, z, s, done, cg, K, nr, fo);
-        case 4: return launch_bs4(f, r, z, s, done, cg, K, nr, fo);
-        case 8: return launch_bs8(f, r, z, s, done, cg, K, nr, fo);
-        case 16: return launch_bs16(f, r, z, s, done, cg, K, nr, fo);
-        case 32: return launch_bs32(f, r, z, s, done, cg, K, nr, fo);
+        case 1: return launch_bs1(f, r, z, s, done, cg, K, nr, fo, fl);
+        case 2: return launch_bs2(f, r, z, s, done, cg, K, nr, fo, fl);
+        case 4: return launch_bs4(f, r, z, s, done, cg, K, nr, fo, fl);
+        case 8: return launch_bs8(f, r, z, s, done, cg, K, nr, fo, fl);
+        case 16: return launch_bs16(f, r, z, s, done, cg, K, nr, fo, fl);
+        case 32: return launch_bs32(f, r, z, s, done, cg, K, nr, fo, fl);
         default: return fail(HBMC_EINVAL, "bs = %d has no device kernel (1, 2, 4, 8, 16, 32)", f->bs);
     }
 }
@@ -91,6 +120,14 @@ extern "C" int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel) {
     return HBMC_OK;
 }
 
+extern "C" int hbmc_factor_set_sync(hbmc_factor_t *f, int32_t sync) {
+    if (!f) return fail(HBMC_EINVAL, "null handle");
+    if (sync != HBMC_SYNC_AUTO && sync != HBMC_SYNC_LAUNCH) return fail(HBMC_EINVAL, "unknown sync %d", sync);
+    f->sync = sync;
+    release_graphs(f);
+    return HBMC_OK;
+}
+
 extern "C" int hbmc_factor_set_rhs_tile(hbmc_factor_t *f, int32_t nr) {
     if (!f) return fail(HBMC_EINVAL, "null handle");
     if (nr != 0 && !tile_ok(nr)) return fail(HBMC_EINVAL, "right-hand-side tile %d (0, 4, 8, 16)", nr);
@@ -105,4 +142,28 @@ extern "C" int ic0_apply(const hbmc_factor_t *f, const double *r, double *z, int
     if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
     if (r == z) return fail(HBMC_EINVAL, "z must not alias r");
     return apply_launch(f, r, z, stream, nullptr, nullptr, nrhs);
+}
+
+// Workspace of ic0_apply_ws: the error word, then y ([n_pad] doubles).
+constexpr size_t kWsHead = 256;
+
+extern "C" int ic0_apply_ws_bytes(const hbmc_factor_t *f, size_t *bytes) {
+    if (!f || !bytes) return fail(HBMC_EINVAL, "null argument");
+    *bytes = kWsHead + size_t(f->n_pad) * sizeof(double);
+    return HBMC_OK;
+}
+
+extern "C" int ic0_apply_ws(const hbmc_factor_t *f, const double *r, double *z, int32_t nrhs, void *ws,
+                            size_t ws_bytes, void *stream) {
+    if (!f || !r || !z) return fail(HBMC_EINVAL, "null argument");
+    if (!f->dev) return fail(HBMC_ENOTREADY, "factor not uploaded");
+    if (nrhs < 1) return fail(HBMC_EINVAL, "nrhs = %d", nrhs);
+    if (r == z) return fail(HBMC_EINVAL, "z must not alias r");
+    if (!ws || !flow_ok(f, nrhs)) return apply_launch(f, r, z, stream, nullptr, nullptr, nrhs);
+    const size_t need = kWsHead + size_t(f->n_pad) * sizeof(double);
+    if (ws_bytes < need) return fail(HBMC_EINVAL, "workspace too small (%zu < %zu)", ws_bytes, need);
+    if (reinterpret_cast<uintptr_t>(ws) % 256) return fail(HBMC_EINVAL, "workspace not 256-byte aligned");
+    auto *b = static_cast<uint8_t *>(ws);
+    const Flow fl{reinterpret_cast<double *>(b + kWsHead), reinterpret_cast<int32_t *>(b), true, true};
+    return apply_launch(f, r, z, stream, nullptr, nullptr, nrhs, false, &fl);
 }

@@ -33,6 +33,7 @@
 #include <cmath>
 #include <vector>
 
+#include "flow.h"
 #include "fold.h"
 #include "xcd.h"
 #include "hbmc_internal.h"
@@ -42,19 +43,20 @@ namespace hbmc {
 // Launches the phases of one apply for factors of block size BS (defined in
 // sweep_bs<BS>.hip).  K right-hand sides, nr of them per wavefront.  With
 // fwd_only, only the forward substitution runs (z = (D + L)^-1 r, every
-// color in the forward form).
+// color in the forward form).  With fl, the row kernel's phases run in one
+// launch (flow.h; the caller has checked flow_ok).
 int launch_bs1(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 int launch_bs2(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 int launch_bs4(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 int launch_bs8(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-               const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 int launch_bs16(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 int launch_bs32(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg *cg, int K, int nr, bool fwd_only);
+               const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl);
 
 }  // namespace hbmc
 
@@ -202,9 +204,12 @@ struct Lane {
 // Strided slots read z[base + jc]; the bases and lane masks of the tile's
 // strided slots (at most 64) are fetched by one vector load, one slot per
 // lane, and broadcast with readlane, so no load waits on another.
-template <int BS, int CH, typename T>
+// WAIT (all phases in one launch, flow.h): a gathered value a lane uses is
+// waited for once the chunk's loads are back; lanes that drop the product
+// never wait (their address may belong to a later phase).
+template <int BS, int CH, typename T, bool WAIT = false>
 __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
-                                   const double *__restrict__ z) {
+                                   const double *__restrict__ z, int32_t *err = nullptr) {
     const int jc = L.jc;
     int32_t so[BS + 1];
 #pragma unroll
@@ -219,6 +224,8 @@ __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j,
     for (int l = 0; l < BS; ++l) smax = max(smax, so[l + 1] - so[l]);
     for (int c0 = 0; c0 < smax; c0 += CH) {
         T v[BS][CH], g[BS][CH];
+        double gd[BS][CH];
+        int32_t ix[BS][CH];
         bool on[BS][CH];
 #pragma unroll
         for (int l = 0; l < BS; ++l)
@@ -231,7 +238,15 @@ __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j,
                 const int64_t slot = has ? so[l] + c0 + k : E.spad;
                 on[l][k] = (mask >> jc) & 1;
                 v[l][k] = val[slot * kLanes + jc];
-                g[l][k] = T(z[L.at(base + jc)]);
+                ix[l][k] = base + jc;
+                gd[l][k] = z[L.at(ix[l][k])];
+            }
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                if (WAIT && on[l][k]) gd[l][k] = flow_take(gd[l][k], z + L.at(ix[l][k]), err);
+                g[l][k] = T(gd[l][k]);
             }
 #pragma unroll
         for (int l = 0; l < BS; ++l)
@@ -242,9 +257,9 @@ __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j,
 
 // Indexed slots: each loads the slot's lane mask and first entry, then the
 // lane's column.
-template <int BS, int CH, typename T>
+template <int BS, int CH, typename T, bool WAIT = false>
 __device__ inline void ext_packed(T (&acc)[BS], const Ext E, int64_t gt, const Lane &L,
-                                  const double *__restrict__ z) {
+                                  const double *__restrict__ z, int32_t *err = nullptr) {
     const int jc = L.jc;
     int32_t io[BS + 1];
 #pragma unroll
@@ -268,10 +283,18 @@ __device__ inline void ext_packed(T (&acc)[BS], const Ext E, int64_t gt, const L
                 v[l][k] = val[e];
             }
         T g[BS][CH];
+        double gd[BS][CH];
 #pragma unroll
         for (int l = 0; l < BS; ++l)
 #pragma unroll
-            for (int k = 0; k < CH; ++k) g[l][k] = T(z[L.at(col[l][k] >= 0 ? col[l][k] : 0)]);
+            for (int k = 0; k < CH; ++k) gd[l][k] = z[L.at(col[l][k] >= 0 ? col[l][k] : 0)];
+#pragma unroll
+        for (int l = 0; l < BS; ++l)
+#pragma unroll
+            for (int k = 0; k < CH; ++k) {
+                if (WAIT && col[l][k] >= 0) gd[l][k] = flow_take(gd[l][k], z + L.at(col[l][k]), err);
+                g[l][k] = T(gd[l][k]);
+            }
 #pragma unroll
         for (int l = 0; l < BS; ++l)
 #pragma unroll
@@ -333,8 +356,9 @@ __device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, c
 // (win: 2 * NW * 64 values); each chain lane then adds up its own entries
 // from the window in column order, the order and arithmetic of ext_lanes.
 // Groups longer than the window take several rounds.
-template <int NW, typename T>
-__device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const double *__restrict__ z, T *win) {
+template <int NW, typename T, bool WAIT = false>
+__device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const double *__restrict__ z, T *win,
+                             int32_t *err = nullptr) {
     const int64_t g0 = E.goff[g];
     const int ne = int(E.goff[g + 1] - g0);
     if (ne == 0) return acc;
@@ -344,7 +368,8 @@ __device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const doubl
     T *wv = win, *wz = win + NW * kLanes;
     for (int w0 = 0; w0 < ne; w0 += NW * kLanes) {
         const int nk = min(NW, (ne - w0 + kLanes - 1) / kLanes);
-        T v[NW], gz[NW];
+        T v[NW];
+        double gz[NW];
         int32_t col[NW];
 #pragma unroll
         for (int k = 0; k < NW; ++k)
@@ -355,12 +380,13 @@ __device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const doubl
             }
 #pragma unroll
         for (int k = 0; k < NW; ++k)
-            if (k < nk) gz[k] = T(z[col[k]]);
+            if (k < nk) gz[k] = z[col[k]];
 #pragma unroll
         for (int k = 0; k < NW; ++k)
             if (k < nk) {
+                if (WAIT) gz[k] = flow_take(gz[k], z + col[k], err);
                 wv[k * kLanes + j] = v[k];
-                wz[k * kLanes + j] = gz[k];
+                wz[k * kLanes + j] = T(gz[k]);
             }
         // the window is written by other lanes of this wavefront
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -414,14 +440,16 @@ __device__ inline void stage_steps(const Tri &E, int64_t gt, int l0, int l1, int
 // right-hand side after the couplings to other colors.  Stores y (forward
 // phases) or z, and with CG the (r, z) partial of the lane's right-hand side
 // at pslot.  MI == 0: couplings inside the block are staged into this
-// wavefront's LDS region sv/sl when lds, else read in place.
-template <int BS, typename T, int MODE, int MI, bool CG, int NR>
+// wavefront's LDS region sv/sl when lds, else read in place.  Forward
+// values go to yout when set (all phases in one launch), else to z; WT
+// stores them with agent-scope atomic stores (flow.h).
+template <int BS, typename T, int MODE, int MI, bool CG, int NR, bool WT = false>
 __device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], const double (&rn)[BS],
                               const T (&fv)[BS][MI > 0 ? MI : 1], const int32_t (&fl)[BS][MI > 0 ? MI : 1],
                               const T (&bv)[BS][MI > 0 ? MI : 1], const int32_t (&bl)[BS][MI > 0 ? MI : 1],
                               T *sv, int32_t *sl, bool lds, int64_t gt, int j, const Lane &L, int64_t rb,
                               bool valid, bool qv, double *__restrict__ z, int64_t pslot,
-                              T *svb = nullptr, int32_t *slb = nullptr) {
+                              T *svb = nullptr, int32_t *slb = nullptr, double *yout = nullptr) {
     constexpr int RM = MI > 0 ? MI : 1;
     const int w = ph.w;
     const int jc = L.jc;
@@ -457,7 +485,11 @@ __device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], 
                 for (int64_t s = s0; s < s1; ++s) a -= ival(ph.f, s) * pick<BS, T>(y, ilp(ph.f, s), 0, l);
             }
             y[l] = a * dv[l];
-            if (MODE == kForward && valid) z[L.at(rb + int64_t(l) * w)] = double(y[l]);
+            if (MODE == kForward && valid) {
+                double *d = (yout ? yout : z) + L.at(rb + int64_t(l) * w);
+                if (WT) flow_put(d, double(y[l]));
+                else *d = double(y[l]);
+            }
         }
     } else {
 #pragma unroll
@@ -478,7 +510,11 @@ __device__ inline void chains(const Phase &ph, T (&acc)[BS], const T (&dv)[BS], 
                 for (int64_t s = s0; s < s1; ++s) a -= ival(ph.b, s) * pick<BS, T>(y, ilp(ph.b, s), l + 1, BS);
             }
             y[l] = a;
-            if (valid) z[L.at(rb + int64_t(l) * w)] = double(a);
+            if (valid) {
+                double *d = z + L.at(rb + int64_t(l) * w);
+                if (WT) flow_put(d, double(a));
+                else *d = double(a);
+            }
         }
         if (CG) {
             double rz = 0.0;
@@ -609,36 +645,46 @@ __global__ void __launch_bounds__(WAVES * kLanes) k_sweep(Phase ph, const double
                                     rb, valid, qv, z, pslot);
 }
 
-// One color phase, one workgroup per tile with one wavefront per step: each
-// wavefront folds in the couplings to other colors of its step for the 64
-// lanes, the partial right-hand sides meet in LDS, and wavefront 0 runs the
-// chains.  Eight times the wavefronts of k_sweep, each with one step's loads:
-// best when a color has few tiles or its steps have many couplings.  One
-// right-hand side only.
-template <int BS, typename T, int MODE, int MI, int CH, bool CG>
-__global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph, const double *__restrict__ r,
-                                                      double *__restrict__ z) {
-    if (ph.done && *ph.done) return;
+// Where a tile of the row kernel reads and writes.  One launch per color:
+// everything in z (y of the colors whose forward sweep is done, z of those
+// whose backward sweep is done).  All phases in one launch (flow.h): the
+// forward values in y, the result in z, each waited for where it is read.
+struct RowsIo {
+    const double *gsrc;   // values gathered from other colors
+    const double *own;    // backward: y of the tile's own rows
+    double *yout;         // forward: y of the tile's own rows
+    int32_t *err;         // a wait past its time limit
+};
+
+// One tile of one color phase, one workgroup per tile with one wavefront
+// per step: each wavefront folds in the couplings to other colors of its
+// step for the 64 lanes, the partial right-hand sides meet in LDS, and
+// wavefront 0 runs the chains.  Eight times the wavefronts of k_sweep, each
+// with one step's loads: best when a color has few tiles or its steps have
+// many couplings.  One right-hand side only.
+// With FLOW and CG, r's update (r -= alpha q) is computed by the forward
+// tile for its sums and again, with the same single rounding, by the
+// backward tile of the same rows, which stores it: the forward tile never
+// writes r, so that no tile reads a value of r another workgroup stored.
+// The backward tile stores it only after the barrier that follows its wait
+// for the rows' own forward values, i.e. after the forward tile has read
+// the old r (it reads r before it stores those values).
+template <int BS, typename T, int MODE, int MI, int CH, bool CG, bool FLOW>
+__device__ inline void rows_tile(const Phase &ph, int64_t tile, int64_t row0, int64_t tile0, int64_t nlane,
+                                 const double *__restrict__ r, double *__restrict__ z, const RowsIo &io) {
     const int l = __builtin_amdgcn_readfirstlane(int(threadIdx.x) / kLanes);   // this wave's step
     const int j = threadIdx.x % kLanes;
-    // XCD-contiguous tiles for an ordering with locality (after the
-    // renumbering): the tiles one XCD takes gather from neighbouring places
-    // (1M-point 13-NN graph after reverse Cuthill-McKee: 217.7 -> 198.5 us
-    // per apply, solve 104.9 -> 101.8 ms).  In the shuffled numbering the
-    // hardware order is faster (solve 131.9 against 134.7 ms), and the
-    // wavefront-per-tile kernel keeps it too (128^3 apply 51.5 against 53.2 us)
-    const int64_t tile = ph.xcd ? xcd_block(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
     // the tile's system state; with one system its stop is the all-stopped
-    // flag checked above, and nothing waits for the state here
-    const CgState *cs = CG ? &ph.cg.st[ph.one_sys ? 0 : ph.cg.tile_sys[ph.tile0 + tile]] : nullptr;
+    // flag checked on entry, and nothing waits for the state here
+    const CgState *cs = CG ? &ph.cg.st[ph.one_sys ? 0 : ph.cg.tile_sys[tile0 + tile]] : nullptr;
     if (CG && !ph.one_sys && cs->done) return;   // the whole workgroup: one tile
     const Lane L{j, 0, 1};
     const int64_t lam = tile * kLanes + j;
-    const bool valid = lam < ph.nlane;
+    const bool valid = lam < nlane;
     const int w = ph.w;
-    const int64_t lc = valid ? lam : ph.nlane - 1;
-    const int64_t rb = ph.row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
-    const int64_t gt = (ph.tile0 + tile) * BS;
+    const int64_t lc = valid ? lam : nlane - 1;
+    const int64_t rb = row0 + ((lc >> ph.lw) << ph.lw) * BS + (lc & (w - 1));
+    const int64_t gt = (tile0 + tile) * BS;
 
     extern __shared__ __align__(16) unsigned char smem[];
     double *srn = reinterpret_cast<double *>(smem);          // [BS][64] (CG)
@@ -663,17 +709,29 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
     }
     const int64_t row = rb + int64_t(l) * w;
     double rn1 = 0.0, rr = 0.0;
-    const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
-    T acc1[1] = {row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn1, rr)};
+    T acc1[1];
+    if constexpr (FLOW) {
+        if (CG) {
+            const double alpha = cs->alpha;
+            rn1 = __builtin_fma(-alpha, ph.cg.q[row], ph.cg.r[row]);
+            if (MODE != kBackward && valid) rr += rn1 * rn1;
+        }
+        if (MODE == kBackward) acc1[0] = T(flow_take(io.own[row], io.own + row, io.err));
+        else acc1[0] = T(CG ? rn1 : r[row]);
+    } else {
+        const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
+        acc1[0] = row_rhs<T, MODE, CG>(ph, r, z, row, valid, alpha, rn1, rr);
+    }
     if (MODE != kBackward) sd[l * kLanes + j] = static_cast<const T *>(ph.dinv)[row];
     if (MI == 0 && ph.lds_slots > 0) {   // this step's couplings inside the block
         if (MODE != kBackward) stage_steps<T>(ph.f, gt, l, l + 1, j, svf, slf);
         if (MODE != kForward) stage_steps<T>(ph.b, gt, l, l + 1, j, svb, slb);
     }
     const Ext &ext = MODE == kBackward ? ph.b.ext : ph.f.ext;
-    ext_strided<1, CH, T>(acc1, ext, gt + l, j, L, z);
-    if (ext.flat) acc1[0] = ext_split<NW, T>(acc1[0], ext, gt + l, j, z, win);
-    else ext_packed<1, CH, T>(acc1, ext, gt + l, L, z);
+    const double *src = FLOW ? io.gsrc : z;
+    ext_strided<1, CH, T, FLOW>(acc1, ext, gt + l, j, L, src, io.err);
+    if (ext.flat) acc1[0] = ext_split<NW, T, FLOW>(acc1[0], ext, gt + l, j, src, win, io.err);
+    else ext_packed<1, CH, T, FLOW>(acc1, ext, gt + l, L, src, io.err);
     sq[l * kLanes + j] = acc1[0];
     if (CG) {
         srn[l * kLanes + j] = rn1;
@@ -683,6 +741,7 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
         }
     }
     __syncthreads();
+    if (FLOW && CG && MODE != kForward && valid) ph.cg.r[row] = rn1;   // see above
     if (l != 0) return;
 
     T acc[BS], dv[BS];
@@ -697,10 +756,72 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
         double t = 0.0;
 #pragma unroll
         for (int k = 0; k < BS; ++k) t += srr[k];
-        ph.cg.part_rr[ph.tile0 + tile] = t;
+        ph.cg.part_rr[tile0 + tile] = t;
     }
-    chains<BS, T, MODE, MI, CG, 1>(ph, acc, dv, rn, fv, fl, bv, bl, svf, slf, ph.lds_slots > 0, gt, j, L, rb,
-                                   valid, true, z, ph.tile0 + tile, svb, slb);
+    chains<BS, T, MODE, MI, CG, 1, FLOW>(ph, acc, dv, rn, fv, fl, bv, bl, svf, slf, ph.lds_slots > 0, gt, j, L,
+                                         rb, valid, true, z, tile0 + tile, svb, slb, FLOW ? io.yout : nullptr);
+}
+
+// One color phase of the row kernel, a workgroup per tile.
+template <int BS, typename T, int MODE, int MI, int CH, bool CG>
+__global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph, const double *__restrict__ r,
+                                                      double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    // XCD-contiguous tiles for an ordering with locality (after the
+    // renumbering): the tiles one XCD takes gather from neighbouring places
+    // (1M-point 13-NN graph after reverse Cuthill-McKee: 217.7 -> 198.5 us
+    // per apply, solve 104.9 -> 101.8 ms).  In the shuffled numbering the
+    // hardware order is faster (solve 131.9 against 134.7 ms), and the
+    // wavefront-per-tile kernel keeps it too (128^3 apply 51.5 against 53.2 us)
+    const int64_t tile = ph.xcd ? xcd_block(blockIdx.x, gridDim.x) : int64_t(blockIdx.x);
+    rows_tile<BS, T, MODE, MI, CH, CG, false>(ph, tile, ph.row0, ph.tile0, ph.nlane, r, z, RowsIo{});
+}
+
+// The phases of one apply in one launch (flow.h).  Workgroups
+// [pblock[p], pblock[p + 1]) run phase p: forward color p for p < nc - 1,
+// the last color for p = nc - 1, then backward color 2 nc - 2 - p.  With
+// XCD-contiguous tiles every phase starts at a multiple of 8 workgroups
+// (the extra ones return at once), so that its own tiles are spread the
+// way k_rows spreads them.
+struct FlowTab {
+    int64_t color_start[kFlowMaxColors + 1];
+    int64_t tile_base[kFlowMaxColors + 1];
+    int32_t pblock[2 * kFlowMaxColors];
+    int32_t nc;
+    double *y;        // forward values, kFlowEmpty on entry
+    int32_t *err;
+};
+
+template <int BS, typename T, int MI, int CH, bool CG>
+__global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_flow(Phase ph, FlowTab ft,
+                                                      const double *__restrict__ r, double *__restrict__ z) {
+    if (ph.done && *ph.done) return;
+    const int32_t b = int32_t(blockIdx.x);
+    const int np = 2 * ft.nc - 1;
+    int lo = 0, hi = np - 1;   // the last phase starting at or before b
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (ft.pblock[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    const int p = lo;
+    const int c = p < ft.nc ? p : 2 * ft.nc - 2 - p;
+    const int64_t i = b - ft.pblock[p];
+    const int64_t nb = (p + 1 < np ? int64_t(ft.pblock[p + 1]) : int64_t(gridDim.x)) - ft.pblock[p];
+    const int64_t tile = ph.xcd ? xcd_block(i, nb) : i;
+    const int64_t tile0 = ft.tile_base[c];
+    if (tile >= ft.tile_base[c + 1] - tile0) return;
+    const int64_t row0 = ft.color_start[c];
+    const int64_t nlane = (ft.color_start[c + 1] - row0) / BS;
+    if (p < ft.nc - 1)
+        rows_tile<BS, T, kForward, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
+                                                    RowsIo{ft.y, nullptr, ft.y, ft.err});
+    else if (p == ft.nc - 1)
+        rows_tile<BS, T, kLast, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
+                                                 RowsIo{ft.y, nullptr, nullptr, ft.err});
+    else
+        rows_tile<BS, T, kBackward, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
+                                                     RowsIo{z, ft.y, nullptr, ft.err});
 }
 
 // ---------------------------------------------------------------------------
@@ -727,7 +848,7 @@ Tri tri_of(const ::hbmc_factor_s *f, const TriOffsets &o, const LayoutCounts &e)
 
 template <int BS, typename T, int MI, bool CG, int NR>
 int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s,
-                  const int32_t *done, const ApplyCg &cg, int K, bool fwd_only) {
+                  const int32_t *done, const ApplyCg &cg, int K, bool fwd_only, const Flow *fl) {
     constexpr int CH = BS <= 4 ? 4 : (BS <= 8 ? 2 : 1);   // measured best on 128^3, bs 8
     constexpr int WAVES = MI > 0 ? 4 : 1;                 // k_sweep: wavefronts per workgroup
     constexpr int CHR = 16;                               // k_rows: slots per chunk
@@ -761,6 +882,36 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
         lds = size_t(BS) * kLanes * (8 + 2 * sizeof(T)) + 8 * BS + 2 * size_t(ph.lds_slots) * kLanes * tw + split;
     else
         lds = size_t(WAVES) * ph.lds_slots * kLanes * tw;
+    const int nc = f->nc;
+    if (fl) {
+        if constexpr (NR == 1) {
+            if (!rows || K != 1 || fwd_only || nc > kFlowMaxColors || f->nsys != 1)
+                return fail(HBMC_EINVAL, "internal: the one-launch form does not apply");
+            FlowTab ft{};
+            ft.nc = nc;
+            ft.y = fl->y;
+            ft.err = fl->err;
+            for (int c = 0; c <= nc; ++c) {
+                ft.color_start[c] = f->color_start[c];
+                ft.tile_base[c] = f->tile_base[c];
+            }
+            int64_t blocks = 0;
+            for (int p = 0; p < 2 * nc - 1; ++p) {
+                const int c = p < nc ? p : 2 * nc - 2 - p;
+                const int64_t nt = f->tile_base[c + 1] - f->tile_base[c];
+                ft.pblock[p] = int32_t(blocks);
+                blocks += ph.xcd ? (nt + kXcds - 1) / kXcds * kXcds : nt;
+                if (blocks > int64_t(INT32_MAX)) return fail(HBMC_EINVAL, "too many workgroups for one launch");
+            }
+            if (blocks == 0) return HBMC_OK;
+            hipLaunchKernelGGL((k_flow<BS, T, MI, CHR, CG>), dim3(unsigned(blocks)), dim3(BS * kLanes), lds, s, ph,
+                               ft, r, z);
+            SWEEP_TRY(hipGetLastError());
+            return HBMC_OK;
+        } else {
+            return fail(HBMC_EINVAL, "internal: the one-launch form runs one right-hand side");
+        }
+    }
     auto run = [&](int c, auto sweep, auto rowk) -> int {
         ph.row0 = f->color_start[c];
         ph.row1 = f->color_start[c + 1];
@@ -782,7 +933,6 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
         SWEEP_TRY(hipGetLastError());
         return HBMC_OK;
     };
-    const int nc = f->nc;
     int st;
     if (fwd_only) {
         if (CG) return fail(HBMC_EINVAL, "internal: forward-only substitution inside CG");
@@ -805,12 +955,12 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
 // right-hand sides per wavefront: 1 (one right-hand side), 4, 8 or 16
 template <int BS, typename T, int MI, bool CG>
 int dispatch_nr(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg &cg, int K, int nr, bool fo) {
+                const ApplyCg &cg, int K, int nr, bool fo, const Flow *fl) {
     switch (nr) {
-        case 1: return launch_phases<BS, T, MI, CG, 1>(f, r, z, s, done, cg, K, fo);
-        case 4: return launch_phases<BS, T, MI, CG, 4>(f, r, z, s, done, cg, K, fo);
-        case 8: return launch_phases<BS, T, MI, CG, 8>(f, r, z, s, done, cg, K, fo);
-        case 16: return launch_phases<BS, T, MI, CG, 16>(f, r, z, s, done, cg, K, fo);
+        case 1: return launch_phases<BS, T, MI, CG, 1>(f, r, z, s, done, cg, K, fo, fl);
+        case 4: return launch_phases<BS, T, MI, CG, 4>(f, r, z, s, done, cg, K, fo, fl);
+        case 8: return launch_phases<BS, T, MI, CG, 8>(f, r, z, s, done, cg, K, fo, fl);
+        case 16: return launch_phases<BS, T, MI, CG, 16>(f, r, z, s, done, cg, K, fo, fl);
         default: return fail(HBMC_EINVAL, "right-hand-side tile %d (1, 4, 8, 16)", nr);
     }
 }
@@ -818,23 +968,23 @@ int dispatch_nr(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_
 // couplings per step inside a level-1 block: <= 1, <= 2, or more (LDS path)
 template <int BS, typename T, bool CG>
 int dispatch_mi(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                const ApplyCg &cg, int K, int nr, bool fo) {
+                const ApplyCg &cg, int K, int nr, bool fo, const Flow *fl) {
     const int mi = std::max(f->max_int_step_f, f->max_int_step_b);
-    if (mi <= 1) return dispatch_nr<BS, T, 1, CG>(f, r, z, s, done, cg, K, nr, fo);
-    if (BS <= 16 && mi <= 2) return dispatch_nr<BS, T, 2, CG>(f, r, z, s, done, cg, K, nr, fo);
-    return dispatch_nr<BS, T, 0, CG>(f, r, z, s, done, cg, K, nr, fo);
+    if (mi <= 1) return dispatch_nr<BS, T, 1, CG>(f, r, z, s, done, cg, K, nr, fo, fl);
+    if (BS <= 16 && mi <= 2) return dispatch_nr<BS, T, 2, CG>(f, r, z, s, done, cg, K, nr, fo, fl);
+    return dispatch_nr<BS, T, 0, CG>(f, r, z, s, done, cg, K, nr, fo, fl);
 }
 
 template <int BS>
 int launch_bs(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-              const ApplyCg *cgp, int K, int nr, bool fo) {
+              const ApplyCg *cgp, int K, int nr, bool fo, const Flow *fl) {
     if (!cgp) {
         const ApplyCg none{};
-        return f->precision == HBMC_F64 ? dispatch_mi<BS, double, false>(f, r, z, s, done, none, K, nr, fo)
-                                        : dispatch_mi<BS, float, false>(f, r, z, s, done, none, K, nr, fo);
+        return f->precision == HBMC_F64 ? dispatch_mi<BS, double, false>(f, r, z, s, done, none, K, nr, fo, fl)
+                                        : dispatch_mi<BS, float, false>(f, r, z, s, done, none, K, nr, fo, fl);
     }
-    return f->precision == HBMC_F64 ? dispatch_mi<BS, double, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo)
-                                    : dispatch_mi<BS, float, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo);
+    return f->precision == HBMC_F64 ? dispatch_mi<BS, double, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo, fl)
+                                    : dispatch_mi<BS, float, true>(f, cgp->r, z, s, done, *cgp, K, nr, fo, fl);
 }
 
 }  // namespace

@@ -4,6 +4,6 @@
 #include "sweep.h"
 
 int hbmc::launch_bs32(const ::hbmc_factor_s *f, const double *r, double *z, hipStream_t s, const int32_t *done,
-                   const ApplyCg *cg, int K, int nr, bool fwd_only) {
-    return launch_bs<32>(f, r, z, s, done, cg, K, nr, fwd_only);
+                   const ApplyCg *cg, int K, int nr, bool fwd_only, const Flow *fl) {
+    return launch_bs<32>(f, r, z, s, done, cg, K, nr, fwd_only, fl);
 }

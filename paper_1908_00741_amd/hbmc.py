@@ -20,6 +20,7 @@ HBMC_OK, HBMC_EINVAL, HBMC_ENOTSYM, HBMC_EDIAG, HBMC_EBREAKDOWN = 0, -1, -2, -3,
 HBMC_EHIP, HBMC_ENOMEM, HBMC_ENOTREADY, HBMC_ENOCONV = -5, -6, -7, 1
 HBMC_F64, HBMC_F32 = 0, 1
 HBMC_KERNEL_AUTO, HBMC_KERNEL_SWEEP, HBMC_KERNEL_ROWS = 0, 1, 2
+HBMC_SYNC_AUTO, HBMC_SYNC_LAUNCH = 0, 1
 HBMC_SMOOTH_SYMMETRIC, HBMC_SMOOTH_FORWARD = 0, 1
 
 # every symbol include/hbmc.h declares
@@ -28,7 +29,7 @@ SYMBOLS = (
     "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
     "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "hbmc_factor_set_rhs_tile",
-    "ic0_apply", "hbmc_matrix_create",
+    "hbmc_factor_set_sync", "ic0_apply", "ic0_apply_ws_bytes", "ic0_apply_ws", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_solve_noalloc",
     "iccg_history",
@@ -93,6 +94,9 @@ def lib():
         L.hbmc_factor_destroy.argtypes = [P]
         L.hbmc_factor_destroy.restype = None
         L.ic0_apply.argtypes = [P, P, P, i32, P]
+        L.hbmc_factor_set_sync.argtypes = [P, i32]
+        L.ic0_apply_ws_bytes.argtypes = [P, P]
+        L.ic0_apply_ws.argtypes = [P, P, P, i32, P, sz, P]
         L.hbmc_matrix_create.argtypes = [P, P, P, P, P]
         L.hbmc_matrix_device_bytes.argtypes = [P, P]
         L.hbmc_matrix_upload.argtypes = [P, P, sz, P]
@@ -252,6 +256,15 @@ class Factor:
     def set_kernel(self, kernel: int):
         _check("hbmc_factor_set_kernel", lib().hbmc_factor_set_kernel(self._h, int(kernel)))
         return self
+
+    def set_sync(self, sync: int):
+        _check("hbmc_factor_set_sync", lib().hbmc_factor_set_sync(self._h, int(sync)))
+        return self
+
+    def apply_ws_bytes(self) -> int:
+        b = C.c_size_t(0)
+        _check("ic0_apply_ws_bytes", lib().ic0_apply_ws_bytes(self._h, C.byref(b)))
+        return b.value
 
     def set_rhs_tile(self, nr: int):
         _check("hbmc_factor_set_rhs_tile", lib().hbmc_factor_set_rhs_tile(self._h, int(nr)))
@@ -465,6 +478,36 @@ def ic0_apply(f: Factor, r, z=None, nrhs: int = 1, stream=None):
     _vec_check(z, f.n_pad, nrhs, "z")
     _check("ic0_apply", lib().ic0_apply(f.handle, _dptr(r), _dptr(z), nrhs, _stream(stream)))
     return z
+
+
+def apply_workspace(f: Factor, device="cuda"):
+    """A device workspace for ic0_apply_ws (ic0_apply_ws_bytes bytes)."""
+    import torch
+    return torch.zeros(f.apply_ws_bytes(), dtype=torch.uint8, device=device)
+
+
+def ic0_apply_ws(f: Factor, r, z=None, ws=None, nrhs: int = 1, stream=None):
+    """ic0_apply with a workspace (the one-launch form of the row kernel
+    where it applies); ws from apply_workspace, allocated if None."""
+    import torch
+    _vec_check(r, f.n_pad, nrhs, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    _vec_check(z, f.n_pad, nrhs, "z")
+    if ws is None:
+        ws = apply_workspace(f, r.device)
+    if ws.dtype != torch.uint8 or not ws.is_contiguous():
+        raise ValueError("ws must be a contiguous uint8 tensor")
+    _check("ic0_apply_ws", lib().ic0_apply_ws(f.handle, _dptr(r), _dptr(z), nrhs, _dptr(ws), ws.numel(),
+                                              _stream(stream)))
+    return z
+
+
+def apply_ws_error(ws) -> int:
+    """The error word of an ic0_apply_ws workspace (nonzero: a wait timed
+    out and z holds NaN); synchronizes with the device."""
+    import torch
+    return int(ws[:4].view(torch.int32).item())
 
 
 def smooth_workspace(f: Factor, nrhs: int = 1, device="cuda"):
