@@ -45,10 +45,14 @@ PROFILES = {
                                                    "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
     "knn1m": ("ic0_apply_knn1m.md", ["paper_1908_00741_amd/csrc/sweep.h",
                                      "paper_1908_00741_amd/csrc/sweep_bs2.hip",
+                                     "paper_1908_00741_amd/csrc/flow.h",
+                                     "paper_1908_00741_amd/csrc/substitution.hip",
                                      "paper_1908_00741_amd/csrc/factor.cpp",
                                      "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
     "knn1m_rcm": ("ic0_apply_knn1m_rcm.md", ["paper_1908_00741_amd/csrc/sweep.h",
                                              "paper_1908_00741_amd/csrc/sweep_bs2.hip",
+                                             "paper_1908_00741_amd/csrc/flow.h",
+                                             "paper_1908_00741_amd/csrc/substitution.hip",
                                              "paper_1908_00741_amd/csrc/factor.cpp",
                                              "paper_1908_00741_amd/csrc/hbmc_internal.h"]),
 }

@@ -74,6 +74,7 @@ using namespace hbmc;
 
 constexpr int kLanes = kTileLanes;
 constexpr size_t kMaxLds = 64 * 1024;      // LDS budget of one workgroup (general path)
+constexpr size_t kLdsPerCu = 160 * 1024;   // LDS of one CU
 
 // Device pointers of a factor's Packed layout: strided slots per group,
 // then the left-over couplings either in indexed slots or in flat form
@@ -904,8 +905,16 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
                 if (blocks > int64_t(INT32_MAX)) return fail(HBMC_EINVAL, "too many workgroups for one launch");
             }
             if (blocks == 0) return HBMC_OK;
-            hipLaunchKernelGGL((k_flow<BS, T, MI, CHR, CG>), dim3(unsigned(blocks)), dim3(BS * kLanes), lds, s, ph,
-                               ft, r, z);
+            // At most four workgroups per CU (five for an ordering with
+            // locality), set through the LDS each takes: more resident tiles
+            // only wait longer and crowd the caches.  1M-point 13-NN graph,
+            // bs 2, w 32, FP32 apply (FP64 takes four by its own LDS):
+            // shuffled 239 us with eight per CU, 196 with four, 204 with
+            // five, 220 with three; renumbered 158 / 148 / 142 / 166 us.
+            const int per_cu = f->xcd_tiles ? 5 : 4;
+            const size_t lds_flow = std::max(lds, kLdsPerCu / size_t(per_cu + 1) + 1);
+            hipLaunchKernelGGL((k_flow<BS, T, MI, CHR, CG>), dim3(unsigned(blocks)), dim3(BS * kLanes), lds_flow, s,
+                               ph, ft, r, z);
             SWEEP_TRY(hipGetLastError());
             return HBMC_OK;
         } else {
