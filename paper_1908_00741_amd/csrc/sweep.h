@@ -780,10 +780,11 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_rows(Phase ph
 
 // The phases of one apply in one launch (flow.h).  Workgroups
 // [pblock[p], pblock[p + 1]) run phase p: forward color p for p < nc - 1,
-// the last color for p = nc - 1, then backward color 2 nc - 2 - p.  With
-// XCD-contiguous tiles every phase starts at a multiple of 8 workgroups
-// (the extra ones return at once), so that its own tiles are spread the
-// way k_rows spreads them.
+// the last color for p = nc - 1, then backward color 2 nc - 2 - p.  Tiles
+// in the hardware order: the XCD-contiguous order that helps k_rows after
+// the renumbering measured slightly slower here (1M-point 13-NN graph,
+// renumbered, FP64: apply 153.6 against 152.6 us, solve 80.3 against
+// 79.2 ms).
 struct FlowTab {
     int64_t color_start[kFlowMaxColors + 1];
     int64_t tile_base[kFlowMaxColors + 1];
@@ -807,9 +808,7 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_flow(Phase ph
     }
     const int p = lo;
     const int c = p < ft.nc ? p : 2 * ft.nc - 2 - p;
-    const int64_t i = b - ft.pblock[p];
-    const int64_t nb = (p + 1 < np ? int64_t(ft.pblock[p + 1]) : int64_t(gridDim.x)) - ft.pblock[p];
-    const int64_t tile = ph.xcd ? xcd_block(i, nb) : i;
+    const int64_t tile = b - ft.pblock[p];
     const int64_t tile0 = ft.tile_base[c];
     if (tile >= ft.tile_base[c + 1] - tile0) return;
     const int64_t row0 = ft.color_start[c];
@@ -899,14 +898,13 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
             int64_t blocks = 0;
             for (int p = 0; p < 2 * nc - 1; ++p) {
                 const int c = p < nc ? p : 2 * nc - 2 - p;
-                const int64_t nt = f->tile_base[c + 1] - f->tile_base[c];
                 ft.pblock[p] = int32_t(blocks);
-                blocks += ph.xcd ? (nt + kXcds - 1) / kXcds * kXcds : nt;
+                blocks += f->tile_base[c + 1] - f->tile_base[c];
                 if (blocks > int64_t(INT32_MAX)) return fail(HBMC_EINVAL, "too many workgroups for one launch");
             }
             if (blocks == 0) return HBMC_OK;
             // At most four workgroups per CU (five for an ordering with
-            // locality), set through the LDS each takes: more resident tiles
+            // locality, i.e. after the renumbering), set through the LDS each takes: more resident tiles
             // only wait longer and crowd the caches.  1M-point 13-NN graph,
             // bs 2, w 32, FP32 apply (FP64 takes four by its own LDS):
             // shuffled 239 us with eight per CU, 196 with four, 204 with

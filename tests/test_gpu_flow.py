@@ -10,10 +10,9 @@ Every case also checks that no wait ran past its time limit (the
 workspace's error word is 0).  Covered: FP64 and FP32 factors; bs 1, 2, 4,
 8, 16 (bs 32 falls back to launches and must be unchanged); grids (strided
 slots) and graphs (flat form with row splitting, packed slots); a ragged
-last tile; the pattern renumbered by reverse Cuthill-McKee (tiles in
-XCD-contiguous order, phases padded to whole groups of eight workgroups);
-the 1M-point 13-NN Laplacian at full size; repeated calls on one
-workspace; the captured CG graph replayed.
+last tile; the pattern renumbered by reverse Cuthill-McKee (five
+workgroups per CU instead of four); the 1M-point 13-NN Laplacian at full
+size; repeated calls on one workspace; the captured CG graph replayed.
 """
 import numpy as np
 import pytest
