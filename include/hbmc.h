@@ -219,8 +219,8 @@ int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel);
  * different speed; Section 4.4.3 synchronizes once per color):
  * HBMC_SYNC_LAUNCH -- one kernel launch per color phase, the launch
  *   boundary being the synchronization;
- * HBMC_SYNC_AUTO (default) -- where it applies (ROWS kernel, one system,
- *   one right-hand side, at most 64 colors, and the solve, or
+ * HBMC_SYNC_AUTO (default) -- where it applies (ROWS kernel, bs <= 4, one
+ *   system, one right-hand side, at most 64 colors, and the solve, or
  *   ic0_apply_ws), all phases in one launch: every forward value and every
  *   result starts as a reserved bit pattern (a signalling NaN, which
  *   arithmetic never yields), and a tile that reads a value of another

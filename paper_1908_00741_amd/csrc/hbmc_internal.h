@@ -93,6 +93,12 @@ struct ApplyCg {
 // fill the launcher first marks y and z empty (and with reset_err clears
 // *err); else the caller has (the CG direction update does).
 constexpr int kFlowMaxColors = 64;
+// Largest block size that takes the one-launch form: with bs 8 a tile's
+// chain is long and its workgroup of bs wavefronts large, and a launch per
+// phase is faster (1M-point 13-NN graph, row kernel, w 64: solve 254.9
+// against 284.7 ms; bs 1 w 64, bs 2 w 32, bs 4 w 16 gain: 139.1 -> 133.8,
+// 128.7 -> 110.4, 148.8 -> 134.4 ms).
+constexpr int kFlowMaxBs = 4;
 struct Flow {
     double *y;
     int32_t *err;

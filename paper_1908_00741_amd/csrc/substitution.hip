@@ -46,10 +46,11 @@ bool hbmc::use_rows(const hbmc_factor_s *f, int bs, int K, int nr) {
 }
 
 // The one-launch form of the row kernel (flow.h): one system, one
-// right-hand side, both substitutions, colors within the kernel's table.
+// right-hand side, both substitutions, colors within the kernel's table,
+// block sizes up to kFlowMaxBs.
 bool hbmc::flow_ok(const hbmc_factor_s *f, int K, bool fo) {
     return f->sync == HBMC_SYNC_AUTO && !fo && K == 1 && f->nsys == 1 && f->nc >= 1 &&
-           f->nc <= kFlowMaxColors && use_rows(f, f->bs, 1, 1);
+           f->nc <= kFlowMaxColors && f->bs <= kFlowMaxBs && use_rows(f, f->bs, 1, 1);
 }
 
 namespace {

@@ -884,7 +884,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
         lds = size_t(WAVES) * ph.lds_slots * kLanes * tw;
     const int nc = f->nc;
     if (fl) {
-        if constexpr (NR == 1) {
+        if constexpr (NR == 1 && BS <= kFlowMaxBs) {
             if (!rows || K != 1 || fwd_only || nc > kFlowMaxColors || f->nsys != 1)
                 return fail(HBMC_EINVAL, "internal: the one-launch form does not apply");
             FlowTab ft{};
@@ -916,7 +916,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
             SWEEP_TRY(hipGetLastError());
             return HBMC_OK;
         } else {
-            return fail(HBMC_EINVAL, "internal: the one-launch form runs one right-hand side");
+            return fail(HBMC_EINVAL, "internal: the one-launch form runs one right-hand side, bs <= %d", kFlowMaxBs);
         }
     }
     auto run = [&](int c, auto sweep, auto rowk) -> int {

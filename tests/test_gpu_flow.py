@@ -7,8 +7,8 @@ with the oracle the parity tests establish), and the CG solve with the
 factor's synchronization set to automatic against the same solve with one
 launch per color (iteration counts, stopping residuals and x all equal).
 Every case also checks that no wait ran past its time limit (the
-workspace's error word is 0).  Covered: FP64 and FP32 factors; bs 1, 2, 4,
-8, 16 (bs 32 falls back to launches and must be unchanged); grids (strided
+workspace's error word is 0).  Covered: FP64 and FP32 factors; bs 1, 2, 4
+(bs 8 and above fall back to launches and must be unchanged); grids (strided
 slots) and graphs (flat form with row splitting, packed slots); a ragged
 last tile; the pattern renumbered by reverse Cuthill-McKee (five
 workgroups per CU instead of four); the 1M-point 13-NN Laplacian at full
