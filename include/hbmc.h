@@ -232,6 +232,13 @@ int hbmc_factor_set_kernel(hbmc_factor_t *f, int32_t kernel);
 #define HBMC_SYNC_LAUNCH 1
 int hbmc_factor_set_sync(hbmc_factor_t *f, int32_t sync);
 
+/* Time limit of each wait in the one-launch form, in microseconds (0: the
+ * default, 50 ms, far above any legitimate wait).  A wait past it sets the
+ * error word (ic0_apply_ws's, or the solve's: HBMC_EHIP) and yields NaN;
+ * every later wait of the call then gives up at once.  Small values are for
+ * tests of that path.  HBMC_EINVAL outside 0 .. 60,000,000. */
+int hbmc_factor_set_wait_limit(hbmc_factor_t *f, int64_t us);
+
 /* Right-hand-side tile for nrhs > 1 (same results up to the order of the
  * partial sums, different speed): nr right-hand sides per wavefront, which
  * then covers 64/nr level-1-block lanes, nr lanes per lane of the factor

@@ -26,15 +26,23 @@ namespace hbmc {
 // signalling NaN comes out quieted), so no computed value has these bits.
 constexpr uint64_t kFlowEmpty = 0x7FF00000DEADBEEFull;
 
+// The error word and the time limit of every wait (ticks of the 100 MHz
+// real-time counter).
+struct FlowWait {
+    int32_t *err;
+    uint64_t ticks;
+};
+
 // The value at p once it is stored; past the time limit, or once another
 // wait has timed out, a quiet NaN.
-__device__ inline double flow_wait(const double *p, int32_t *err) {
+__device__ inline double flow_wait(const double *p, const FlowWait &fw) {
     const uint64_t *w = reinterpret_cast<const uint64_t *>(p);
     const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    int32_t *err = fw.err;
     uint64_t v;
     while ((v = get(w)) == kFlowEmpty) {
         if (get(err) != 0) return __builtin_nan("");
-        if (__builtin_amdgcn_s_memrealtime() - t0 > kFoldWaitTicks) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > fw.ticks) {
             atomicOr(err, 2);
             return __builtin_nan("");
         }
@@ -45,8 +53,8 @@ __device__ inline double flow_wait(const double *p, int32_t *err) {
 
 // v, loaded from p by an ordinary load (which may see a stale empty line in
 // a cache), or the stored value once it is there.
-__device__ inline double flow_take(double v, const double *p, int32_t *err) {
-    return __double_as_longlong(v) == int64_t(kFlowEmpty) ? flow_wait(p, err) : v;
+__device__ inline double flow_take(double v, const double *p, const FlowWait &fw) {
+    return __double_as_longlong(v) == int64_t(kFlowEmpty) ? flow_wait(p, fw) : v;
 }
 
 __device__ inline void flow_put(double *p, double v) {

@@ -268,6 +268,7 @@ struct hbmc_factor_s {
     int32_t n = 0, bs = 0, w = 0, nc = 0, precision = HBMC_F64;
     int32_t kernel = HBMC_KERNEL_AUTO;
     int32_t sync = HBMC_SYNC_AUTO;
+    uint64_t wait_ticks = 5000000;     // time limit of a wait in the one-launch form (100 MHz ticks: 50 ms)
     bool xcd_tiles = false;            // the row kernel takes tiles in XCD-contiguous order
     int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;

@@ -129,6 +129,14 @@ extern "C" int hbmc_factor_set_sync(hbmc_factor_t *f, int32_t sync) {
     return HBMC_OK;
 }
 
+extern "C" int hbmc_factor_set_wait_limit(hbmc_factor_t *f, int64_t us) {
+    if (!f) return fail(HBMC_EINVAL, "null handle");
+    if (us < 0 || us > 60000000) return fail(HBMC_EINVAL, "wait limit %lld us (0 .. 60000000)", (long long)us);
+    f->wait_ticks = us == 0 ? 5000000 : uint64_t(us) * 100;
+    release_graphs(f);
+    return HBMC_OK;
+}
+
 extern "C" int hbmc_factor_set_rhs_tile(hbmc_factor_t *f, int32_t nr) {
     if (!f) return fail(HBMC_EINVAL, "null handle");
     if (nr != 0 && !tile_ok(nr)) return fail(HBMC_EINVAL, "right-hand-side tile %d (0, 4, 8, 16)", nr);

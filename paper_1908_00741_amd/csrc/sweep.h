@@ -210,7 +210,7 @@ struct Lane {
 // never wait (their address may belong to a later phase).
 template <int BS, int CH, typename T, bool WAIT = false>
 __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j, const Lane &L,
-                                   const double *__restrict__ z, int32_t *err = nullptr) {
+                                   const double *__restrict__ z, const FlowWait &fw = FlowWait{}) {
     const int jc = L.jc;
     int32_t so[BS + 1];
 #pragma unroll
@@ -246,7 +246,7 @@ __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j,
         for (int l = 0; l < BS; ++l)
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                if (WAIT && on[l][k]) gd[l][k] = flow_take(gd[l][k], z + L.at(ix[l][k]), err);
+                if (WAIT && on[l][k]) gd[l][k] = flow_take(gd[l][k], z + L.at(ix[l][k]), fw);
                 g[l][k] = T(gd[l][k]);
             }
 #pragma unroll
@@ -260,7 +260,7 @@ __device__ inline void ext_strided(T (&acc)[BS], const Ext E, int64_t gt, int j,
 // lane's column.
 template <int BS, int CH, typename T, bool WAIT = false>
 __device__ inline void ext_packed(T (&acc)[BS], const Ext E, int64_t gt, const Lane &L,
-                                  const double *__restrict__ z, int32_t *err = nullptr) {
+                                  const double *__restrict__ z, const FlowWait &fw = FlowWait{}) {
     const int jc = L.jc;
     int32_t io[BS + 1];
 #pragma unroll
@@ -293,7 +293,7 @@ __device__ inline void ext_packed(T (&acc)[BS], const Ext E, int64_t gt, const L
         for (int l = 0; l < BS; ++l)
 #pragma unroll
             for (int k = 0; k < CH; ++k) {
-                if (WAIT && col[l][k] >= 0) gd[l][k] = flow_take(gd[l][k], z + L.at(col[l][k]), err);
+                if (WAIT && col[l][k] >= 0) gd[l][k] = flow_take(gd[l][k], z + L.at(col[l][k]), fw);
                 g[l][k] = T(gd[l][k]);
             }
 #pragma unroll
@@ -359,7 +359,7 @@ __device__ inline void ext_sweep(T (&acc)[BS], const Ext E, int64_t gt, int j, c
 // Groups longer than the window take several rounds.
 template <int NW, typename T, bool WAIT = false>
 __device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const double *__restrict__ z, T *win,
-                             int32_t *err = nullptr) {
+                             const FlowWait &fw = FlowWait{}) {
     const int64_t g0 = E.goff[g];
     const int ne = int(E.goff[g + 1] - g0);
     if (ne == 0) return acc;
@@ -385,7 +385,7 @@ __device__ inline T ext_split(T acc, const Ext &E, int64_t g, int j, const doubl
 #pragma unroll
         for (int k = 0; k < NW; ++k)
             if (k < nk) {
-                if (WAIT) gz[k] = flow_take(gz[k], z + col[k], err);
+                if (WAIT) gz[k] = flow_take(gz[k], z + col[k], fw);
                 wv[k * kLanes + j] = v[k];
                 wz[k * kLanes + j] = T(gz[k]);
             }
@@ -654,7 +654,7 @@ struct RowsIo {
     const double *gsrc;   // values gathered from other colors
     const double *own;    // backward: y of the tile's own rows
     double *yout;         // forward: y of the tile's own rows
-    int32_t *err;         // a wait past its time limit
+    FlowWait fw;          // error word and time limit of the waits
 };
 
 // One tile of one color phase, one workgroup per tile with one wavefront
@@ -717,7 +717,7 @@ __device__ inline void rows_tile(const Phase &ph, int64_t tile, int64_t row0, in
             rn1 = __builtin_fma(-alpha, ph.cg.q[row], ph.cg.r[row]);
             if (MODE != kBackward && valid) rr += rn1 * rn1;
         }
-        if (MODE == kBackward) acc1[0] = T(flow_take(io.own[row], io.own + row, io.err));
+        if (MODE == kBackward) acc1[0] = T(flow_take(io.own[row], io.own + row, io.fw));
         else acc1[0] = T(CG ? rn1 : r[row]);
     } else {
         const double alpha = CG && MODE != kBackward ? cs->alpha : 0.0;
@@ -730,9 +730,9 @@ __device__ inline void rows_tile(const Phase &ph, int64_t tile, int64_t row0, in
     }
     const Ext &ext = MODE == kBackward ? ph.b.ext : ph.f.ext;
     const double *src = FLOW ? io.gsrc : z;
-    ext_strided<1, CH, T, FLOW>(acc1, ext, gt + l, j, L, src, io.err);
-    if (ext.flat) acc1[0] = ext_split<NW, T, FLOW>(acc1[0], ext, gt + l, j, src, win, io.err);
-    else ext_packed<1, CH, T, FLOW>(acc1, ext, gt + l, L, src, io.err);
+    ext_strided<1, CH, T, FLOW>(acc1, ext, gt + l, j, L, src, io.fw);
+    if (ext.flat) acc1[0] = ext_split<NW, T, FLOW>(acc1[0], ext, gt + l, j, src, win, io.fw);
+    else ext_packed<1, CH, T, FLOW>(acc1, ext, gt + l, L, src, io.fw);
     sq[l * kLanes + j] = acc1[0];
     if (CG) {
         srn[l * kLanes + j] = rn1;
@@ -791,7 +791,7 @@ struct FlowTab {
     int32_t pblock[2 * kFlowMaxColors];
     int32_t nc;
     double *y;        // forward values, kFlowEmpty on entry
-    int32_t *err;
+    FlowWait fw;
 };
 
 template <int BS, typename T, int MI, int CH, bool CG>
@@ -815,13 +815,13 @@ __global__ void __launch_bounds__(BS <= 16 ? BS * kLanes : 1024) k_flow(Phase ph
     const int64_t nlane = (ft.color_start[c + 1] - row0) / BS;
     if (p < ft.nc - 1)
         rows_tile<BS, T, kForward, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
-                                                    RowsIo{ft.y, nullptr, ft.y, ft.err});
+                                                    RowsIo{ft.y, nullptr, ft.y, ft.fw});
     else if (p == ft.nc - 1)
         rows_tile<BS, T, kLast, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
-                                                 RowsIo{ft.y, nullptr, nullptr, ft.err});
+                                                 RowsIo{ft.y, nullptr, nullptr, ft.fw});
     else
         rows_tile<BS, T, kBackward, MI, CH, CG, true>(ph, tile, row0, tile0, nlane, r, z,
-                                                     RowsIo{z, ft.y, nullptr, ft.err});
+                                                     RowsIo{z, ft.y, nullptr, ft.fw});
 }
 
 // ---------------------------------------------------------------------------
@@ -890,7 +890,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
             FlowTab ft{};
             ft.nc = nc;
             ft.y = fl->y;
-            ft.err = fl->err;
+            ft.fw = FlowWait{fl->err, f->wait_ticks};
             for (int c = 0; c <= nc; ++c) {
                 ft.color_start[c] = f->color_start[c];
                 ft.tile_base[c] = f->tile_base[c];

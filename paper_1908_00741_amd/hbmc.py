@@ -29,7 +29,7 @@ SYMBOLS = (
     "hbmc_order_perm",
     "hbmc_order_destroy", "ic0_factor", "hbmc_factor_export", "hbmc_factor_device_bytes",
     "hbmc_factor_upload", "hbmc_factor_destroy", "hbmc_factor_set_kernel", "hbmc_factor_set_rhs_tile",
-    "hbmc_factor_set_sync", "ic0_apply", "ic0_apply_ws_bytes", "ic0_apply_ws", "hbmc_matrix_create",
+    "hbmc_factor_set_sync", "hbmc_factor_set_wait_limit", "ic0_apply", "ic0_apply_ws_bytes", "ic0_apply_ws", "hbmc_matrix_create",
     "hbmc_matrix_device_bytes", "hbmc_matrix_upload", "hbmc_matrix_destroy", "hbmc_spmv",
     "hbmc_to_hbmc", "hbmc_from_hbmc", "iccg_workspace_bytes", "iccg_solve", "iccg_solve_noalloc",
     "iccg_history",
@@ -95,6 +95,7 @@ def lib():
         L.hbmc_factor_destroy.restype = None
         L.ic0_apply.argtypes = [P, P, P, i32, P]
         L.hbmc_factor_set_sync.argtypes = [P, i32]
+        L.hbmc_factor_set_wait_limit.argtypes = [P, i64]
         L.ic0_apply_ws_bytes.argtypes = [P, P]
         L.ic0_apply_ws.argtypes = [P, P, P, i32, P, sz, P]
         L.hbmc_matrix_create.argtypes = [P, P, P, P, P]
@@ -259,6 +260,10 @@ class Factor:
 
     def set_sync(self, sync: int):
         _check("hbmc_factor_set_sync", lib().hbmc_factor_set_sync(self._h, int(sync)))
+        return self
+
+    def set_wait_limit(self, us: int):
+        _check("hbmc_factor_set_wait_limit", lib().hbmc_factor_set_wait_limit(self._h, int(us)))
         return self
 
     def apply_ws_bytes(self) -> int:

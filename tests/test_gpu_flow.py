@@ -137,3 +137,35 @@ def test_solve_one_launch_graph_replay(torch):
         _ = (x_g * 2).sum().item()          # eager work between replays
         assert st_g.iters == st_e.iters and st_g.status == hbmc.HBMC_OK
         assert torch.equal(x_g, x_e)
+
+
+def test_wait_limit_reports_time_out(torch):
+    """The failure path, forced from the host: with a 1 us limit the waits of
+    the one-launch form run out long before the values they wait for are
+    stored (all 27 phases of the 100k-point graph are resident at once), so
+    ic0_apply_ws must set its error word and leave NaN in z, and the solve
+    must report the time-out; back at the default limit both give the same
+    bits as one launch per phase again (the next call clears the word)."""
+    A = inputs.knn_laplacian(100_000, 13, 4, 5, shift=1e-3)
+    o = hbmc.hbmc_order(A, 2, 32)
+    f = hbmc.ic0_factor(o, A).set_kernel(hbmc.HBMC_KERNEL_ROWS).upload()
+    solver = hbmc.Solver(o, f, hbmc.hbmc_matrix_create(o, A).upload())
+    b = torch.from_numpy(inputs.uniform_rhs(A.n, 6)).cuda()
+    ws = hbmc.apply_workspace(f)
+    r = _rhs(torch, o, 3)
+    z_ref = hbmc.ic0_apply(f, r)
+    f.set_wait_limit(1)
+    z = hbmc.ic0_apply_ws(f, r, ws=ws)
+    torch.cuda.synchronize()
+    assert hbmc.apply_ws_error(ws) != 0
+    assert torch.isnan(z).any()
+    with pytest.raises(hbmc.HbmcError, match="timed out"):
+        solver.solve(b, tol=1e-7)
+    f.set_wait_limit(0)
+    z = hbmc.ic0_apply_ws(f, r, ws=ws)
+    torch.cuda.synchronize()
+    assert hbmc.apply_ws_error(ws) == 0 and torch.equal(z, z_ref)
+    x, st = solver.solve(b, tol=1e-7)
+    f.set_sync(hbmc.HBMC_SYNC_LAUNCH)
+    x0, st0 = solver.solve(b, tol=1e-7)
+    assert st.status == hbmc.HBMC_OK and st.iters == st0.iters and torch.equal(x, x0)

@@ -340,3 +340,22 @@ def test_rhs_tile_errors():
         with pytest.raises(hbmc.HbmcError) as e:
             f.set_rhs_tile(bad)
         assert e.value.code == hbmc.HBMC_EINVAL
+
+
+def test_one_launch_settings_and_workspace_size():
+    """The synchronization and wait-limit settings take their documented
+    values only; ic0_apply_ws's workspace is the 256-byte error-word head
+    plus one FP64 value per padded row."""
+    A = inputs.knn_laplacian(3000, 13, 4, 5)
+    o = hbmc.hbmc_order(A, 2, 32)
+    f = hbmc.ic0_factor(o, A)
+    assert f.apply_ws_bytes() == 256 + 8 * o.n_pad
+    for ok in (hbmc.HBMC_SYNC_AUTO, hbmc.HBMC_SYNC_LAUNCH):
+        f.set_sync(ok)
+    for ok in (0, 1, 50_000, 60_000_000):
+        f.set_wait_limit(ok)
+    for bad, setter in ((2, f.set_sync), (-1, f.set_sync), (-1, f.set_wait_limit),
+                        (60_000_001, f.set_wait_limit)):
+        with pytest.raises(hbmc.HbmcError) as e:
+            setter(bad)
+        assert e.value.code == hbmc.HBMC_EINVAL
