@@ -5,7 +5,9 @@ the C ABI.
 The two run the same kernels in the same order on the same inputs, so the
 solutions and statistics must be the same bits.  Two calls in a row, the
 second on a smaller system (the scratch keeps the first call's contents;
-the solve must clear what starts at zero), then the first system again.
+the solve must clear what starts at zero), then a graph Laplacian whose
+substitution runs its color phases in one launch (its forward values and
+empty markers live in the scratch too), then the first system again.
 Argument errors (workspace larger than the scratch, graph replay, residual
 history) come back before any device work.
 """
@@ -63,6 +65,12 @@ def test_noalloc_matches_iccg_solve_twice(torch):
     print("case noalloc grid64 nrhs 3", flush=True)
     x_ref, st_ref, x, st = _pair(torch, s_small, b_small, 3, 1e-7, 10000)
     assert all(s.status == hbmc.HBMC_OK for s in st)
+    _same(x_ref, st_ref, x, st)
+    print("case noalloc knn20000 nrhs 1 (row kernel, color phases in one launch)", flush=True)
+    knn = inputs.knn_laplacian(20000, 13, 4, 5, shift=1e-3)   # bs 2, w 32: row kernel, one launch
+    s_knn = hbmc.Solver.setup(knn, 2, 32)
+    x_ref, st_ref, x, st = _pair(torch, s_knn, _dev(torch, inputs.uniform_rhs(knn.n, 6)), 1, 1e-7, 10000)
+    assert st.status == hbmc.HBMC_OK and st.true_rel_res < 1.5e-7
     _same(x_ref, st_ref, x, st)
     print("case noalloc diffusion40 again, maxit 7", flush=True)
     x_ref, st_ref, x, st = _pair(torch, s_big, b_big, 1, 1e-7, 7)
