@@ -359,3 +359,37 @@ def test_one_launch_settings_and_workspace_size():
         with pytest.raises(hbmc.HbmcError) as e:
             setter(bad)
         assert e.value.code == hbmc.HBMC_EINVAL
+
+
+@pytest.mark.parametrize("name,make,bs,w,rcm", [
+    ("knn_20000_bs2_w32", lambda: inputs.knn_laplacian(20000, 13, 4, 5, shift=1e-3), 2, 32, False),
+    ("knn_20000_bs2_w32_rcm", lambda: inputs.knn_laplacian(20000, 13, 4, 5, shift=1e-3), 2, 32, True),
+    ("knn_3000_bs4_w8", lambda: inputs.knn_laplacian(3000, 13, 6, 7), 4, 8, False),
+    ("grid_ragged_bs4_w8", lambda: inputs.grid2d_5pt(37, 11), 4, 8, False),
+    ("random_bs1_w64", lambda: inputs.random_spd(1500, 0.004, 7), 1, 64, False),
+], ids=lambda v: v if isinstance(v, str) else "")
+def test_one_launch_waits_only_on_earlier_phases(name, make, bs, w, rcm):
+    """What makes the one-launch substitution's waits end: in the factor the
+    library builds, every coupling of a row to another level-1 block belongs
+    to an earlier color (the forward sweep waits on its y) -- so, U being
+    L's transpose, the backward sweep waits only on later colors' z -- and
+    couplings inside a color stay inside one level-1 block, where the chain
+    computes them without a wait.  The phase order (forward colors up, then
+    backward colors down) therefore puts every awaited value in an earlier
+    phase."""
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w, rcm=rcm)
+    _, cs = o.perm()
+    _, rp, ci, _ = hbmc.ic0_factor(o, A).export()
+    rows = np.repeat(np.arange(o.n_pad), np.diff(rp))
+    color = np.searchsorted(cs, np.arange(o.n_pad), side="right") - 1
+    local = np.arange(o.n_pad) - cs[color]
+    block = (color.astype(np.int64) << 40) | ((local // (bs * w)) << 16) | (local % w)   # level-1 block id
+    ci = ci.astype(np.int64)
+    assert np.all(ci < rows)                                   # strictly lower
+    earlier = color[ci] < color[rows]
+    same_block = block[ci] == block[rows]
+    assert np.all(earlier | same_block), name
+    assert np.all(color[ci] <= color[rows])
+    step = (local // w) % bs                                   # in-block: an earlier step of the chain
+    assert np.all(step[ci][same_block] < step[rows][same_block])
