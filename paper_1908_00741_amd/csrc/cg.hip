@@ -48,6 +48,7 @@ namespace {
 constexpr int kLanes = kTileLanes;
 constexpr int kBlock = kPartRows;   // threads of the vector kernels: one row each
 constexpr int kFin = 1024;       // threads of the finalizing kernels (one workgroup per system)
+constexpr int64_t kFinFillRows = 32768;   // largest system whose α finalizer marks the step's vectors empty
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -603,13 +604,24 @@ __global__ void __launch_bounds__(kBlock) k_spmv_dot(Mat m, int K, Sys sys, cons
 }
 
 // sigma = (p, Ap); alpha = rho / sigma
+// With fy (one system, one right-hand side, a small system whose
+// preconditioning step runs in one launch after the product that forms p):
+// also marks fy and fz ([fn]) empty for that step, in place of a kernel of
+// its own, unless the system has stopped (the old direction in fy may then
+// hold the last step's direction).
 __global__ void __launch_bounds__(kFin) k_fin_alpha(const double *part, int64_t np, int pmul, int K, Sys sys,
-                                                    CgState *st, int32_t *ndone, int32_t *alldone) {
+                                                    CgState *st, int32_t *ndone, int32_t *alldone,
+                                                    double *fy, double *fz, int64_t fn) {
     const int b = blockIdx.x, s = b / K, q = b % K;
     CgState &c = st[b];
     // the stop flag is read beside the partials, not before them
     const int32_t done = c.done;
     const double sigma = sys_total(part + q * np, sys.parts, sys.nc, s, pmul, sys.nsys == 1 ? np : -1);
+    if (fy && !done)
+        for (int64_t i = threadIdx.x; i < fn; i += blockDim.x) {
+            reinterpret_cast<uint64_t *>(fy)[i] = kFlowEmpty;
+            reinterpret_cast<uint64_t *>(fz)[i] = kFlowEmpty;
+        }
     if (threadIdx.x || done) return;
     c.sigma = sigma;
     if (!(sigma > 0.0) || !isfinite(sigma)) {
@@ -887,7 +899,11 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
     // them anyway; after the product that forms p itself a kernel does.
     const bool flow = flow_ok(f, K);
     const bool fused = K == 1 && m.fuse_p;
-    const Flow fl{p_old, w.err, fused, false};
+    // small systems: the α finalizer marks them, one launch fewer per
+    // iteration (64x64 grid, 64 iterations: 2.95 -> 2.88 ms eager, 1.62 ->
+    // 1.55 ms replayed as a graph; a launch per phase: 3.07 / 1.63 ms)
+    const bool fin_fill = flow && fused && f->n_pad <= kFinFillRows;
+    const Flow fl{p_old, w.err, fused && !fin_fill, false};
     if (fused) {
         VEC_LAUNCH(k_spmv_dot_p, f->n_pad, K, s, m, K, sys, w.z, p_old, p_new, w.xb, w.q, w.part_g, w.np, w.st,
                    w.alldone);
@@ -913,7 +929,7 @@ int enqueue_iteration(const hbmc_factor_s *f, const Mat &m, const Work &w, hipSt
         cg.alldone = w.alldone;
     } else {
         hipLaunchKernelGGL(k_fin_alpha, dim3(nst), dim3(kFin), 0, s, w.part_g, w.np, w.pmul, K, sys, w.st, w.ndone,
-                           w.alldone);
+                           w.alldone, fin_fill ? p_old : nullptr, fin_fill ? w.z : nullptr, f->n_pad);
         HIP_TRY(hipGetLastError());
     }
     int st = apply_launch(f, w.r, w.z, s, w.alldone, &cg, K, false, flow ? &fl : nullptr);

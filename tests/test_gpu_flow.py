@@ -119,12 +119,20 @@ def test_solve_one_launch_matches_launches(torch, name, make, bs, w, rcm, precis
     assert torch.equal(x1, x0), (x1 - x0).abs().max().item()
 
 
-def test_solve_one_launch_graph_replay(torch):
+@pytest.mark.parametrize("name,make,bs,w", [
+    ("knn_20000_bs2_w32", lambda: inputs.knn_laplacian(20000, 13, 4, 5, shift=1e-3), 2, 32),
+    ("grid64_bs4_w8", lambda: inputs.grid2d_5pt(64), 4, 8),
+], ids=["knn_20000", "grid64"])
+def test_solve_one_launch_graph_replay(torch, name, make, bs, w):
     """The captured CG graph (pairs of iterations, no-op iterations past the
     stop) with the one-launch substitution, replayed with several check
-    intervals, against eager launches with one launch per color."""
-    A = inputs.knn_laplacian(20000, 13, 4, 5, shift=1e-3)
-    o = hbmc.hbmc_order(A, 2, 32)
+    intervals, against eager launches with one launch per color.  On the
+    grid the product forms p itself and the α finalizer marks the step's
+    vectors empty, except past the stop, where the old direction may be the
+    last step's."""
+    print(f"case graph {name}", flush=True)
+    A = make()
+    o = hbmc.hbmc_order(A, bs, w)
     f = hbmc.ic0_factor(o, A).set_kernel(hbmc.HBMC_KERNEL_ROWS).upload()
     solver = hbmc.Solver(o, f, hbmc.hbmc_matrix_create(o, A).upload())
     b = torch.from_numpy(inputs.uniform_rhs(A.n, 3)).cuda()
