@@ -227,7 +227,8 @@ def locality(device, npts=1_000_000, bs=2, w=32, tol=1e-7, reps=20, log=print):
     """The kNN problem in the input's (shuffled) numbering and renumbered by
     reverse Cuthill-McKee before the ordering: the paper's blocking seeds in
     the input numbering, so its layouts inherit that numbering's locality,
-    and the gathers of the substitutions and the SpMV follow it."""
+    and the gathers of the substitutions and the SpMV follow it.  Each
+    apply and solve is also timed with one launch per color phase."""
     import time
     import torch
     A = inputs.knn_laplacian(npts, 13, 4, 5, shift=1e-3)
@@ -245,9 +246,16 @@ def locality(device, npts=1_000_000, bs=2, w=32, tol=1e-7, reps=20, log=print):
                             label=f"locality {numbering} {name}")
             sv = hbmc.Solver(o, hbmc.ic0_factor(o, A, prec).upload(device), m)
             t, (x, st) = _timed(lambda: sv.solve(b, tol=tol))
-            r[name] = {"apply_us_cold": ap["median_us_cold"], "apply_frac": ap["frac"], "solve_ms": round(t * 1e3, 3),
-                       **_stats(st)}
-            log(f"[ext locality] {numbering} {name}: apply {ap['median_us_cold']:.1f} us, solve {t * 1e3:.2f} ms, "
+            # the same solve with one launch per color phase (same bits)
+            sv.factor.set_sync(hbmc.HBMC_SYNC_LAUNCH)
+            tl, (xl, stl) = _timed(lambda: sv.solve(b, tol=tol), reps=2)
+            if stl.iters != st.iters or not torch.equal(xl, x):
+                raise RuntimeError("one launch and a launch per phase gave different solves")
+            r[name] = {"apply_us_cold": ap["median_us_cold"], "apply_us_cold_launches": ap["median_us_cold_launches"],
+                       "apply_frac": ap["frac"], "solve_ms": round(t * 1e3, 3),
+                       "solve_ms_launches": round(tl * 1e3, 3), **_stats(st)}
+            log(f"[ext locality] {numbering} {name}: apply {ap['median_us_cold']:.1f} us, solve {t * 1e3:.2f} ms "
+                f"(a launch per phase: {ap['median_us_cold_launches']:.1f} us, {tl * 1e3:.2f} ms), "
                 f"{st.iters} its, true res {st.true_rel_res:.2e}")
         res[numbering] = r
         del m
