@@ -783,7 +783,7 @@ void plan_factor(const hbmc_dbuild_s &b, hbmc_factor_s *f) {
     f->n = o->n; f->bs = o->bs; f->w = o->w; f->nc = o->nc; f->precision = b.precision;
     f->n_pad = o->n_pad;
     f->nsys = 1;
-    f->xcd_tiles = o->local;
+    f->local = o->local;
     f->color_start = o->color_start;
     f->sys_ptr = {0, o->n};
     f->tile_base.assign(o->nc + 1, 0);

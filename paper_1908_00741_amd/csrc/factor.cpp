@@ -388,7 +388,7 @@ int make_factor(const hbmc_order_t *o, const int64_t *rowptr, const int32_t *col
         f->iperm = o->iperm;
         f->nsys = o->nsys;
         f->sys_ptr = o->sys_ptr;
-        f->xcd_tiles = o->local;
+        f->local = o->local;
         const Csr a = permute(*o, rowptr, col, val);
         const int64_t n = f->n_pad;
         const int bs = f->bs, w = f->w;

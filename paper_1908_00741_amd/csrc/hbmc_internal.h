@@ -269,7 +269,9 @@ struct hbmc_factor_s {
     int32_t kernel = HBMC_KERNEL_AUTO;
     int32_t sync = HBMC_SYNC_AUTO;
     uint64_t wait_ticks = 5000000;     // time limit of a wait in the one-launch form (100 MHz ticks: 50 ms)
-    bool xcd_tiles = false;            // the row kernel takes tiles in XCD-contiguous order
+    bool local = false;                // ordered after a locality renumbering (hbmc_order_rcm): the row
+                                       // kernel takes tiles in XCD-contiguous order, its one-launch form
+                                       // admits five workgroups per CU
     int32_t rhs_tile = 0;              // right-hand sides per wavefront, 0 = automatic
     int32_t nsys = 1;
     int64_t n_pad = 0;

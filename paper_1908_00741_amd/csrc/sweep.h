@@ -865,7 +865,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
     ph.dinv = dev_at<void>(f->dev, f->off_dinv);
     ph.done = done;
     ph.cg = cg;
-    ph.xcd = f->xcd_tiles;
+    ph.xcd = f->local;   // tiles in XCD-contiguous order after the renumbering
     ph.one_sys = f->nsys == 1;
     bool first_phase = CG && cg.stw != nullptr;   // the next launch computes alpha
     const size_t tw = sizeof(T) + sizeof(int32_t);
@@ -909,7 +909,7 @@ int launch_phases(const ::hbmc_factor_s *f, const double *r, double *z, hipStrea
             // bs 2, w 32, FP32 apply (FP64 takes four by its own LDS):
             // shuffled 239 us with eight per CU, 196 with four, 204 with
             // five, 220 with three; renumbered 158 / 148 / 142 / 166 us.
-            const int per_cu = f->xcd_tiles ? 5 : 4;
+            const int per_cu = f->local ? 5 : 4;
             const size_t lds_flow = std::max(lds, kLdsPerCu / size_t(per_cu + 1) + 1);
             hipLaunchKernelGGL((k_flow<BS, T, MI, CHR, CG>), dim3(unsigned(blocks)), dim3(BS * kLanes), lds_flow, s,
                                ph, ft, r, z);
